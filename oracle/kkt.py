@@ -1,0 +1,78 @@
+"""KKT residual of the velocity subproblem (Sec. 4.2 eq:KKTAO, derived in
+App. A), with the semi-Lagrangian step v_{i+1} = Q(S(v_i) + dt u_i).
+
+Unknowns on one level: v_i, pbar_i for i = 1..N and u_i, p_{i+1} for
+i = 0..N-1; v_0 = 0 is the fixed initial state.  Storage uses N slots per
+field:  v[j] = v_{j+1},  pbar[j] = pbar_{j+1},  u[j] = u_j,  p[j] = p_{j+1}.
+The residual f = (F1, F2, F3, F4) uses the same slots as (v, pbar, u, p):
+
+  F1_i = (K/r)[i<N](v_i - w_i) - [i<N] J_S(v_i)^T u_i / dt + u_{i-1} / dt + G pbar_i
+  F2_i = D v_i
+  F3_i = (v_{i+1} - S(v_i)) / dt - u_i + G p_{i+1},     S(v_0) = 0
+  F4_i = D u_i
+
+F1 is the gradient of the reduced objective r/2 sum|u_i|^2 + K/2 sum|v_i - w_i|^2
+(divided by r) with u_i = (v_{i+1} - S(v_i))/dt + G p_{i+1}:
+du_i/dv_i = -J_S(v_i)/dt and du_{i-1}/dv_i = I/dt.  This moves the
+advection derivative from the u_{i-1} coupling of eq:KKTAO (implicit
+operator) to the u_i coupling (explicit operator).  As in App. A, Q is
+dropped from these partials because u_i is solenoidal at the optimum.
+F1 and F3 are zero on wall faces.
+"""
+import numpy as np
+
+from .grid import Grid, div, grad
+from . import advect
+
+
+class Level:
+    """Grid plus the constants of eq:KKTAO on that level (h doubles per level).
+    advect=False replaces S by the identity (the linear-quadratic special
+    case used by the brute-force checks)."""
+
+    def __init__(self, g: Grid, N, dt, K_over_r, advect=True):
+        self.g, self.N, self.dt, self.kr = g, N, dt, K_over_r
+        self.mask = g.interior_mask()
+        self.advect = advect
+
+    def S(self, v):
+        return advect.self_advect(self.g, v, self.dt, self.g.h) if self.advect else v * self.mask
+
+    def JST(self, v, y):
+        return advect.self_advect_T(self.g, v, y, self.dt, self.g.h) if self.advect else y * self.mask
+
+
+def zeros_state(L: Level):
+    g, N = L.g, L.N
+    return [np.zeros((N, g.nface)), np.zeros((N, g.ncell)), np.zeros((N, g.nface)), np.zeros((N, g.ncell))]
+
+
+def residual_f(L: Level, x, w):
+    """f(x) for the state x = [v, pbar, u, p] and targets w (slot i = w_i).
+    The N time slices are independent given x, so they are evaluated as one
+    batch."""
+    g, N, dt, kr, h = L.g, L.N, L.dt, L.kr, L.g.h
+    v, pb, u, p = x
+    # F1_i, i = j + 1:  u_{i-1}/dt + G pbar_i  [+ (K/r)(v_i - w_i) - J_S(v_i)^T u_i / dt  if i < N]
+    F1 = u / dt + grad(g, pb, h)
+    if N > 1:
+        F1[:N - 1] += kr * (v[:N - 1] - w[1:N]) - L.JST(v[:N - 1], u[1:N]) / dt
+    F1 *= L.mask
+    F2 = div(g, v, h)
+    # F3_i, i = j:  (v_{i+1} - S(v_i))/dt - u_i + G p_{i+1},  S(v_0) = 0
+    S = np.zeros_like(v)
+    if N > 1:
+        S[1:] = L.S(v[:N - 1])
+    F3 = ((v - S) / dt - u + grad(g, p, h)) * L.mask
+    F4 = div(g, u, h)
+    return [F1, F2, F3, F4]
+
+
+def residual(L: Level, x, w, res):
+    """r = res - f(x)."""
+    f = residual_f(L, x, w)
+    return [res[k] - f[k] for k in range(4)]
+
+
+def inf_norm(parts):
+    return max(float(np.max(np.abs(a))) if a.size else 0.0 for a in parts)

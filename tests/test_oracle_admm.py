@@ -1,0 +1,72 @@
+"""ADMM-level checks of the oracle: exact special cases and a brute-force
+comparison with L-BFGS-B on the reduced objective J(u) of eq:opt (the
+gradient comes from the step adjoint, itself pinned by finite differences)."""
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+import synthetic
+from oracle import admm, metric, step
+from oracle.grid import Grid
+
+
+def _problem(w, **kw):
+    return admm.Problem(n=w["n"], num_steps=w["num_steps"], r=w["r"], dt=w["dt"], **kw)
+
+
+def test_keyframe_equal_to_initial_density_needs_no_control():
+    w = synthetic.small_problem((8, 8), 3, seed=1)
+    keys = {3: w["rho0"].copy()}
+    res = admm.solve(_problem(w, max_admm=3, fixed_counts=True, max_vcycles=2), w["rho0"], keys)
+    assert np.all(res.u == 0.0)
+    assert res.objective == 0.0 and res.reg_term == 0.0
+    assert np.array_equal(res.rho_sim[3], w["rho0"])
+
+
+def test_no_keyframes_gives_zero_control():
+    w = synthetic.small_problem((8, 8), 3, seed=2)
+    res = admm.solve(_problem(w, max_admm=2, fixed_counts=True, max_vcycles=2), w["rho0"], {})
+    assert np.all(res.u == 0.0) and res.objective == 0.0
+
+
+def _reduced(p, g, rho0, keys):
+    N, F = p.num_steps, g.nface
+
+    def JandG(uflat):
+        u = uflat.reshape(N, F)
+        rho = np.zeros((N + 1, g.ncell))
+        v = np.zeros((N + 1, F))
+        rho[0] = rho0
+        for i in range(N):
+            rho[i + 1], v[i + 1], _ = step.step_forward(g, rho[i], v[i], u[i], p.dt)
+        J = 0.5 * p.r * np.sum(u * u)
+        grho = np.zeros(g.ncell)
+        gv = np.zeros(F)
+        gu = np.zeros_like(u)
+        for i in range(N, 0, -1):
+            if i in keys:
+                e = rho[i] - keys[i]
+                Ce = metric.apply_metric(g, e, p.metric_levels)
+                J += 0.5 * e @ Ce
+                grho = grho + Ce
+            grho, gv, gu[i - 1] = step.step_backward(g, rho[i - 1], v[i - 1], grho, gv, p.dt)
+        return J, (gu + p.r * u).ravel()
+    return JandG
+
+
+@pytest.mark.slow
+def test_admm_close_to_brute_force_optimum():
+    w = synthetic.small_problem((8, 8), 4, seed=0, r=1e-2)
+    prob = _problem(w, max_admm=10, max_vcycles=40, eps_stfas=1e-10)
+    res = admm.solve(prob, w["rho0"], w["keys"])
+    p = prob.resolved(w["rho0"])
+    g = Grid(p.n)
+    JandG = _reduced(p, g, w["rho0"], w["keys"])
+    J0, g0 = JandG(np.zeros(p.num_steps * g.nface))
+    bf = minimize(JandG, np.zeros(p.num_steps * g.nface), jac=True, method="L-BFGS-B",
+                  options=dict(maxiter=2000, gtol=1e-10, ftol=1e-14))
+    Ja, ga = JandG(res.u.ravel())
+    assert abs(Ja - res.objective) < 1e-10 * Ja        # reported objective = J(u) re-simulated
+    assert Ja < 0.7 * J0
+    assert bf.fun <= Ja <= 1.02 * bf.fun
+    assert np.linalg.norm(ga) < 0.2 * np.linalg.norm(g0)
