@@ -1,0 +1,144 @@
+/*
+ * stfas.h - C interface of the MI355X spacetime-multigrid smoke-control solver.
+ *
+ * The solver computes the keyframe smoke-control problem of Pan & Manocha,
+ * "Efficient Optimal Control of Smoke using Spacetime Multigrid"
+ * (arXiv:1608.01102), Sec. 3.2 eq:opt:
+ *
+ *   minimise over u_0..u_{N-1}
+ *     1/2 sum_t <rho_t - rho*_t, C (rho_t - rho*_t)>  +  r/2 sum_i |u_i|^2
+ *   subject to the simulation step (Sec. 3.1 eq:NSA-eq:Conv, with
+ *   semi-Lagrangian advection as allowed in Sec. 4.1):
+ *     rho_{i+1} = A(rho_i, v_i),   v_{i+1} = Q(S(v_i) + dt u_i),   v_0 = 0,
+ *
+ * by the ADMM outer loop of Alg:outter: the density subproblem of Sec. 4.1
+ * (Alg:Passive) and the velocity subproblem of Sec. 4.2, whose KKT system
+ * (eq:KKTAO) is solved by the spacetime FAS V-cycle of Alg:STFAS with the
+ * spacetime SCGS smoother of Sec. 4.3 (eq:HESS).  C is the Gaussian keyframe
+ * metric of Sec. 4.1.
+ *
+ * Grid and layout (every pointer below uses it):
+ *   dim in {2,3}, n = (n0, n1, n2) with n2 = 1 in 2D, cell size h = 1/n0.
+ *   cells  [n2][n1][n0]                 (x fastest)
+ *   faces  x | y | z concatenated, shapes [n2][n1][n0+1], [n2][n1+1][n0],
+ *          [n2+1][n1][n0] (no z block in 2D); wall faces (index 0 or n_a
+ *          along the normal) are stored and are always zero.
+ *   a sequence of N fields is N consecutive fields (time major).
+ *
+ * Precision: STFAS_FP64 - every device buffer is double.  STFAS_MIXED -
+ * every device buffer is float; the coarsest Poisson level and all
+ * reductions (objective, line search, stop tests) run in double.
+ *
+ * Streams and ownership: all device pointers are caller-owned, contiguous
+ * and on the device of the stream passed at creation.  The library keeps no
+ * caller pointer after a call returns.  A context owns its workspace, which
+ * is allocated in stfas_create and freed in stfas_destroy.  One context per
+ * host thread; contexts on different streams may run concurrently.
+ *
+ * Errors: every call returns a status; nothing is thrown across the
+ * interface.  Invalid arguments are rejected before any device work.
+ */
+#ifndef STFAS_H
+#define STFAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stfas_ctx stfas_ctx;
+
+typedef enum {
+    STFAS_OK = 0,
+    STFAS_E_INVALID = 1,   /* bad argument; nothing was launched */
+    STFAS_E_NOMEM = 2,     /* device allocation failed */
+    STFAS_E_DEVICE = 3,    /* a HIP call failed */
+    STFAS_E_NONFINITE = 4  /* a reduction (objective, residual) was not finite */
+} stfas_status;
+
+typedef enum { STFAS_FP64 = 0, STFAS_MIXED = 1 } stfas_precision;
+
+/* Problem description (Sec. 3.2 eq:opt and the parameter table of Sec. 5).
+ * A field <= 0 selects the documented default. */
+typedef struct {
+    int32_t dim;            /* 2 or 3 */
+    int32_t n[3];           /* n0, n1, n2 (n2 = 1 in 2D); every n_a >= 4 */
+    int32_t num_steps;      /* N >= 1 */
+    double dt;              /* time step; default 1/n0 */
+    double r;               /* control regularisation weight, > 0 (required) */
+    double K;               /* ADMM penalty; default r / dt^2 */
+    double beta;            /* multiplier step factor; default 1 */
+    int32_t ao_iters;       /* fixed-point iterations of the density subproblem; default 2 */
+    double eps_stfas;       /* relative KKT residual target |f| <= eps |f(0)|; default 1e-5 */
+    double eps_admm;        /* stop when max_i |rho_i - rho_i^last|_inf < eps; default max(rho0)/100 */
+    int32_t max_admm;       /* ADMM iteration cap; default 50 */
+    int32_t max_vcycles;    /* V-cycles per velocity subproblem cap; default 30 */
+    int32_t metric_levels;  /* Gaussian filters in C; < 0 selects largest L with 2^(L-1) <= min(n)/8 */
+    double poisson_rtol;    /* projection relative residual; default 1e-13 (FP64) / 1e-6 (MIXED) */
+    int32_t fixed_counts;   /* 1: ignore eps_*, run exactly max_admm and max_vcycles (parity mode) */
+    int32_t precision;      /* stfas_precision */
+} stfas_problem;
+
+typedef struct {
+    int32_t admm_iters;     /* ADMM iterations run */
+    int32_t vcycles;        /* V-cycles run in total */
+    int32_t converged;      /* 1 if the ADMM stop test fired */
+    double objective;       /* J with the metric C, on the re-simulated trajectory */
+    double objective_l2;    /* same with C replaced by the identity */
+    double reg_term;        /* r/2 sum |u_i|^2 */
+    double kkt_res_inf;     /* |f|_inf of the last velocity subproblem */
+    double visual_diff;     /* last max_i |rho_i - rho_i^last|_inf */
+    double seconds;         /* wall time of the solve */
+} stfas_stats;
+
+/* Device bytes stfas_create allocates for this problem (exact); used for
+ * admission control.  Returns 0 for an invalid problem. */
+size_t stfas_workspace_bytes(const stfas_problem* prob);
+
+/* Validate the problem, allocate the workspace on the current device and bind
+ * the context to hip_stream (a hipStream_t; NULL = default stream). */
+stfas_status stfas_create(const stfas_problem* prob, void* hip_stream, stfas_ctx** out);
+
+/* Solve (Alg:outter).  rho0: initial density [cells].  key_steps: host array
+ * of num_key step indices in 1..N, strictly increasing.  key_rho: keyframe
+ * densities [num_key][cells].  u_out: the control sequence [N][faces].
+ * Stats go to the host struct.  Blocks until the outputs are complete.
+ * Non-convergence is not an error (stats->converged = 0). */
+stfas_status stfas_solve(stfas_ctx* ctx, const void* rho0, int32_t num_key, const int32_t* key_steps,
+                         const void* key_rho, void* u_out, stfas_stats* stats);
+
+/* One simulation step (Sec. 3.1 eq:NSA-eq:Conv with semi-Lagrangian advection):
+ *   rho_out = A(rho, v),  v_out = Q(S(v) + dt u),  p_out = phi/dt (may be NULL).
+ * work: caller scratch of stfas_step_work_bytes(prob) bytes.  Asynchronous
+ * on the stream; the projection runs a fixed number of multigrid cycles
+ * (stfas_step_vcycles) so that the call never synchronises. */
+stfas_status stfas_step_forward(const stfas_problem* prob, void* hip_stream, const void* rho, const void* v,
+                                const void* u, void* rho_out, void* v_out, void* p_out, void* work);
+
+/* Adjoint of stfas_step_forward: given the cotangents g_rho_out, g_v_out of
+ * (rho_out, v_out), writes g_rho = W(v)^T g_rho_out,
+ * g_v = J_S(v)^T Q g_v_out + (dA/dv)^T g_rho_out and g_u = dt Q g_v_out
+ * (Q is symmetric).  Asynchronous. */
+stfas_status stfas_step_backward(const stfas_problem* prob, void* hip_stream, const void* rho, const void* v,
+                                 const void* g_rho_out, const void* g_v_out, void* g_rho, void* g_v, void* g_u,
+                                 void* work);
+
+size_t stfas_step_work_bytes(const stfas_problem* prob);
+
+/* Number of projection V-cycles the step functions run (depends on the
+ * precision only; chosen so that the relative residual reaches
+ * poisson_rtol on smooth data). */
+int32_t stfas_step_vcycles(const stfas_problem* prob);
+
+void stfas_destroy(stfas_ctx* ctx);
+const char* stfas_status_string(stfas_status s);
+
+/* Library version and build information (static string). */
+const char* stfas_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STFAS_H */

@@ -1,0 +1,165 @@
+// Device-side grid description, index maps and the clamped multilinear
+// interpolation shared by every kernel of the solver.
+//
+// MAC grid (Sec. 3.1): cells [n2][n1][n0], faces x | y | z with shapes
+// [n2][n1][n0+1], [n2][n1+1][n0], [n2+1][n1][n0]; wall faces are stored and
+// held at zero.  2D problems use n2 = 1 and have no z block.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stfas {
+
+struct Grid {
+    int n[3];        // n0, n1, n2 (n2 = 1 in 2D)
+    int dim;
+    int ncell;
+    int fcount[3];   // faces per axis (0 for z in 2D)
+    int foff[3];     // offset of each axis block
+    int nface;
+    double h;        // cell size on this level
+};
+
+inline Grid make_grid(int dim, const int n[3], double h) {
+    Grid g{};
+    g.dim = dim;
+    g.n[0] = n[0];
+    g.n[1] = n[1];
+    g.n[2] = dim == 3 ? n[2] : 1;
+    g.ncell = g.n[0] * g.n[1] * g.n[2];
+    g.fcount[0] = g.n[2] * g.n[1] * (g.n[0] + 1);
+    g.fcount[1] = g.n[2] * (g.n[1] + 1) * g.n[0];
+    g.fcount[2] = dim == 3 ? (g.n[2] + 1) * g.n[1] * g.n[0] : 0;
+    g.foff[0] = 0;
+    g.foff[1] = g.fcount[0];
+    g.foff[2] = g.fcount[0] + g.fcount[1];
+    g.nface = g.fcount[0] + g.fcount[1] + g.fcount[2];
+    g.h = h;
+    return g;
+}
+
+inline Grid coarse_grid(const Grid& f) {
+    int n[3] = {f.n[0] / 2, f.n[1] / 2, f.dim == 3 ? f.n[2] / 2 : 1};
+    return make_grid(f.dim, n, 2.0 * f.h);
+}
+
+// Extent of the a-face lattice along axis b.
+__host__ __device__ inline int face_ext(const Grid& g, int a, int b) { return g.n[b] + (a == b ? 1 : 0); }
+
+__host__ __device__ inline int cell_index(const Grid& g, int i, int j, int k) {
+    return (k * g.n[1] + j) * g.n[0] + i;
+}
+
+// Flat index of a-face (i, j, k) (lattice coordinates of that axis).
+__host__ __device__ inline int face_index(const Grid& g, int a, int i, int j, int k) {
+    const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1);
+    return g.foff[a] + (k * ey + j) * ex + i;
+}
+
+// Decode a flat face index into (axis, i, j, k).
+__device__ inline void face_decode(const Grid& g, int f, int& a, int& i, int& j, int& k) {
+    a = (f >= g.foff[1]) + (g.dim == 3 && f >= g.foff[2]);
+    int r = f - g.foff[a];
+    const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1);
+    i = r % ex;
+    r /= ex;
+    j = r % ey;
+    k = r / ey;
+}
+
+__device__ inline bool face_interior(const Grid& g, int a, int i, int j, int k) {
+    const int c = a == 0 ? i : (a == 1 ? j : k);
+    return c >= 1 && c <= g.n[a] - 1;
+}
+
+// One axis of the clamped multilinear interpolation on a lattice with M
+// nodes:  yc = clamp(y, 0, M-1),  i0 = min(floor(yc), M-2),  t = yc - i0;
+// the derivative of the interpolant along this axis is multiplied by 1 on
+// the closed box [0, M-1] and 0 outside.
+template <typename T>
+struct Axis {
+    int i0;
+    T t;
+    T in;
+};
+
+template <typename T>
+__device__ inline Axis<T> locate(T y, int M) {
+    Axis<T> s;
+    const T top = (T)(M - 1);
+    // fmax/fmin return the non-NaN operand, so a NaN foot point is clamped
+    // to node 0 and every corner index stays inside the lattice.
+    const T yc = fmin(fmax(y, (T)0), top);
+    int i = (int)floor(yc);
+    if (i < 0) i = 0;
+    if (i > M - 2) i = M - 2;
+    s.i0 = i;
+    s.t = yc - (T)i;
+    s.in = (y >= (T)0 && y <= top) ? (T)1 : (T)0;
+    return s;
+}
+
+// Lattice with extents ex, ey (ez implied) and x-fastest strides.
+template <typename T, int D>
+struct Interp {
+    Axis<T> ax[3];
+    int base;   // flat index of corner (i0, j0, k0)
+    int sy, sz; // strides
+
+    __device__ inline void setup(const T* y, int ex, int ey, int ez) {
+        ax[0] = locate<T>(y[0], ex);
+        ax[1] = locate<T>(y[1], ey);
+        if (D == 3) ax[2] = locate<T>(y[2], ez);
+        sy = ex;
+        sz = ex * ey;
+        base = ax[0].i0 + ax[1].i0 * sy + (D == 3 ? ax[2].i0 * sz : 0);
+    }
+
+    __device__ inline int corner(int c) const {
+        return base + (c & 1) + ((c >> 1) & 1) * sy + (D == 3 ? ((c >> 2) & 1) * sz : 0);
+    }
+
+    __device__ inline T weight(int c) const {
+        T w = (c & 1) ? ax[0].t : (T)1 - ax[0].t;
+        w *= ((c >> 1) & 1) ? ax[1].t : (T)1 - ax[1].t;
+        if (D == 3) w *= ((c >> 2) & 1) ? ax[2].t : (T)1 - ax[2].t;
+        return w;
+    }
+
+    // d weight(c) / d y_a (times the clamp derivative).
+    __device__ inline T dweight(int c, int a) const {
+        T w = ax[a].in * (((c >> a) & 1) ? (T)1 : (T)-1);
+        for (int b = 0; b < D; ++b) {
+            if (b == a) continue;
+            w *= ((c >> b) & 1) ? ax[b].t : (T)1 - ax[b].t;
+        }
+        return w;
+    }
+
+    __device__ inline T value(const T* q) const {
+        T s = 0;
+#pragma unroll
+        for (int c = 0; c < (1 << D); ++c) s += weight(c) * q[corner(c)];
+        return s;
+    }
+
+    __device__ inline void grad(const T* q, T* g) const {
+#pragma unroll
+        for (int a = 0; a < D; ++a) g[a] = 0;
+#pragma unroll
+        for (int c = 0; c < (1 << D); ++c) {
+            const T qc = q[corner(c)];
+#pragma unroll
+            for (int a = 0; a < D; ++a) g[a] += dweight(c, a) * qc;
+        }
+    }
+};
+
+template <typename T>
+__device__ inline void atomic_add(T* p, T v) {
+    atomicAdd(p, v);
+}
+
+inline int blocks_for(long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+}  // namespace stfas

@@ -1,0 +1,335 @@
+// Velocity-subproblem kernels: KKT residual (Sec. 4.2 eq:KKTAO with the
+// semi-Lagrangian step), spacetime SCGS smoother (Sec. 4.3, eq:HESS) and the
+// FAS transfers (Sec. 4.3).
+//
+// State of one level (N slots per field): v[j] = v_{j+1}, pbar[j] =
+// pbar_{j+1}, u[j] = u_j, p[j] = p_{j+1}; v_0 = 0 is fixed.  Residual rows
+// use the same slots: F1 ~ v, F2 ~ pbar, F3 ~ u, F4 ~ p.
+//   F1_i = (K/r)[i<N](v_i - w_i) - [i<N] J_S(v_i)^T u_i/dt + u_{i-1}/dt + G pbar_i
+//   F2_i = D v_i
+//   F3_i = (v_{i+1} - S(v_i))/dt - u_i + G p_{i+1}      (S(v_0) = 0)
+//   F4_i = D u_i
+// Kernels compute out = res + sgn f (sgn = -1: residual res - f; sgn = +1:
+// the FAS right-hand side f(R x) + R r).
+#pragma once
+#include "common.hpp"
+#include "k_advect.hpp"
+
+namespace stfas {
+
+// Face rows F1, F3 without the J_S^T term of F1 (added by k_self_advect_T).
+template <typename T, int D>
+__global__ void k_kkt_faces(Grid g, int N, T dt, T kr, T cfl, T sgn, const T* __restrict__ v,
+                            const T* __restrict__ pb, const T* __restrict__ u, const T* __restrict__ p,
+                            const T* __restrict__ w, const T* res1, const T* res3, T* out1, T* out3) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= g.nface) return;
+    const int j = blockIdx.y;
+    const long F = g.nface, C = g.ncell;
+    int a, i, jj, k;
+    face_decode(g, f, a, i, jj, k);
+    const long e = j * F + f;
+    if (!face_interior(g, a, i, jj, k)) {
+        out1[e] = (T)0;
+        out3[e] = (T)0;
+        return;
+    }
+    const int c = cell_index(g, i, jj, k);
+    const int cm = cell_index(g, i - (a == 0), jj - (a == 1), k - (a == 2));
+    const T ih = (T)(1.0 / g.h);
+    // F1_{j+1}
+    T f1 = u[e] / dt + (pb[j * C + c] - pb[j * C + cm]) * ih;
+    if (j < N - 1) f1 += kr * (v[e] - w[(j + 1) * F + f]);
+    // F3_j
+    T s = 0;
+    if (j >= 1) {
+        const T* vp = v + (j - 1) * F;
+        T vh[3];
+        face_velocity<T, D>(g, vp, a, i, jj, k, vh);
+        const int idx[3] = {i, jj, k};
+        T y[3];
+        for (int b = 0; b < D; ++b) y[b] = (T)idx[b] - cfl * vh[b];
+        Interp<T, D> it;
+        it.setup(y, face_ext(g, a, 0), face_ext(g, a, 1), face_ext(g, a, 2));
+        s = it.value(vp + g.foff[a]);
+    }
+    const T f3 = (v[e] - s) / dt - u[e] + (p[j * C + c] - p[j * C + cm]) * ih;
+    out1[e] = (res1 ? res1[e] : (T)0) + sgn * f1;
+    out3[e] = (res3 ? res3[e] : (T)0) + sgn * f3;
+}
+
+// Cell rows F2 = D v_i, F4 = D u_i.
+template <typename T, int D>
+__global__ void k_kkt_cells(Grid g, T sgn, const T* __restrict__ v, const T* __restrict__ u, const T* res2,
+                            const T* res4, T* out2, T* out4) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell) return;
+    const int j = blockIdx.y;
+    const long F = g.nface;
+    const int i = c % g.n[0], jj = (c / g.n[0]) % g.n[1], k = c / (g.n[0] * g.n[1]);
+    const T* vj = v + j * F;
+    const T* uj = u + j * F;
+    T dv = 0, du = 0;
+    for (int a = 0; a < D; ++a) {
+        const int hi = face_index(g, a, i + (a == 0), jj + (a == 1), k + (a == 2));
+        const int lo = face_index(g, a, i, jj, k);
+        dv += vj[hi] - vj[lo];
+        du += uj[hi] - uj[lo];
+    }
+    const T ih = (T)(1.0 / g.h);
+    const long e = (long)j * g.ncell + c;
+    out2[e] = (res2 ? res2[e] : (T)0) + sgn * dv * ih;
+    out4[e] = (res4 ? res4[e] : (T)0) + sgn * du * ih;
+}
+
+// ---------------------------------------------------------------- SCGS
+// Cells of one colour (parity bits of the coordinates) and their faces.
+struct ColourSet {
+    int p[3];
+    int cnt[3];
+    int total;
+};
+
+inline ColourSet colour_set(const Grid& g, int colour) {
+    ColourSet s{};
+    for (int a = 0; a < 3; ++a) {
+        s.p[a] = (a < g.dim) ? ((colour >> a) & 1) : 0;
+        s.cnt[a] = (a < g.dim) ? (g.n[a] - s.p[a] + 1) / 2 : 1;
+    }
+    s.total = s.cnt[0] * s.cnt[1] * s.cnt[2];
+    return s;
+}
+
+// Local geometry of one cell: face indices, interior flags, 1/|g|, ghat.
+template <int D>
+struct CellFaces {
+    int face[2 * D];
+    bool inner[2 * D];
+    int m;
+};
+
+template <int D>
+__device__ inline void cell_faces(const Grid& g, int i, int j, int k, CellFaces<D>& cf) {
+    const int idx[3] = {i, j, k};
+    cf.m = 0;
+    for (int a = 0; a < D; ++a) {
+        cf.face[2 * a] = face_index(g, a, i, j, k);
+        cf.face[2 * a + 1] = face_index(g, a, i + (a == 0), j + (a == 1), k + (a == 2));
+        cf.inner[2 * a] = idx[a] >= 1;
+        cf.inner[2 * a + 1] = idx[a] + 1 <= g.n[a] - 1;
+        cf.m += cf.inner[2 * a] + cf.inner[2 * a + 1];
+    }
+}
+
+__device__ inline void colour_cell(const ColourSet& cs, int q, int& i, int& j, int& k) {
+    const int ci = q % cs.cnt[0];
+    const int cj = (q / cs.cnt[0]) % cs.cnt[1];
+    const int ck = q / (cs.cnt[0] * cs.cnt[1]);
+    i = 2 * ci + cs.p[0];
+    j = 2 * cj + cs.p[1];
+    k = 2 * ck + cs.p[2];
+}
+
+// Face part of the local spacetime solve.  With ghat = g/|g| (g the
+// divergence coefficients -1/h, +1/h of the cell's interior faces) and
+// P = I - ghat ghat^T, the local system [T (x) I, -g; g^T, 0] (blocks in time
+// order (u_0,p_1), (v_1,pbar_1), ..., (v_N,pbar_N)) splits into
+//   P x_k = (T^-1 P r)_k          (one scalar tridiagonal solve per face)
+//   ghat^T x_k = xi_k = s_k/|g|   (s = divergence-row residual)
+// so dx_k = (T^-1 P r)_k + ghat xi_k.  T is shared by all cells: the host
+// passes its Thomas factors (sub-diagonal, c', 1/pivot).
+template <typename T, int D>
+__global__ void k_scgs_faces(Grid g, int N, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ r2,
+                             const T* __restrict__ r3, const T* __restrict__ r4, T* v, T* u,
+                             const T* __restrict__ tsub, const T* __restrict__ tcp, const T* __restrict__ tinv,
+                             T* __restrict__ scratch) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nthreads = cs.total * 2 * D;
+    if (tid >= nthreads) return;
+    const int q = tid / (2 * D), s = tid % (2 * D);
+    int i, j, k;
+    colour_cell(cs, q, i, j, k);
+    CellFaces<D> cf;
+    cell_faces<D>(g, i, j, k, cf);
+    if (!cf.inner[s]) return;
+    const T ginv = (T)1 / sqrt((T)cf.m);        // |ghat_s| = 1/sqrt(m)
+    T gh[2 * D];
+    for (int t = 0; t < 2 * D; ++t) gh[t] = cf.inner[t] ? ((t & 1) ? ginv : -ginv) : (T)0;
+    const long F = g.nface, C = g.ncell;
+    const int c = cell_index(g, i, j, k);
+    const int own = cf.face[s];
+    T dprev = 0;
+    for (int kk = 0; kk < 2 * N; ++kk) {
+        const long jo = (long)(kk >> 1) * F;
+        const T* r = (kk & 1) ? r1 + jo : r3 + jo;
+        T gr = 0;
+        for (int t = 0; t < 2 * D; ++t)
+            if (cf.inner[t]) gr += gh[t] * r[cf.face[t]];
+        const T pr = r[own] - gh[s] * gr;
+        const T d = (pr - tsub[kk] * dprev) * tinv[kk];
+        scratch[(long)kk * nthreads + tid] = d;
+        dprev = d;
+    }
+    const T gn_inv = (T)g.h * ginv;             // 1/|g| = h/sqrt(m)
+    T x = 0;
+    for (int kk = 2 * N - 1; kk >= 0; --kk) {
+        x = scratch[(long)kk * nthreads + tid] - tcp[kk] * x;
+        const long jj = kk >> 1;
+        const T sk = (kk & 1) ? r2[jj * C + c] : r4[jj * C + c];
+        const T dx = x + gh[s] * sk * gn_inv;
+        T* fld = (kk & 1) ? v : u;
+        fld[jj * F + own] += dx;
+    }
+}
+
+// Pressure part: dpi_k = (sum_l T_kl xi_l - ghat^T r_k) / |g|, one thread per
+// (cell, block).
+template <typename T, int D>
+__global__ void k_scgs_cells(Grid g, int N, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ r2,
+                             const T* __restrict__ r3, const T* __restrict__ r4, T* pb, T* p,
+                             const T* __restrict__ tdiag, const T* __restrict__ tsub, const T* __restrict__ tsup) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= cs.total * 2 * N) return;
+    const int q = tid % cs.total, kk = tid / cs.total;
+    int i, j, k;
+    colour_cell(cs, q, i, j, k);
+    CellFaces<D> cf;
+    cell_faces<D>(g, i, j, k, cf);
+    const T ginv = (T)1 / sqrt((T)cf.m);
+    const T gn_inv = (T)g.h * ginv;
+    const long F = g.nface, C = g.ncell;
+    const int c = cell_index(g, i, j, k);
+    auto srow = [&](int b) -> T {
+        const long jj = b >> 1;
+        return ((b & 1) ? r2[jj * C + c] : r4[jj * C + c]) * gn_inv;
+    };
+    T acc = tdiag[kk] * srow(kk);
+    if (kk > 0) acc += tsub[kk] * srow(kk - 1);
+    if (kk < 2 * N - 1) acc += tsup[kk] * srow(kk + 1);
+    const long jo = (long)(kk >> 1) * F;
+    const T* r = (kk & 1) ? r1 + jo : r3 + jo;
+    T gr = 0;
+    for (int t = 0; t < 2 * D; ++t)
+        if (cf.inner[t]) gr += ((t & 1) ? ginv : -ginv) * r[cf.face[t]];
+    T* fld = (kk & 1) ? pb : p;
+    fld[(long)(kk >> 1) * C + c] += (acc - gr) * gn_inv;
+}
+
+// ---------------------------------------------------------------- transfers
+// Interpolation weight of coarse node I for a fine sample at coarse
+// position y on an axis with M coarse nodes.
+template <typename T>
+__device__ inline T axis_weight(T y, int M, int I) {
+    const Axis<T> s = locate<T>(y, M);
+    if (I == s.i0) return (T)1 - s.t;
+    if (I == s.i0 + 1) return s.t;
+    return (T)0;
+}
+
+// Coarse position of fine index j: cell-type axis (j + 1/2)/2 - 1/2, node-type j/2.
+template <typename T>
+__device__ inline T fine_pos(int j, bool node) {
+    return node ? (T)j * (T)0.5 : ((T)j + (T)0.5) * (T)0.5 - (T)0.5;
+}
+
+// coarse = 2^-d P^T fine on the cell lattice (gather form), batched over slots.
+template <typename T, int D>
+__global__ void k_restrict_cells(Grid gf, Grid gc, const T* __restrict__ fine, T* __restrict__ coarse) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= gc.ncell) return;
+    fine += (long)blockIdx.y * gf.ncell;
+    coarse += (long)blockIdx.y * gc.ncell;
+    const int I[3] = {c % gc.n[0], (c / gc.n[0]) % gc.n[1], c / (gc.n[0] * gc.n[1])};
+    T s = 0;
+    const int lo2 = D == 3 ? 2 * I[2] - 1 : 0, hi2 = D == 3 ? 2 * I[2] + 2 : 0;
+    for (int k = lo2; k <= hi2; ++k) {
+        if (k < 0 || k >= gf.n[2]) continue;
+        const T wk = D == 3 ? axis_weight<T>(fine_pos<T>(k, false), gc.n[2], I[2]) : (T)1;
+        if (wk == (T)0) continue;
+        for (int j = 2 * I[1] - 1; j <= 2 * I[1] + 2; ++j) {
+            if (j < 0 || j >= gf.n[1]) continue;
+            const T wj = axis_weight<T>(fine_pos<T>(j, false), gc.n[1], I[1]);
+            if (wj == (T)0) continue;
+            for (int i = 2 * I[0] - 1; i <= 2 * I[0] + 2; ++i) {
+                if (i < 0 || i >= gf.n[0]) continue;
+                const T wi = axis_weight<T>(fine_pos<T>(i, false), gc.n[0], I[0]);
+                s += wi * wj * wk * fine[cell_index(gf, i, j, k)];
+            }
+        }
+    }
+    coarse[c] = s * (T)(D == 3 ? 0.125 : 0.25);
+}
+
+// Face lattices; coarse wall faces are set to zero.
+template <typename T, int D>
+__global__ void k_restrict_faces(Grid gf, Grid gc, const T* __restrict__ fine, T* __restrict__ coarse) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= gc.nface) return;
+    fine += (long)blockIdx.y * gf.nface;
+    coarse += (long)blockIdx.y * gc.nface;
+    int a, I0, I1, I2;
+    face_decode(gc, f, a, I0, I1, I2);
+    if (!face_interior(gc, a, I0, I1, I2)) {
+        coarse[f] = (T)0;
+        return;
+    }
+    const int I[3] = {I0, I1, I2};
+    int lo[3], hi[3];
+    for (int b = 0; b < 3; ++b) {
+        if (b >= D) { lo[b] = hi[b] = 0; continue; }
+        if (b == a) { lo[b] = 2 * I[b] - 1; hi[b] = 2 * I[b] + 1; }
+        else { lo[b] = 2 * I[b] - 1; hi[b] = 2 * I[b] + 2; }
+    }
+    T s = 0;
+    for (int k = lo[2]; k <= hi[2]; ++k) {
+        if (D == 3 && (k < 0 || k >= face_ext(gf, a, 2))) continue;
+        const T wk = D == 3 ? axis_weight<T>(fine_pos<T>(k, a == 2), face_ext(gc, a, 2), I[2]) : (T)1;
+        if (wk == (T)0) continue;
+        for (int j = lo[1]; j <= hi[1]; ++j) {
+            if (j < 0 || j >= face_ext(gf, a, 1)) continue;
+            const T wj = axis_weight<T>(fine_pos<T>(j, a == 1), face_ext(gc, a, 1), I[1]);
+            if (wj == (T)0) continue;
+            for (int i = lo[0]; i <= hi[0]; ++i) {
+                if (i < 0 || i >= face_ext(gf, a, 0)) continue;
+                const T wi = axis_weight<T>(fine_pos<T>(i, a == 0), face_ext(gc, a, 0), I[0]);
+                s += wi * wj * wk * fine[face_index(gf, a, i, j, k)];
+            }
+        }
+    }
+    coarse[f] = s * (T)(D == 3 ? 0.125 : 0.25);
+}
+
+// fine += sign * P coarse on the cell lattice.
+template <typename T, int D>
+__global__ void k_prolong_cells(Grid gf, Grid gc, const T* __restrict__ coarse, T sign, T* __restrict__ fine) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= gf.ncell) return;
+    fine += (long)blockIdx.y * gf.ncell;
+    coarse += (long)blockIdx.y * gc.ncell;
+    const int idx[3] = {c % gf.n[0], (c / gf.n[0]) % gf.n[1], c / (gf.n[0] * gf.n[1])};
+    T y[3];
+    for (int b = 0; b < D; ++b) y[b] = fine_pos<T>(idx[b], false);
+    Interp<T, D> it;
+    it.setup(y, gc.n[0], gc.n[1], gc.n[2]);
+    fine[c] += sign * it.value(coarse);
+}
+
+// fine += sign * P coarse on the face lattices (fine walls untouched).
+template <typename T, int D>
+__global__ void k_prolong_faces(Grid gf, Grid gc, const T* __restrict__ coarse, T sign, T* __restrict__ fine) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= gf.nface) return;
+    fine += (long)blockIdx.y * gf.nface;
+    coarse += (long)blockIdx.y * gc.nface;
+    int a, i, j, k;
+    face_decode(gf, f, a, i, j, k);
+    if (!face_interior(gf, a, i, j, k)) return;
+    const int idx[3] = {i, j, k};
+    T y[3];
+    for (int b = 0; b < D; ++b) y[b] = fine_pos<T>(idx[b], b == a);
+    Interp<T, D> it;
+    it.setup(y, face_ext(gc, a, 0), face_ext(gc, a, 1), face_ext(gc, a, 2));
+    fine[f] += sign * it.value(coarse + gc.foff[a]);
+}
+
+}  // namespace stfas

@@ -1,0 +1,934 @@
+// Host driver of the solver: workspace layout, the multigrid projection,
+// the FAS V-cycle and velocity subproblem, the density subproblem, the ADMM
+// outer loop and the re-simulated outputs.  Every device step is a kernel of
+// this library launched on the context's stream; the host only sequences
+// them and reads back the scalars the stop tests need.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/stfas.h"
+#include "../../include/stfas_ops.h"
+#include "common.hpp"
+#include "k_advect.hpp"
+#include "k_kkt.hpp"
+#include "k_misc.hpp"
+#include "k_poisson.hpp"
+
+namespace stfas {
+
+constexpr int BS = 256;
+constexpr int RED_BLOCKS = 512;
+constexpr int MAX_COARSE_CELLS = 4096;
+constexpr int MAX_PROJECT_CYCLES = 60;
+
+struct HipError {
+    hipError_t e;
+};
+#define HCK(x)                                   \
+    do {                                         \
+        hipError_t _e = (x);                     \
+        if (_e != hipSuccess) throw HipError{_e}; \
+    } while (0)
+#define LAUNCH_CHECK() HCK(hipPeekAtLastError())
+
+// Bump allocator with a planning pass: plan() sizes every buffer, carve()
+// hands out the same offsets inside one allocation.
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename U>
+    U* take(size_t count) {
+        const size_t bytes = ((count * sizeof(U)) + 255) & ~size_t(255);
+        U* p = base ? reinterpret_cast<U*>(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+// Resolved problem constants (defaults of stfas.h applied).
+struct Params {
+    int dim, n[3], N;
+    double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol;
+    int ao_iters, max_admm, max_vcycles, metric_levels, fixed_counts, precision;
+};
+
+inline int default_metric_levels(const int* n, int dim) {
+    int m = n[0];
+    for (int a = 1; a < dim; ++a) m = std::min(m, n[a]);
+    int L = 0;
+    while (std::ldexp(1.0, L) <= m / 8.0) ++L;
+    return L;
+}
+
+inline bool resolve(const stfas_problem* p, Params& o) {
+    if (!p) return false;
+    if (p->dim != 2 && p->dim != 3) return false;
+    o.dim = p->dim;
+    for (int a = 0; a < 3; ++a) o.n[a] = a < p->dim ? p->n[a] : 1;
+    for (int a = 0; a < o.dim; ++a)
+        if (o.n[a] < 4 || o.n[a] > (1 << 14)) return false;
+    if (o.dim == 2 && p->n[2] > 1) return false;
+    if (p->num_steps < 1 || p->num_steps > 100000) return false;
+    if (!(p->r > 0) || !std::isfinite(p->r)) return false;
+    if (p->precision != STFAS_FP64 && p->precision != STFAS_MIXED) return false;
+    o.N = p->num_steps;
+    o.dt = p->dt > 0 ? p->dt : 1.0 / o.n[0];
+    o.r = p->r;
+    o.K = p->K > 0 ? p->K : o.r / (o.dt * o.dt);
+    o.beta = p->beta > 0 ? p->beta : 1.0;
+    o.ao_iters = p->ao_iters > 0 ? p->ao_iters : 2;
+    o.eps_stfas = p->eps_stfas > 0 ? p->eps_stfas : 1e-5;
+    o.eps_admm = p->eps_admm;   // <= 0: max(rho0)/100, fixed at solve time
+    o.max_admm = p->max_admm > 0 ? p->max_admm : 50;
+    o.max_vcycles = p->max_vcycles > 0 ? p->max_vcycles : 30;
+    o.metric_levels = p->metric_levels >= 0 ? p->metric_levels : default_metric_levels(o.n, o.dim);
+    o.precision = p->precision;
+    o.poisson_rtol = p->poisson_rtol > 0 ? p->poisson_rtol : (o.precision == STFAS_FP64 ? 1e-13 : 1e-6);
+    o.fixed_counts = p->fixed_counts ? 1 : 0;
+    const double total = (double)o.n[0] * o.n[1] * o.n[2];
+    if (total > 2.0e9 / (o.dim + 1)) return false;
+    return true;
+}
+
+// STFAS levels: coarsen every axis by 2 while every n_a / 2^l >= 4.
+inline std::vector<Grid> stfas_levels(const Grid& g0) {
+    std::vector<Grid> v{g0};
+    for (;;) {
+        const Grid& g = v.back();
+        bool ok = true;
+        for (int a = 0; a < g.dim; ++a) ok = ok && (g.n[a] % 2 == 0) && (g.n[a] / 2 >= 4);
+        if (!ok) break;
+        v.push_back(coarse_grid(g));
+    }
+    return v;
+}
+
+// Poisson levels: coarsen while every n_a is even and n_a / 2 >= 2.
+inline std::vector<Grid> poisson_levels(const Grid& g0) {
+    std::vector<Grid> v{g0};
+    for (;;) {
+        const Grid& g = v.back();
+        bool ok = true;
+        for (int a = 0; a < g.dim; ++a) ok = ok && (g.n[a] % 2 == 0) && (g.n[a] / 2 >= 2);
+        if (!ok) break;
+        v.push_back(coarse_grid(g));
+    }
+    return v;
+}
+
+// Pseudo-inverse of the Neumann Laplacian of a small grid, row-major m x m:
+// pinv = (L - 11^T/m)^-1 + 11^T/m (the constant is L's only null vector).
+inline void coarse_pinv(const Grid& g, std::vector<double>& out) {
+    const int m = g.ncell;
+    std::vector<double> A((size_t)m * m, 0.0), I((size_t)m * m, 0.0);
+    const double ih2 = 1.0 / (g.h * g.h);
+    for (int k = 0; k < g.n[2]; ++k)
+        for (int j = 0; j < g.n[1]; ++j)
+            for (int i = 0; i < g.n[0]; ++i) {
+                const int c = cell_index(g, i, j, k);
+                const int nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+                for (int q = 0; q < 6; ++q) {
+                    const int a = nb[q][0], b = nb[q][1], cc = nb[q][2];
+                    if (a < 0 || a >= g.n[0] || b < 0 || b >= g.n[1] || cc < 0 || cc >= g.n[2]) continue;
+                    A[(size_t)c * m + cell_index(g, a, b, cc)] += ih2;
+                    A[(size_t)c * m + c] -= ih2;
+                }
+            }
+    for (size_t e = 0; e < A.size(); ++e) A[e] -= 1.0 / m;
+    for (int d = 0; d < m; ++d) I[(size_t)d * m + d] = 1.0;
+    // Gauss-Jordan with partial pivoting
+    for (int col = 0; col < m; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < m; ++r)
+            if (std::fabs(A[(size_t)r * m + col]) > std::fabs(A[(size_t)piv * m + col])) piv = r;
+        if (piv != col)
+            for (int q = 0; q < m; ++q) {
+                std::swap(A[(size_t)piv * m + q], A[(size_t)col * m + q]);
+                std::swap(I[(size_t)piv * m + q], I[(size_t)col * m + q]);
+            }
+        const double inv = 1.0 / A[(size_t)col * m + col];
+        for (int q = 0; q < m; ++q) {
+            A[(size_t)col * m + q] *= inv;
+            I[(size_t)col * m + q] *= inv;
+        }
+        for (int r = 0; r < m; ++r) {
+            if (r == col) continue;
+            const double f = A[(size_t)r * m + col];
+            if (f == 0.0) continue;
+            for (int q = 0; q < m; ++q) {
+                A[(size_t)r * m + q] -= f * A[(size_t)col * m + q];
+                I[(size_t)r * m + q] -= f * I[(size_t)col * m + q];
+            }
+        }
+    }
+    out.assign((size_t)m * m, 0.0);
+    for (size_t e = 0; e < out.size(); ++e) out[e] = I[e] + 1.0 / m;
+}
+
+// Normalised Gaussian taps exp(-t^2 / (2 sigma^2)), t = -R..R, R = ceil(3 sigma).
+inline std::vector<double> gauss_taps(double sigma) {
+    const int R = (int)std::ceil(3.0 * sigma);
+    std::vector<double> k(2 * R + 1);
+    double s = 0;
+    for (int t = -R; t <= R; ++t) s += (k[t + R] = std::exp(-(double)t * t / (2.0 * sigma * sigma)));
+    for (auto& x : k) x /= s;
+    return k;
+}
+
+// Thomas factors of the temporal matrix of the SCGS local system (blocks
+// u_0, v_1, u_1, ..., v_N): diagonal -1 (u), K/r (v_i, i<N), 0 (v_N);
+// T(u_{i-1}, v_i) = 1/dt, T(v_i, u_i) = -1/dt.
+struct TFactors {
+    std::vector<double> diag, sub, sup, cp, inv;
+};
+
+inline TFactors temporal_factors(int N, double dt, double kr) {
+    TFactors f;
+    const int M = 2 * N;
+    f.diag.resize(M);
+    f.sub.assign(M, 0.0);
+    f.sup.assign(M, 0.0);
+    f.cp.assign(M, 0.0);
+    f.inv.resize(M);
+    for (int k = 0; k < M; ++k) {
+        f.diag[k] = (k % 2 == 0) ? -1.0 : (((k + 1) / 2 < N) ? kr : 0.0);
+        if (k + 1 < M) f.sup[k] = (k % 2 == 0) ? 1.0 / dt : -1.0 / dt;
+        if (k > 0) f.sub[k] = f.sup[k - 1];
+    }
+    double cprev = 0;
+    for (int k = 0; k < M; ++k) {
+        const double den = f.diag[k] - f.sub[k] * cprev;
+        f.inv[k] = 1.0 / den;
+        f.cp[k] = f.sup[k] * f.inv[k];
+        cprev = f.cp[k];
+    }
+    return f;
+}
+
+// Multigrid projection Q for B independent slices (Sec. 4.1).
+template <typename T, int D>
+struct Poisson {
+    std::vector<Grid> PG;
+    std::vector<T*> phi, b;
+    double* pinv = nullptr;
+    double* pool = nullptr;   // per-slice residual partials
+    double* out = nullptr;    // 8 doubles of reduction results
+    int Bmax = 1;
+    hipStream_t st = nullptr;
+
+    void init(const Grid& g0, int bmax, hipStream_t s) {
+        PG = poisson_levels(g0);
+        Bmax = bmax;
+        st = s;
+    }
+    bool coarse_ok() const { return PG.back().ncell <= MAX_COARSE_CELLS; }
+    void layout(Arena& A, double* shared_pinv) {
+        phi.assign(PG.size(), nullptr);
+        b.assign(PG.size(), nullptr);
+        for (size_t l = 0; l < PG.size(); ++l) {
+            phi[l] = A.take<T>((size_t)Bmax * PG[l].ncell);
+            b[l] = A.take<T>((size_t)Bmax * PG[l].ncell);
+        }
+        pinv = shared_pinv ? shared_pinv : A.take<double>((size_t)PG.back().ncell * PG.back().ncell);
+        pool = A.take<double>((size_t)Bmax * RED_BLOCKS * 2);
+        out = A.take<double>(8);
+    }
+    void upload_pinv() {
+        std::vector<double> pv;
+        coarse_pinv(PG.back(), pv);
+        HCK(hipMemcpyAsync(pinv, pv.data(), pv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HCK(hipStreamSynchronize(st));
+    }
+
+    void vcycle(int l, int B) {
+        const Grid& g = PG[l];
+        const long C = g.ncell;
+        if (l == (int)PG.size() - 1) {
+            k_coarse_solve<T><<<B, BS, C * sizeof(double), st>>>((int)C, pinv, b[l], phi[l], C);
+            return;
+        }
+        const int half = (g.n[0] + 1) / 2 * g.n[1] * g.n[2];
+        const dim3 gr(blocks_for(half, BS), B);
+        for (int s = 0; s < 2; ++s) {
+            k_rbgs<T, D><<<gr, BS, 0, st>>>(g, phi[l], b[l], 0, C);
+            k_rbgs<T, D><<<gr, BS, 0, st>>>(g, phi[l], b[l], 1, C);
+        }
+        const Grid& gc = PG[l + 1];
+        k_resid_restrict<T, D><<<dim3(blocks_for(gc.ncell, BS), B), BS, 0, st>>>(g, gc, phi[l], b[l], b[l + 1], C,
+                                                                                gc.ncell);
+        k_fill<T><<<blocks_for((long)B * gc.ncell, BS), BS, 0, st>>>((long)B * gc.ncell, phi[l + 1], (T)0);
+        vcycle(l + 1, B);
+        k_prolong_add<T, D><<<dim3(blocks_for(C, BS), B), BS, 0, st>>>(g, gc, phi[l + 1], phi[l], C, gc.ncell);
+        for (int s = 0; s < 2; ++s) {
+            k_rbgs<T, D><<<gr, BS, 0, st>>>(g, phi[l], b[l], 1, C);
+            k_rbgs<T, D><<<gr, BS, 0, st>>>(g, phi[l], b[l], 0, C);
+        }
+    }
+
+    // max over slices of |b - L phi| / |b| (synchronises; host mirror given).
+    double ratio(int B, double* host) {
+        const Grid& g = PG[0];
+        const int nb = std::min(RED_BLOCKS, blocks_for(g.ncell, BS));
+        k_poisson_resid_norm<T, D><<<dim3(nb, B), BS, 0, st>>>(g, phi[0], b[0], pool, g.ncell);
+        k_poisson_ratio<<<1, BS, 0, st>>>(B, nb, pool, out, 0);
+        HCK(hipMemcpyAsync(host, out, sizeof(double), hipMemcpyDeviceToHost, st));
+        HCK(hipStreamSynchronize(st));
+        return host[0];
+    }
+
+    // out = Q w for B slices (out may alias w).  fixed > 0: exactly that many
+    // cycles and no host synchronisation; otherwise cycles until the
+    // relative residual of every slice is <= rtol.  Returns the cycle count.
+    int project(const T* w, T* o, T* phi_out, int B, double rtol, int fixed, double* host) {
+        const Grid& g = PG[0];
+        const long C = g.ncell;
+        k_divergence<T, D><<<dim3(blocks_for(C, BS), B), BS, 0, st>>>(g, w, b[0], g.nface, C);
+        k_fill<T><<<blocks_for((long)B * C, BS), BS, 0, st>>>((long)B * C, phi[0], (T)0);
+        int cycles = 0;
+        for (;;) {
+            vcycle(0, B);
+            ++cycles;
+            if (fixed > 0) {
+                if (cycles >= fixed) break;
+                continue;
+            }
+            if (cycles >= MAX_PROJECT_CYCLES) break;
+            const double r = ratio(B, host);
+            if (!std::isfinite(r) || r <= rtol) break;
+        }
+        k_project_apply<T, D><<<dim3(blocks_for(g.nface, BS), B), BS, 0, st>>>(g, w, phi[0], o, g.nface, C);
+        if (phi_out) {
+            k_slice_sum<T><<<B, BS, 0, st>>>((int)C, phi[0], pool, C);
+            k_sub_mean<T><<<dim3(blocks_for(C, BS), B), BS, 0, st>>>((int)C, phi[0], pool, C);
+            HCK(hipMemcpyAsync(phi_out, phi[0], (size_t)B * C * sizeof(T), hipMemcpyDeviceToDevice, st));
+        }
+        return cycles;
+    }
+};
+
+class SolverBase {
+public:
+    virtual ~SolverBase() {}
+    Params P;
+    hipStream_t st = nullptr;
+    size_t bytes = 0;
+    char* mem = nullptr;
+    virtual size_t plan() = 0;
+    virtual bool valid() const = 0;
+    virtual void carve(char* base) = 0;
+    virtual void init_tables() = 0;
+    virtual stfas_status solve(const void*, int, const int*, const void*, void*, stfas_stats*) = 0;
+    virtual int nlevels() const = 0;
+    virtual const Grid& level(int l) const = 0;
+    virtual void op_advect(int, const void*, const void*, void*) = 0;
+    virtual void op_advect_T(int, const void*, const void*, const void*, void*) = 0;
+    virtual void op_advect_dv_T(int, const void*, const void*, const void*, const void*, double, void*) = 0;
+    virtual void op_self_advect(int, int, const void*, const void*, void*) = 0;
+    virtual void op_self_advect_T(int, int, const void*, const void*, double, void*) = 0;
+    virtual int op_project(int, const void*, void*, void*) = 0;
+    virtual void op_metric(const void*, void*) = 0;
+    virtual void op_kkt(int, stfas_state, const void*, stfas_state, stfas_state) = 0;
+    virtual void op_sweep(int, stfas_state, const void*, stfas_state) = 0;
+    virtual void op_restrict(int, stfas_state, stfas_state) = 0;
+    virtual void op_prolong(int, stfas_state, double, stfas_state) = 0;
+    virtual int op_nso(stfas_state, const void*, double*) = 0;
+    virtual void op_ao(const void*, int, const int*, const void*, const void*, void*, void*, double*) = 0;
+};
+
+template <typename T, int D>
+class Solver : public SolverBase {
+public:
+    // ---- levels and constant tables
+    std::vector<Grid> L;      // STFAS levels
+    int N = 0;
+    // STFAS per-level buffers
+    struct Lev {
+        T *v, *pb, *u, *p;       // state
+        T *r1, *r2, *r3, *r4;    // residual
+        T *s1, *s2, *s3, *s4;    // FAS right-hand side (unused on level 0)
+        T* w;                    // targets
+    };
+    std::vector<Lev> lev;
+    T* scgs_scratch = nullptr;
+    T *t_diag, *t_sub, *t_sup, *t_cp, *t_inv;
+    Poisson<T, D> pois;      // projection, batched over up to N slices
+    // density subproblem
+    T *rho, *rho_t, *mu, *vt, *vstar, *cand, *trial;
+    T *ce_e, *ce_acc, *ce_t1, *ce_t2;
+    T* taps = nullptr;
+    std::vector<int> tap_off, tap_R;
+    // ADMM
+    T *lam, *rho_last, *wt;
+    // re-simulation
+    T *rs_rho[2], *rs_v[2], *rs_w;
+    // reductions
+    double *red_part, *red_out;
+    double* host_out = nullptr;   // pinned mirror of red_out
+
+    explicit Solver(const Params& p, hipStream_t s) {
+        P = p;
+        st = s;
+        N = p.N;
+        const int n[3] = {p.n[0], p.n[1], p.n[2]};
+        Grid g0 = make_grid(p.dim, n, 1.0 / p.n[0]);
+        L = stfas_levels(g0);
+        pois.init(g0, p.N, s);
+    }
+    ~Solver() override {
+        if (host_out) (void)hipHostFree(host_out);
+    }
+
+    int nlevels() const override { return (int)L.size(); }
+    const Grid& level(int l) const override { return L[l]; }
+
+    bool valid() const override { return pois.coarse_ok(); }
+
+    void layout(Arena& A) {
+        const long F0 = L[0].nface, C0 = L[0].ncell;
+        lev.assign(L.size(), Lev{});
+        for (size_t l = 0; l < L.size(); ++l) {
+            const long F = L[l].nface, C = L[l].ncell;
+            Lev& q = lev[l];
+            q.v = A.take<T>(N * F);
+            q.pb = A.take<T>(N * C);
+            q.u = A.take<T>(N * F);
+            q.p = A.take<T>(N * C);
+            q.r1 = A.take<T>(N * F);
+            q.r2 = A.take<T>(N * C);
+            q.r3 = A.take<T>(N * F);
+            q.r4 = A.take<T>(N * C);
+            if (l > 0) {
+                q.s1 = A.take<T>(N * F);
+                q.s2 = A.take<T>(N * C);
+                q.s3 = A.take<T>(N * F);
+                q.s4 = A.take<T>(N * C);
+            } else {
+                q.s1 = q.s2 = q.s3 = q.s4 = nullptr;
+            }
+            q.w = A.take<T>(N * F);
+        }
+        // SCGS scratch: the largest colour of level 0, 2N blocks, 2d faces per cell
+        long maxcol = 0;
+        for (int c = 0; c < (1 << D); ++c) maxcol = std::max<long>(maxcol, colour_set(L[0], c).total);
+        scgs_scratch = A.take<T>((size_t)maxcol * 2 * D * 2 * N);
+        t_diag = A.take<T>(2 * N);
+        t_sub = A.take<T>(2 * N);
+        t_sup = A.take<T>(2 * N);
+        t_cp = A.take<T>(2 * N);
+        t_inv = A.take<T>(2 * N);
+        pois.layout(A, nullptr);
+        rho = A.take<T>((N + 1) * C0);
+        rho_t = A.take<T>((N + 1) * C0);
+        mu = A.take<T>(N * C0);
+        vt = A.take<T>(N * F0);
+        vstar = A.take<T>(N * F0);
+        cand = A.take<T>(N * F0);
+        trial = A.take<T>(N * F0);
+        ce_e = A.take<T>(C0);
+        ce_acc = A.take<T>(C0);
+        ce_t1 = A.take<T>(C0);
+        ce_t2 = A.take<T>(C0);
+        size_t ntaps = 0;
+        for (int l = 1; l <= P.metric_levels; ++l) ntaps += gauss_taps(std::ldexp(1.0, l - 1)).size();
+        taps = A.take<T>(std::max<size_t>(ntaps, 1));
+        lam = A.take<T>(N * F0);
+        rho_last = A.take<T>((N + 1) * C0);
+        wt = A.take<T>(N * F0);
+        rs_rho[0] = A.take<T>(C0);
+        rs_rho[1] = A.take<T>(C0);
+        rs_v[0] = A.take<T>(F0);
+        rs_v[1] = A.take<T>(F0);
+        rs_w = A.take<T>(F0);
+        red_part = A.take<double>(RED_BLOCKS);
+        red_out = A.take<double>(64);
+    }
+
+    size_t plan() override {
+        Arena A;
+        layout(A);
+        return A.off;
+    }
+    void carve(char* base) override {
+        Arena A;
+        A.base = base;
+        layout(A);
+    }
+
+    template <typename U>
+    void upload(U* dst, const std::vector<double>& src) {
+        std::vector<U> tmp(src.begin(), src.end());
+        HCK(hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(U), hipMemcpyHostToDevice, st));
+        HCK(hipStreamSynchronize(st));
+    }
+
+    void init_tables() override {
+        HCK(hipHostMalloc((void**)&host_out, 64 * sizeof(double), hipHostMallocDefault));
+        TFactors f = temporal_factors(N, P.dt, P.K / P.r);
+        upload(t_diag, f.diag);
+        upload(t_sub, f.sub);
+        upload(t_sup, f.sup);
+        upload(t_cp, f.cp);
+        upload(t_inv, f.inv);
+        pois.upload_pinv();
+        std::vector<double> all;
+        tap_off.clear();
+        tap_R.clear();
+        for (int l = 1; l <= P.metric_levels; ++l) {
+            auto k = gauss_taps(std::ldexp(1.0, l - 1));
+            tap_off.push_back((int)all.size());
+            tap_R.push_back(((int)k.size() - 1) / 2);
+            all.insert(all.end(), k.begin(), k.end());
+        }
+        if (!all.empty()) upload(taps, all);
+    }
+
+    // ------------------------------------------------------------ helpers
+    T cfl(int l) const { return (T)(P.dt / L[l].h); }
+    void fill(T* x, long n, T val) {
+        if (n <= 0) return;
+        k_fill<T><<<blocks_for(n, BS), BS, 0, st>>>(n, x, val);
+    }
+    void copy(T* dst, const T* src, long n) {
+        if (n <= 0) return;
+        HCK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    }
+    void axpby(long n, T a, const T* x, T b, const T* y, T* out) {
+        k_axpby<T><<<blocks_for(n, BS), BS, 0, st>>>(n, a, x, b, y, out);
+    }
+    // red_out[slot] (op)= reduce(x, y) over n elements
+    void reduce(int op, long n, const T* x, const T* y, int slot, bool accumulate) {
+        const int nb = (int)std::min<long>(RED_BLOCKS, std::max<long>(1, blocks_for(n, BS)));
+        k_reduce_part<T><<<nb, BS, 0, st>>>(n, op, x, y, red_part);
+        k_reduce_final<<<1, BS, 0, st>>>(nb, op, red_part, red_out, slot, accumulate ? 1 : 0);
+    }
+    void zero_slots(int n) { k_fill<double><<<1, 64, 0, st>>>(n, red_out, 0.0); }
+    void readback(int n) {
+        HCK(hipMemcpyAsync(host_out, red_out, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        HCK(hipStreamSynchronize(st));
+    }
+
+    // ------------------------------------------------------------ advection
+    void advect(const T* r, const T* v, T* out, int batch) {
+        const Grid& g = L[0];
+        k_advect<T, D><<<dim3(blocks_for(g.ncell, BS), batch), BS, 0, st>>>(g, cfl(0), r, v, out, g.ncell, g.nface);
+    }
+    void advect_T(const T* m, const T* v, T* out, int batch) {
+        const Grid& g = L[0];
+        k_advect_T<T, D><<<dim3(blocks_for(g.ncell, BS), batch), BS, 0, st>>>(g, cfl(0), m, v, out, g.ncell,
+                                                                             g.nface);
+    }
+    void advect_dv_T(const T* m, const T* r, const T* v, const T* vtt, T scale, T* gv, int batch) {
+        const Grid& g = L[0];
+        k_advect_dv_T<T, D><<<dim3(blocks_for(g.nface, BS), batch), BS, 0, st>>>(g, cfl(0), m, r, v, vtt, scale,
+                                                                                gv, g.ncell, g.nface);
+    }
+    void self_advect(int l, const T* v, const T* u, T* out, int batch) {
+        const Grid& g = L[l];
+        k_self_advect<T, D><<<dim3(blocks_for(g.nface, BS), batch), BS, 0, st>>>(g, cfl(l), (T)P.dt, v, u, out,
+                                                                                g.nface);
+    }
+    void self_advect_T(int l, const T* v, const T* y, T scale, T* out, int batch) {
+        if (batch <= 0) return;
+        const Grid& g = L[l];
+        k_self_advect_T<T, D><<<dim3(blocks_for(g.nface, BS), batch), BS, 0, st>>>(g, cfl(l), v, y, scale, out,
+                                                                                  g.nface);
+    }
+
+    // ------------------------------------------------------------ projection
+    int project(const T* w, T* out, T* phi_out, int B, int fixed = 0) {
+        return pois.project(w, out, phi_out, B, P.poisson_rtol, fixed, host_out);
+    }
+
+    // ------------------------------------------------------------ metric
+    // out = C e = e + sum_l G_l G_l e   (separable Gaussians, zero padding)
+    void metric(const T* e, T* out) {
+        const Grid& g = L[0];
+        const long C = g.ncell;
+        copy(out, e, C);
+        for (int l = 0; l < P.metric_levels; ++l) {
+            const T* src = e;
+            T* bufs[2] = {ce_t1, ce_t2};
+            int cur = 0;
+            for (int pass = 0; pass < 2 * D; ++pass) {
+                k_blur_axis<T><<<blocks_for(C, BS), BS, 0, st>>>(g, pass % D, tap_R[l], taps + tap_off[l], src,
+                                                                 bufs[cur]);
+                src = bufs[cur];
+                cur ^= 1;
+            }
+            axpby(C, (T)1, out, (T)1, src, out);
+        }
+    }
+
+    // ------------------------------------------------------------ KKT
+    // out = res + sgn f(x) on level l.
+    void kkt(int l, const T* v, const T* pb, const T* u, const T* p, const T* w, const T* s1, const T* s2,
+             const T* s3, const T* s4, T* o1, T* o2, T* o3, T* o4, T sgn) {
+        const Grid& g = L[l];
+        const T dt = (T)P.dt;
+        k_kkt_faces<T, D><<<dim3(blocks_for(g.nface, BS), N), BS, 0, st>>>(g, N, dt, (T)(P.K / P.r), cfl(l), sgn, v, pb,
+                                                                          u, p, w, s1, s3, o1, o3);
+        k_kkt_cells<T, D><<<dim3(blocks_for(g.ncell, BS), N), BS, 0, st>>>(g, sgn, v, u, s2, s4, o2, o4);
+        if (N > 1) self_advect_T(l, v, u + g.nface, (T)(-sgn / dt), o1, N - 1);
+    }
+    void kkt_level(int l, bool fas_rhs) {
+        Lev& q = lev[l];
+        if (fas_rhs)
+            kkt(l, q.v, q.pb, q.u, q.p, q.w, q.s1, q.s2, q.s3, q.s4, q.s1, q.s2, q.s3, q.s4, (T)1);
+        else
+            kkt(l, q.v, q.pb, q.u, q.p, q.w, q.s1, q.s2, q.s3, q.s4, q.r1, q.r2, q.r3, q.r4, (T)-1);
+    }
+
+    void sweep(int l) {
+        const Grid& g = L[l];
+        Lev& q = lev[l];
+        for (int colour = 0; colour < (1 << D); ++colour) {
+            kkt_level(l, false);
+            const ColourSet cs = colour_set(g, colour);
+            const int nf = cs.total * 2 * D;
+            k_scgs_faces<T, D><<<blocks_for(nf, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r2, q.r3, q.r4, q.v, q.u, t_sub,
+                                                                 t_cp, t_inv, scgs_scratch);
+            const int nc = cs.total * 2 * N;
+            k_scgs_cells<T, D><<<blocks_for(nc, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r2, q.r3, q.r4, q.pb, q.p, t_diag,
+                                                                 t_sub, t_sup);
+        }
+    }
+
+    void restrict_faces(int l, const T* fine, T* coarse) {
+        k_restrict_faces<T, D><<<dim3(blocks_for(L[l + 1].nface, BS), N), BS, 0, st>>>(L[l], L[l + 1], fine, coarse);
+    }
+    void restrict_cells(int l, const T* fine, T* coarse) {
+        k_restrict_cells<T, D><<<dim3(blocks_for(L[l + 1].ncell, BS), N), BS, 0, st>>>(L[l], L[l + 1], fine, coarse);
+    }
+    void prolong_faces(int l, const T* coarse, T sign, T* fine) {
+        k_prolong_faces<T, D><<<dim3(blocks_for(L[l].nface, BS), N), BS, 0, st>>>(L[l], L[l + 1], coarse, sign, fine);
+    }
+    void prolong_cells(int l, const T* coarse, T sign, T* fine) {
+        k_prolong_cells<T, D><<<dim3(blocks_for(L[l].ncell, BS), N), BS, 0, st>>>(L[l], L[l + 1], coarse, sign, fine);
+    }
+
+    void vcycle(int l) {
+        Lev& q = lev[l];
+        if (l == (int)L.size() - 1) {
+            for (int s = 0; s < 10; ++s) sweep(l);
+            return;
+        }
+        sweep(l);
+        sweep(l);
+        kkt_level(l, false);                                   // r = res - f(x_s)
+        Lev& c = lev[l + 1];
+        restrict_faces(l, q.v, c.v);                           // x^{2h} = R x_s
+        restrict_cells(l, q.pb, c.pb);
+        restrict_faces(l, q.u, c.u);
+        restrict_cells(l, q.p, c.p);
+        prolong_faces(l, c.v, (T)-1, q.v);                     // x = x_s - P x^{2h}
+        prolong_cells(l, c.pb, (T)-1, q.pb);
+        prolong_faces(l, c.u, (T)-1, q.u);
+        prolong_cells(l, c.p, (T)-1, q.p);
+        restrict_faces(l, q.r1, c.s1);                         // res^{2h} = R r + f(x^{2h})
+        restrict_cells(l, q.r2, c.s2);
+        restrict_faces(l, q.r3, c.s3);
+        restrict_cells(l, q.r4, c.s4);
+        kkt_level(l + 1, true);
+        vcycle(l + 1);
+        prolong_faces(l, c.v, (T)1, q.v);                      // x += P x^{2h}
+        prolong_cells(l, c.pb, (T)1, q.pb);
+        prolong_faces(l, c.u, (T)1, q.u);
+        prolong_cells(l, c.p, (T)1, q.p);
+        sweep(l);
+        sweep(l);
+    }
+
+    double residual_inf() {
+        Lev& q = lev[0];
+        kkt_level(0, false);
+        const long F = L[0].nface, C = L[0].ncell;
+        reduce(RED_MAXABS_DIFF, N * F, q.r1, nullptr, 0, false);
+        reduce(RED_MAXABS_DIFF, N * C, q.r2, nullptr, 0, true);
+        reduce(RED_MAXABS_DIFF, N * F, q.r3, nullptr, 0, true);
+        reduce(RED_MAXABS_DIFF, N * C, q.r4, nullptr, 0, true);
+        readback(1);
+        return host_out[0];
+    }
+
+    // Velocity subproblem on lev[0] state with lev[0].w targets.
+    int nso(double* hist, double* last) {
+        for (size_t l = 0; l + 1 < L.size(); ++l) restrict_faces((int)l, lev[l].w, lev[l + 1].w);
+        const long F = L[0].nface;
+        double f0 = 0;
+        if (N > 1) {
+            reduce(RED_MAXABS_DIFF, (N - 1) * F, lev[0].w + F, nullptr, 0, false);
+            readback(1);
+            f0 = (P.K / P.r) * host_out[0];
+        }
+        double h = residual_inf();
+        if (hist) hist[0] = h;
+        int n = 0;
+        while (n < P.max_vcycles) {
+            if (!P.fixed_counts && h <= P.eps_stfas * f0) break;
+            vcycle(0);
+            ++n;
+            h = residual_inf();
+            if (hist) hist[n] = h;
+            if (!std::isfinite(h)) break;
+        }
+        if (last) *last = h;
+        return n;
+    }
+
+    // ------------------------------------------------------------ density subproblem
+    void forward_sweep(const T* rho0, const T* vs, T* r) {
+        const long C = L[0].ncell, F = L[0].nface;
+        copy(r, rho0, C);
+        for (int i = 0; i < N; ++i) advect(r + i * C, vs + i * F, r + (i + 1) * C, 1);
+    }
+
+    // Phi = 1/2 sum_key <e, C e> + K/2 |vt - vs|^2 (reduced in double).
+    double ao_objective(const T* r, const T* vs, int nk, const int* ks, const T* keys) {
+        const long C = L[0].ncell, F = L[0].nface;
+        zero_slots(2);
+        for (int q = 0; q < nk; ++q) {
+            axpby(C, (T)1, r + (long)ks[q] * C, (T)-1, keys + q * C, ce_e);
+            metric(ce_e, ce_acc);
+            reduce(RED_DOT, C, ce_e, ce_acc, 0, true);
+        }
+        reduce(RED_SUMSQ_DIFF, N * F, vt, vs, 1, false);
+        readback(2);
+        return 0.5 * host_out[0] + 0.5 * P.K * host_out[1];
+    }
+
+    void ao_backward(const T* r, const T* vs, int nk, const int* ks, const T* keys) {
+        const long C = L[0].ncell, F = L[0].nface;
+        for (int i = N; i >= 1; --i) {
+            T* out = mu + (i - 1) * C;
+            int kq = -1;
+            for (int q = 0; q < nk; ++q)
+                if (ks[q] == i) kq = q;
+            if (kq >= 0) {
+                axpby(C, (T)1, r + (long)i * C, (T)-1, keys + kq * C, ce_e);
+                metric(ce_e, ce_acc);
+                axpby(C, (T)-1, ce_acc, (T)0, nullptr, out);
+            } else {
+                fill(out, C, (T)0);
+            }
+            if (i < N) advect_T(mu + i * C, vs + i * F, out, 1);
+        }
+    }
+
+    // Alg:Passive with blending; vt must hold v + lambda/K.  Result in vstar, rho.
+    void ao(const T* rho0, int nk, const int* ks, const T* keys, double* hist) {
+        const long C = L[0].ncell, F = L[0].nface;
+        copy(vstar, vt, N * F);
+        forward_sweep(rho0, vstar, rho);
+        double phi = ao_objective(rho, vstar, nk, ks, keys);
+        if (hist) hist[0] = phi;
+        for (int it = 0; it < P.ao_iters; ++it) {
+            ao_backward(rho, vstar, nk, ks, keys);
+            advect_dv_T(mu, rho, vstar, vt, (T)(1.0 / P.K), cand, N);
+            project(cand, cand, nullptr, N);
+            double alpha = 1.0;
+            for (int hv = 0; hv <= 10; ++hv) {
+                blend(vstar, cand, (T)alpha, trial, N * F);
+                forward_sweep(rho0, trial, rho_t);
+                const double pt = ao_objective(rho_t, trial, nk, ks, keys);
+                if (pt <= phi) {
+                    std::swap(vstar, trial);
+                    std::swap(rho, rho_t);
+                    phi = pt;
+                    break;
+                }
+                alpha *= 0.5;
+            }
+            if (hist) hist[it + 1] = phi;
+        }
+    }
+
+    void blend(const T* x, const T* y, T alpha, T* out, long n);
+
+    // ------------------------------------------------------------ ADMM
+    stfas_status solve(const void* rho0v, int nk, const int* ks, const void* keysv, void* u_out,
+                       stfas_stats* stats) override {
+        const auto t0 = std::chrono::steady_clock::now();
+        const T* rho0 = (const T*)rho0v;
+        const T* keys = (const T*)keysv;
+        const long C = L[0].ncell, F = L[0].nface;
+        Lev& q = lev[0];
+        fill(q.v, N * F, (T)0);
+        fill(q.pb, N * C, (T)0);
+        fill(q.u, N * F, (T)0);
+        fill(q.p, N * C, (T)0);
+        fill(lam, N * F, (T)0);
+        for (int i = 0; i <= N; ++i) copy(rho_last + i * C, rho0, C);
+        double eps_admm = P.eps_admm;
+        if (eps_admm <= 0) {
+            reduce(RED_MAXABS_DIFF, C, rho0, nullptr, 0, false);
+            readback(1);
+            eps_admm = host_out[0] / 100.0;
+        }
+        const T invK = (T)(1.0 / P.K);
+        int it = 0, conv = 0, vcs = 0;
+        double last_res = 0, diff = 0;
+        while (it < P.max_admm) {
+            ++it;
+            // vt = v + lambda/K (v_0 = 0)
+            k_shift_combine<T><<<blocks_for(N * F, BS), BS, 0, st>>>(F, N, (T)1, q.v, invK, lam, (T)0, nullptr, vt);
+            ao(rho0, nk, ks, keys, nullptr);
+            // w = v* - lambda/K
+            axpby(N * F, (T)1, vstar, -invK, lam, q.w);
+            vcs += nso(nullptr, &last_res);
+            if (!std::isfinite(last_res)) return STFAS_E_NONFINITE;
+            reduce(RED_MAXABS_DIFF, (N + 1) * C, rho_last, rho, 0, false);
+            readback(1);
+            diff = host_out[0];
+            if (!std::isfinite(diff)) return STFAS_E_NONFINITE;
+            if (!P.fixed_counts && diff < eps_admm) {
+                conv = 1;
+                break;
+            }
+            copy(rho_last, rho, (N + 1) * C);
+            const T kb = (T)(P.K * P.beta);
+            k_shift_combine<T><<<blocks_for(N * F, BS), BS, 0, st>>>(F, N, kb, q.v, (T)1, lam, -kb, vstar, lam);
+        }
+        copy((T*)u_out, q.u, N * F);
+        // re-simulate and evaluate the objective
+        zero_slots(3);
+        copy(rs_rho[0], rho0, C);
+        fill(rs_v[0], F, (T)0);
+        int cur = 0;
+        for (int i = 0; i < N; ++i) {
+            advect(rs_rho[cur], rs_v[cur], rs_rho[cur ^ 1], 1);
+            self_advect(0, rs_v[cur], q.u + i * F, rs_w, 1);
+            project(rs_w, rs_v[cur ^ 1], nullptr, 1);
+            cur ^= 1;
+            for (int kq = 0; kq < nk; ++kq)
+                if (ks[kq] == i + 1) {
+                    axpby(C, (T)1, rs_rho[cur], (T)-1, keys + kq * C, ce_e);
+                    metric(ce_e, ce_acc);
+                    reduce(RED_DOT, C, ce_e, ce_acc, 0, true);
+                    reduce(RED_SUMSQ_DIFF, C, ce_e, nullptr, 1, true);
+                }
+        }
+        reduce(RED_SUMSQ_DIFF, N * F, q.u, nullptr, 2, false);
+        readback(3);
+        const double reg = 0.5 * P.r * host_out[2];
+        if (stats) {
+            stats->admm_iters = it;
+            stats->vcycles = vcs;
+            stats->converged = conv;
+            stats->objective = 0.5 * host_out[0] + reg;
+            stats->objective_l2 = 0.5 * host_out[1] + reg;
+            stats->reg_term = reg;
+            stats->kkt_res_inf = last_res;
+            stats->visual_diff = diff;
+            stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (!std::isfinite(0.5 * host_out[0] + reg)) return STFAS_E_NONFINITE;
+        return STFAS_OK;
+    }
+
+    // ------------------------------------------------------------ ops
+    void op_advect(int batch, const void* r, const void* v, void* out) override {
+        advect((const T*)r, (const T*)v, (T*)out, batch);
+    }
+    void op_advect_T(int batch, const void* m, const void* v, const void* add, void* out) override {
+        const long C = L[0].ncell;
+        if (add)
+            copy((T*)out, (const T*)add, batch * C);
+        else
+            fill((T*)out, batch * C, (T)0);
+        advect_T((const T*)m, (const T*)v, (T*)out, batch);
+    }
+    void op_advect_dv_T(int batch, const void* m, const void* r, const void* v, const void* vtt, double scale,
+                        void* gv) override {
+        advect_dv_T((const T*)m, (const T*)r, (const T*)v, (const T*)vtt, (T)scale, (T*)gv, batch);
+    }
+    void op_self_advect(int l, int batch, const void* v, const void* u, void* out) override {
+        self_advect(l, (const T*)v, (const T*)u, (T*)out, batch);
+    }
+    void op_self_advect_T(int l, int batch, const void* v, const void* y, double scale, void* out) override {
+        self_advect_T(l, (const T*)v, (const T*)y, (T)scale, (T*)out, batch);
+    }
+    int op_project(int batch, const void* w, void* out, void* phi) override {
+        return project((const T*)w, (T*)out, (T*)phi, batch);
+    }
+    void op_metric(const void* e, void* out) override { metric((const T*)e, (T*)out); }
+    void op_kkt(int l, stfas_state x, const void* w, stfas_state res, stfas_state out) override {
+        kkt(l, (const T*)x.v, (const T*)x.pbar, (const T*)x.u, (const T*)x.p, (const T*)w, (const T*)res.v,
+            (const T*)res.pbar, (const T*)res.u, (const T*)res.p, (T*)out.v, (T*)out.pbar, (T*)out.u, (T*)out.p,
+            (T)-1);
+    }
+    // Copy caller state into level l, run, copy back.
+    void load(int l, stfas_state x, const void* w, const stfas_state* res) {
+        const long F = L[l].nface, C = L[l].ncell;
+        Lev& q = lev[l];
+        copy(q.v, (const T*)x.v, N * F);
+        copy(q.pb, (const T*)x.pbar, N * C);
+        copy(q.u, (const T*)x.u, N * F);
+        copy(q.p, (const T*)x.p, N * C);
+        copy(q.w, (const T*)w, N * F);
+        if (res && l > 0) {
+            copy(q.s1, (const T*)res->v, N * F);
+            copy(q.s2, (const T*)res->pbar, N * C);
+            copy(q.s3, (const T*)res->u, N * F);
+            copy(q.s4, (const T*)res->p, N * C);
+        }
+    }
+    void store(int l, stfas_state x) {
+        const long F = L[l].nface, C = L[l].ncell;
+        Lev& q = lev[l];
+        copy((T*)x.v, q.v, N * F);
+        copy((T*)x.pbar, q.pb, N * C);
+        copy((T*)x.u, q.u, N * F);
+        copy((T*)x.p, q.p, N * C);
+    }
+    void op_sweep(int l, stfas_state x, const void* w, stfas_state res) override {
+        load(l, x, w, &res);
+        sweep(l);
+        store(l, x);
+    }
+    void op_restrict(int l, stfas_state f, stfas_state c) override {
+        restrict_faces(l, (const T*)f.v, (T*)c.v);
+        restrict_cells(l, (const T*)f.pbar, (T*)c.pbar);
+        restrict_faces(l, (const T*)f.u, (T*)c.u);
+        restrict_cells(l, (const T*)f.p, (T*)c.p);
+    }
+    void op_prolong(int l, stfas_state c, double sign, stfas_state f) override {
+        prolong_faces(l, (const T*)c.v, (T)sign, (T*)f.v);
+        prolong_cells(l, (const T*)c.pbar, (T)sign, (T*)f.pbar);
+        prolong_faces(l, (const T*)c.u, (T)sign, (T*)f.u);
+        prolong_cells(l, (const T*)c.p, (T)sign, (T*)f.p);
+    }
+    int op_nso(stfas_state x, const void* w, double* hist) override {
+        load(0, x, w, nullptr);
+        const int n = nso(hist, nullptr);
+        store(0, x);
+        return n;
+    }
+    void op_ao(const void* rho0, int nk, const int* ks, const void* keys, const void* vtt, void* vs, void* r,
+               double* hist) override {
+        const long C = L[0].ncell, F = L[0].nface;
+        copy(vt, (const T*)vtt, N * F);
+        ao((const T*)rho0, nk, ks, (const T*)keys, hist);
+        copy((T*)vs, vstar, N * F);
+        copy((T*)r, rho, (N + 1) * C);
+    }
+};
+
+// out = x + alpha (y - x), the blend of the density subproblem.
+template <typename T>
+__global__ void k_blend(long n, const T* __restrict__ x, const T* __restrict__ y, T alpha, T* __restrict__ out) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) out[e] = x[e] + alpha * (y[e] - x[e]);
+}
+
+template <typename T, int D>
+void Solver<T, D>::blend(const T* x, const T* y, T alpha, T* out, long n) {
+    k_blend<T><<<blocks_for(n, BS), BS, 0, st>>>(n, x, y, alpha, out);
+}
+
+}  // namespace stfas

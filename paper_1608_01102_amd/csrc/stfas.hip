@@ -1,0 +1,373 @@
+// C interface of the solver (include/stfas.h, include/stfas_ops.h).
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <tuple>
+
+#include "solver.hpp"
+
+using namespace stfas;
+
+struct stfas_ctx {
+    std::unique_ptr<SolverBase> s;
+    int device = 0;
+};
+
+namespace {
+
+template <typename F>
+stfas_status guard(F&& f) {
+    try {
+        return f();
+    } catch (const HipError&) {
+        return STFAS_E_DEVICE;
+    } catch (const std::bad_alloc&) {
+        return STFAS_E_NOMEM;
+    }
+}
+
+std::unique_ptr<SolverBase> make_solver(const Params& p, hipStream_t st) {
+    if (p.precision == STFAS_FP64) {
+        if (p.dim == 2) return std::make_unique<Solver<double, 2>>(p, st);
+        return std::make_unique<Solver<double, 3>>(p, st);
+    }
+    if (p.dim == 2) return std::make_unique<Solver<float, 2>>(p, st);
+    return std::make_unique<Solver<float, 3>>(p, st);
+}
+
+// ---------------------------------------------------------------- step engine
+// Projection workspace for one slice carved from caller memory, with the
+// coarsest-level pseudo-inverse cached per device and grid.
+std::mutex g_pinv_mu;
+std::map<std::tuple<int, int, int, int, int>, double*> g_pinv;
+
+double* cached_pinv(const Grid& coarse, hipStream_t st) {
+    int dev = 0;
+    HCK(hipGetDevice(&dev));
+    const auto key = std::make_tuple(dev, coarse.dim, coarse.n[0], coarse.n[1], coarse.n[2]);
+    std::lock_guard<std::mutex> lk(g_pinv_mu);
+    auto it = g_pinv.find(key);
+    if (it != g_pinv.end()) return it->second;
+    std::vector<double> pv;
+    coarse_pinv(coarse, pv);
+    double* d = nullptr;
+    HCK(hipMalloc((void**)&d, pv.size() * sizeof(double)));
+    HCK(hipMemcpy(d, pv.data(), pv.size() * sizeof(double), hipMemcpyHostToDevice));
+    g_pinv[key] = d;
+    return d;
+}
+
+int step_cycles(const Params& p) { return p.precision == STFAS_FP64 ? 24 : 10; }
+
+template <typename T, int D>
+struct Step {
+    Grid g;
+    Poisson<T, D> pois;
+    T *w, *gw;
+    hipStream_t st;
+    Step(const Params& p, hipStream_t s) : st(s) {
+        const int n[3] = {p.n[0], p.n[1], p.n[2]};
+        g = make_grid(p.dim, n, 1.0 / p.n[0]);
+        pois.init(g, 1, s);
+    }
+    void layout(Arena& A, double* pinv) {
+        pois.layout(A, pinv);
+        w = A.take<T>(g.nface);
+        gw = A.take<T>(g.nface);
+    }
+    size_t bytes() {
+        Arena A;
+        layout(A, (double*)1);
+        return A.off;
+    }
+
+    void forward(const Params& p, const T* rho, const T* v, const T* u, T* rho_o, T* v_o, T* p_o) {
+        const T cfl = (T)(p.dt / g.h);
+        k_advect<T, D><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g, cfl, rho, v, rho_o, g.ncell, g.nface);
+        k_self_advect<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, (T)p.dt, v, u, w, g.nface);
+        pois.project(w, v_o, p_o, 1, p.poisson_rtol, step_cycles(p), nullptr);
+        if (p_o) k_axpby<T><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g.ncell, (T)(1.0 / p.dt), p_o, (T)0, nullptr, p_o);
+    }
+
+    void backward(const Params& p, const T* rho, const T* v, const T* grho_o, const T* gv_o, T* grho, T* gv,
+                  T* gu) {
+        const T cfl = (T)(p.dt / g.h);
+        pois.project(gv_o, gw, nullptr, 1, p.poisson_rtol, step_cycles(p), nullptr);       // g_w = Q g_v'
+        k_axpby<T><<<blocks_for(g.nface, BS), BS, 0, st>>>(g.nface, (T)p.dt, gw, (T)0, nullptr, gu);
+        // g_v = (dA/dv)^T g_rho' + J_S^T g_w
+        k_advect_dv_T<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, grho_o, rho, v, nullptr, (T)1, gv,
+                                                                   g.ncell, g.nface);
+        k_self_advect_T<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, v, gw, (T)1, gv, g.nface);
+        k_fill<T><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g.ncell, grho, (T)0);
+        k_advect_T<T, D><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g, cfl, grho_o, v, grho, g.ncell, g.nface);
+    }
+};
+
+template <typename T, int D>
+stfas_status run_step(const Params& p, hipStream_t st, void* work, bool fwd, const void* a0, const void* a1,
+                      const void* a2, const void* a3, void* o0, void* o1, void* o2) {
+    Step<T, D> s(p, st);
+    if (!s.pois.coarse_ok()) return STFAS_E_INVALID;
+    Arena A;
+    A.base = (char*)work;
+    s.layout(A, cached_pinv(s.pois.PG.back(), st));
+    if (fwd)
+        s.forward(p, (const T*)a0, (const T*)a1, (const T*)a2, (T*)o0, (T*)o1, (T*)o2);
+    else
+        s.backward(p, (const T*)a0, (const T*)a1, (const T*)a2, (const T*)a3, (T*)o0, (T*)o1, (T*)o2);
+    HCK(hipPeekAtLastError());
+    return STFAS_OK;
+}
+
+stfas_status dispatch_step(const Params& p, hipStream_t st, void* work, bool fwd, const void* a0, const void* a1,
+                           const void* a2, const void* a3, void* o0, void* o1, void* o2) {
+    if (p.precision == STFAS_FP64) {
+        if (p.dim == 2) return run_step<double, 2>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2);
+        return run_step<double, 3>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2);
+    }
+    if (p.dim == 2) return run_step<float, 2>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2);
+    return run_step<float, 3>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2);
+}
+
+size_t step_bytes(const Params& p) {
+    if (p.precision == STFAS_FP64) {
+        if (p.dim == 2) return Step<double, 2>(p, nullptr).bytes();
+        return Step<double, 3>(p, nullptr).bytes();
+    }
+    if (p.dim == 2) return Step<float, 2>(p, nullptr).bytes();
+    return Step<float, 3>(p, nullptr).bytes();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stfas_status_string(stfas_status s) {
+    switch (s) {
+        case STFAS_OK: return "ok";
+        case STFAS_E_INVALID: return "invalid argument";
+        case STFAS_E_NOMEM: return "out of device memory";
+        case STFAS_E_DEVICE: return "HIP error";
+        case STFAS_E_NONFINITE: return "non-finite value";
+    }
+    return "unknown status";
+}
+
+const char* stfas_build_info(void) { return "stfas HIP/CDNA4 gfx950 build; fp64 and mixed fp32/fp64 paths"; }
+
+size_t stfas_workspace_bytes(const stfas_problem* prob) {
+    Params p;
+    if (!resolve(prob, p)) return 0;
+    auto s = make_solver(p, nullptr);
+    if (!s->valid()) return 0;
+    return s->plan();
+}
+
+stfas_status stfas_create(const stfas_problem* prob, void* hip_stream, stfas_ctx** out) {
+    if (!out) return STFAS_E_INVALID;
+    *out = nullptr;
+    Params p;
+    if (!resolve(prob, p)) return STFAS_E_INVALID;
+    return guard([&]() -> stfas_status {
+        auto c = std::make_unique<stfas_ctx>();
+        c->s = make_solver(p, (hipStream_t)hip_stream);
+        if (!c->s->valid()) return STFAS_E_INVALID;
+        HCK(hipGetDevice(&c->device));
+        const size_t bytes = c->s->plan();
+        char* mem = nullptr;
+        if (hipMalloc((void**)&mem, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return STFAS_E_NOMEM;
+        }
+        c->s->mem = mem;
+        c->s->bytes = bytes;
+        c->s->carve(mem);
+        c->s->init_tables();
+        *out = c.release();
+        return STFAS_OK;
+    });
+}
+
+void stfas_destroy(stfas_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->s && ctx->s->mem) {
+        (void)hipStreamSynchronize(ctx->s->st);
+        (void)hipFree(ctx->s->mem);
+    }
+    delete ctx;
+}
+
+static bool valid_keys(const stfas_ctx* ctx, int32_t num_key, const int32_t* key_steps, const void* key_rho) {
+    if (num_key < 0) return false;
+    if (num_key > 0 && (!key_steps || !key_rho)) return false;
+    for (int q = 0; q < num_key; ++q) {
+        if (key_steps[q] < 1 || key_steps[q] > ctx->s->P.N) return false;
+        if (q > 0 && key_steps[q] <= key_steps[q - 1]) return false;
+    }
+    return true;
+}
+
+stfas_status stfas_solve(stfas_ctx* ctx, const void* rho0, int32_t num_key, const int32_t* key_steps,
+                         const void* key_rho, void* u_out, stfas_stats* stats) {
+    if (!ctx || !rho0 || !u_out) return STFAS_E_INVALID;
+    if (!valid_keys(ctx, num_key, key_steps, key_rho)) return STFAS_E_INVALID;
+    return guard([&]() -> stfas_status {
+        const stfas_status s = ctx->s->solve(rho0, num_key, key_steps, key_rho, u_out, stats);
+        HCK(hipPeekAtLastError());
+        HCK(hipStreamSynchronize(ctx->s->st));
+        return s;
+    });
+}
+
+size_t stfas_step_work_bytes(const stfas_problem* prob) {
+    Params p;
+    if (!resolve(prob, p)) return 0;
+    return step_bytes(p);
+}
+
+int32_t stfas_step_vcycles(const stfas_problem* prob) {
+    Params p;
+    if (!resolve(prob, p)) return 0;
+    return step_cycles(p);
+}
+
+stfas_status stfas_step_forward(const stfas_problem* prob, void* hip_stream, const void* rho, const void* v,
+                                const void* u, void* rho_out, void* v_out, void* p_out, void* work) {
+    Params p;
+    if (!resolve(prob, p)) return STFAS_E_INVALID;
+    if (!rho || !v || !u || !rho_out || !v_out || !work) return STFAS_E_INVALID;
+    return guard([&]() {
+        return dispatch_step(p, (hipStream_t)hip_stream, work, true, rho, v, u, nullptr, rho_out, v_out, p_out);
+    });
+}
+
+stfas_status stfas_step_backward(const stfas_problem* prob, void* hip_stream, const void* rho, const void* v,
+                                 const void* g_rho_out, const void* g_v_out, void* g_rho, void* g_v, void* g_u,
+                                 void* work) {
+    Params p;
+    if (!resolve(prob, p)) return STFAS_E_INVALID;
+    if (!rho || !v || !g_rho_out || !g_v_out || !g_rho || !g_v || !g_u || !work) return STFAS_E_INVALID;
+    return guard([&]() {
+        return dispatch_step(p, (hipStream_t)hip_stream, work, false, rho, v, g_rho_out, g_v_out, g_rho, g_v, g_u);
+    });
+}
+
+// ---------------------------------------------------------------- operator level
+int32_t stfas_num_levels(const stfas_ctx* ctx) { return ctx ? ctx->s->nlevels() : 0; }
+
+int64_t stfas_level_cells(const stfas_ctx* ctx, int32_t level) {
+    if (!ctx || level < 0 || level >= ctx->s->nlevels()) return 0;
+    return ctx->s->level(level).ncell;
+}
+
+int64_t stfas_level_faces(const stfas_ctx* ctx, int32_t level) {
+    if (!ctx || level < 0 || level >= ctx->s->nlevels()) return 0;
+    return ctx->s->level(level).nface;
+}
+
+static bool ok_batch(const stfas_ctx* ctx, int32_t batch) { return ctx && batch >= 1 && batch <= 65535; }
+static bool ok_level(const stfas_ctx* ctx, int32_t l) { return ctx && l >= 0 && l < ctx->s->nlevels(); }
+
+#define OP_BODY(stmt)                     \
+    return guard([&]() -> stfas_status { \
+        stmt;                             \
+        HCK(hipPeekAtLastError());        \
+        return STFAS_OK;                  \
+    })
+
+stfas_status stfas_op_advect(stfas_ctx* ctx, int32_t batch, const void* rho, const void* v, void* out) {
+    if (!ok_batch(ctx, batch) || !rho || !v || !out) return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_advect(batch, rho, v, out));
+}
+
+stfas_status stfas_op_advect_T(stfas_ctx* ctx, int32_t batch, const void* mu, const void* v, const void* add,
+                               void* out) {
+    if (!ok_batch(ctx, batch) || !mu || !v || !out) return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_advect_T(batch, mu, v, add, out));
+}
+
+stfas_status stfas_op_advect_dv_T(stfas_ctx* ctx, int32_t batch, const void* mu, const void* rho, const void* v,
+                                  const void* vt, double scale, void* gv) {
+    if (!ok_batch(ctx, batch) || !mu || !rho || !v || !gv) return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_advect_dv_T(batch, mu, rho, v, vt, scale, gv));
+}
+
+stfas_status stfas_op_self_advect(stfas_ctx* ctx, int32_t level, int32_t batch, const void* v, const void* u,
+                                  void* out) {
+    if (!ok_batch(ctx, batch) || !ok_level(ctx, level) || !v || !out) return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_self_advect(level, batch, v, u, out));
+}
+
+stfas_status stfas_op_self_advect_T(stfas_ctx* ctx, int32_t level, int32_t batch, const void* v, const void* y,
+                                    double scale, void* out) {
+    if (!ok_batch(ctx, batch) || !ok_level(ctx, level) || !v || !y || !out) return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_self_advect_T(level, batch, v, y, scale, out));
+}
+
+stfas_status stfas_op_project(stfas_ctx* ctx, int32_t batch, const void* w, void* out, void* phi, int32_t* cycles) {
+    if (!ok_batch(ctx, batch) || batch > ctx->s->P.N || !w || !out) return STFAS_E_INVALID;
+    return guard([&]() -> stfas_status {
+        const int c = ctx->s->op_project(batch, w, out, phi);
+        if (cycles) *cycles = c;
+        HCK(hipPeekAtLastError());
+        return STFAS_OK;
+    });
+}
+
+stfas_status stfas_op_metric(stfas_ctx* ctx, const void* e, void* out) {
+    if (!ctx || !e || !out) return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_metric(e, out));
+}
+
+static bool ok_state(const stfas_state& x) { return x.v && x.pbar && x.u && x.p; }
+
+stfas_status stfas_op_kkt_residual(stfas_ctx* ctx, int32_t level, stfas_state x, const void* w, stfas_state res,
+                                   stfas_state out) {
+    if (!ok_level(ctx, level) || !ok_state(x) || !ok_state(out) || !w) return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_kkt(level, x, w, res, out));
+}
+
+stfas_status stfas_op_scgs_sweep(stfas_ctx* ctx, int32_t level, stfas_state x, const void* w, stfas_state res) {
+    if (!ok_level(ctx, level) || !ok_state(x) || !w) return STFAS_E_INVALID;
+    if (level > 0 && !ok_state(res)) return STFAS_E_INVALID;
+    if (level == 0 && (res.v || res.pbar || res.u || res.p)) return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_sweep(level, x, w, res));
+}
+
+stfas_status stfas_op_restrict(stfas_ctx* ctx, int32_t level, stfas_state fine, stfas_state coarse) {
+    if (!ctx || level < 0 || level + 1 >= ctx->s->nlevels() || !ok_state(fine) || !ok_state(coarse))
+        return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_restrict(level, fine, coarse));
+}
+
+stfas_status stfas_op_prolong(stfas_ctx* ctx, int32_t level, stfas_state coarse, double sign, stfas_state fine) {
+    if (!ctx || level < 0 || level + 1 >= ctx->s->nlevels() || !ok_state(fine) || !ok_state(coarse))
+        return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_prolong(level, coarse, sign, fine));
+}
+
+stfas_status stfas_op_nso(stfas_ctx* ctx, stfas_state x, const void* w, int32_t* vcycles, double* hist) {
+    if (!ctx || !ok_state(x) || !w) return STFAS_E_INVALID;
+    return guard([&]() -> stfas_status {
+        const int n = ctx->s->op_nso(x, w, hist);
+        if (vcycles) *vcycles = n;
+        HCK(hipPeekAtLastError());
+        HCK(hipStreamSynchronize(ctx->s->st));
+        return STFAS_OK;
+    });
+}
+
+stfas_status stfas_op_ao(stfas_ctx* ctx, const void* rho0, int32_t num_key, const int32_t* key_steps,
+                         const void* key_rho, const void* vt, void* vstar, void* rho, double* phi_hist) {
+    if (!ctx || !rho0 || !vt || !vstar || !rho) return STFAS_E_INVALID;
+    if (!valid_keys(ctx, num_key, key_steps, key_rho)) return STFAS_E_INVALID;
+    return guard([&]() -> stfas_status {
+        ctx->s->op_ao(rho0, num_key, key_steps, key_rho, vt, vstar, rho, phi_hist);
+        HCK(hipPeekAtLastError());
+        HCK(hipStreamSynchronize(ctx->s->st));
+        return STFAS_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+"""Operator-level parity of the HIP library with the FP64 oracle, through the
+C interface.  Bar: relative L2 error <= 1e-10 (FP64) / 1e-4 (mixed)."""
+import numpy as np
+import pytest
+
+import synthetic
+from gpu_common import TOL, empty, flag, rel, to_dev, to_np, zeros
+from oracle import advect, kkt, metric, poisson, scgs, stfas, transfer
+from oracle.grid import Grid
+
+pytestmark = pytest.mark.gpu
+
+CASES = [((16, 12), 4), ((8, 8, 8), 3), ((20, 12), 5)]
+PRECS = ["fp64", "mixed"]
+
+
+def _ctx(n, N, prec, dt=None, K=None, r=1e-2, **kw):
+    from paper_1608_01102_amd import stfas as S
+    g = Grid(n)
+    dt = 0.7 * g.h if dt is None else dt
+    K = 3.0 * r / dt ** 2 if K is None else K
+    prob = S.make_problem(n, N, r, dt=dt, K=K, precision=prec, **kw)
+    return S, S.stfas_create(prob), g, dt, K
+
+
+def _q(x, prec):
+    """Round inputs to the device precision so both sides see the same data."""
+    return np.asarray(x, dtype=np.float32).astype(np.float64) if prec == "mixed" else np.asarray(x)
+
+
+def _faces(g, rng, B, s=1.0):
+    return np.stack([synthetic.random_faces(g.n, rng, s) for _ in range(B)])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", CASES)
+def test_advect_and_transposes(n, N, prec):
+    S, ctx, g, dt, K = _ctx(n, N, prec)
+    rng = np.random.default_rng(11)
+    B = N
+    rho = _q(rng.standard_normal((B, g.ncell)), prec)
+    v = _q(_faces(g, rng, B, 2.0), prec)
+    mu = _q(rng.standard_normal((B, g.ncell)), prec)
+    vt = _q(_faces(g, rng, B), prec)
+    flag(f"advect n={n} N={N} {prec}")
+    out = empty(B * g.ncell, prec)
+    S.stfas_op_advect(ctx, B, to_dev(rho, prec), to_dev(v, prec), out)
+    ref = advect.advect_scalar(g, rho, v, dt)
+    assert rel(to_np(out), ref) <= TOL[prec]
+    add = _q(rng.standard_normal((B, g.ncell)), prec)
+    S.stfas_op_advect_T(ctx, B, to_dev(mu, prec), to_dev(v, prec), to_dev(add, prec), out)
+    ref = advect.advect_scalar_T(g, mu, v, dt) + add
+    assert rel(to_np(out), ref) <= TOL[prec]
+    gv = empty(B * g.nface, prec)
+    S.stfas_op_advect_dv_T(ctx, B, to_dev(mu, prec), to_dev(rho, prec), to_dev(v, prec), to_dev(vt, prec), 0.3, gv)
+    ref = vt * g.interior_mask() + 0.3 * advect.advect_scalar_dv_T(g, mu, rho, v, dt)
+    assert rel(to_np(gv), ref) <= TOL[prec]
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", CASES)
+def test_self_advect_and_transpose(n, N, prec):
+    S, ctx, g, dt, K = _ctx(n, N, prec)
+    rng = np.random.default_rng(12)
+    B = N
+    for level in range(ctx.num_levels()):
+        gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
+        v = _q(_faces(gl, rng, B, 1.5), prec)
+        u = _q(_faces(gl, rng, B), prec)
+        y = _q(_faces(gl, rng, B), prec)
+        flag(f"self_advect n={n} level={level} {prec}")
+        out = empty(B * gl.nface, prec)
+        S.stfas_op_self_advect(ctx, level, B, to_dev(v, prec), to_dev(u, prec), out)
+        ref = advect.self_advect(gl, v, dt) + dt * u * gl.interior_mask()
+        assert rel(to_np(out), ref) <= TOL[prec]
+        base = _q(_faces(gl, rng, B), prec)
+        acc = to_dev(base, prec)
+        S.stfas_op_self_advect_T(ctx, level, B, to_dev(v, prec), to_dev(y, prec), -2.5, acc)
+        ref = base - 2.5 * advect.self_advect_T(gl, v, y, dt)
+        assert rel(to_np(acc), ref) <= TOL[prec]
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", CASES)
+def test_projection_batched(n, N, prec):
+    S, ctx, g, dt, K = _ctx(n, N, prec)
+    rng = np.random.default_rng(13)
+    w = _q(_faces(g, rng, N), prec)
+    out = empty(N * g.nface, prec)
+    phi = empty(N * g.ncell, prec)
+    flag(f"project n={n} N={N} {prec}")
+    cycles = S.stfas_op_project(ctx, N, to_dev(w, prec), out, phi)
+    ref = np.stack([poisson.project(g, w[b])[0] for b in range(N)])
+    refphi = np.stack([poisson.project(g, w[b])[1] for b in range(N)])
+    tol = TOL[prec] if prec == "fp64" else 2e-5
+    assert rel(to_np(out), ref) <= tol
+    assert rel(to_np(phi), refphi) <= 10 * tol
+    assert 1 <= cycles <= 60
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_metric(prec):
+    S, ctx, g, dt, K = _ctx((24, 20), 2, prec, metric_levels=2)
+    rng = np.random.default_rng(14)
+    e = _q(rng.standard_normal(g.ncell), prec)
+    out = empty(g.ncell, prec)
+    S.stfas_op_metric(ctx, to_dev(e, prec), out)
+    assert rel(to_np(out), metric.apply_metric(g, e, 2)) <= TOL[prec]
+    ctx.destroy()
+
+
+def _state(gl, N, rng, s, prec):
+    return [_q(_faces(gl, rng, N, s), prec), _q(rng.standard_normal((N, gl.ncell)) * s, prec),
+            _q(_faces(gl, rng, N, s), prec), _q(rng.standard_normal((N, gl.ncell)) * s, prec)]
+
+
+def _dev_state(x, prec):
+    return tuple(to_dev(a, prec) for a in x)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", CASES)
+def test_kkt_residual_all_levels(n, N, prec):
+    S, ctx, g, dt, K = _ctx(n, N, prec)
+    kr = K / 1e-2
+    rng = np.random.default_rng(15)
+    for level in range(ctx.num_levels()):
+        gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
+        L = kkt.Level(gl, N, dt, kr)
+        x = _state(gl, N, rng, 0.5, prec)
+        w = _q(_faces(gl, rng, N), prec)
+        res = _state(gl, N, rng, 1.0, prec)
+        out = tuple(empty(a.size, prec) for a in res)
+        flag(f"kkt n={n} level={level} {prec}")
+        S.stfas_op_kkt_residual(ctx, level, _dev_state(x, prec), to_dev(w, prec), _dev_state(res, prec), out)
+        ref = kkt.residual(L, x, w, res)
+        for k in range(4):
+            assert rel(to_np(out[k]), ref[k]) <= TOL[prec], (level, k)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", CASES)
+def test_scgs_sweep(n, N, prec):
+    S, ctx, g, dt, K = _ctx(n, N, prec)
+    kr = K / 1e-2
+    rng = np.random.default_rng(16)
+    for level in (0, ctx.num_levels() - 1):
+        gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
+        L = kkt.Level(gl, N, dt, kr)
+        x = _state(gl, N, rng, 0.3, prec)
+        w = _q(_faces(gl, rng, N), prec)
+        res = _state(gl, N, rng, 1.0, prec) if level > 0 else None
+        xd = _dev_state(x, prec)
+        flag(f"scgs n={n} level={level} {prec}")
+        S.stfas_op_scgs_sweep(ctx, level, xd, to_dev(w, prec), _dev_state(res, prec) if res else None)
+        ref = [a.copy() for a in x]
+        scgs.sweep(L, ref, w, res if res else [np.zeros_like(a) for a in x])
+        for k in range(4):
+            assert rel(to_np(xd[k]), ref[k]) <= TOL[prec], (level, k)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", [((16, 12), 3), ((8, 8, 8), 2)])
+def test_transfers(n, N, prec):
+    S, ctx, g, dt, K = _ctx(n, N, prec)
+    rng = np.random.default_rng(17)
+    T = transfer.Transfer(g)
+    gc = T.coarse
+    xf = _state(g, N, rng, 1.0, prec)
+    xc = tuple(empty(a.size // g.nface * gc.nface if k % 2 == 0 else a.size // g.ncell * gc.ncell, prec)
+               for k, a in enumerate(xf))
+    flag(f"transfers n={n} {prec}")
+    S.stfas_op_restrict(ctx, 0, _dev_state(xf, prec), xc)
+    ref = T.restrict_state([a.copy() for a in xf])
+    for k in range(4):
+        assert rel(to_np(xc[k]), ref[k]) <= TOL[prec]
+    cs = _state(gc, N, rng, 1.0, prec)
+    fd = _dev_state(xf, prec)
+    S.stfas_op_prolong(ctx, 0, _dev_state(cs, prec), -1.0, fd)
+    pr = T.prolong_state(cs)
+    for k in range(4):
+        assert rel(to_np(fd[k]), xf[k] - pr[k]) <= TOL[prec]
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_invalid_arguments_rejected(prec):
+    from paper_1608_01102_amd import stfas as S
+    from paper_1608_01102_amd._lib import StfasError
+    S_, ctx, g, dt, K = _ctx((16, 12), 3, prec)
+    with pytest.raises(StfasError):
+        S.stfas_op_kkt_residual(ctx, 5, tuple(zeros(1 << 12, prec) for _ in range(4)), zeros(1 << 12, prec),
+                                None, tuple(zeros(1 << 12, prec) for _ in range(4)))
+    rho0 = zeros(g.ncell, prec)
+    u = zeros(3 * g.nface, prec)
+    for bad in ([0], [4], [2, 2], [3, 1]):
+        with pytest.raises(StfasError):
+            S.stfas_solve(ctx, rho0, bad, zeros(len(bad) * g.ncell, prec), u)
+    ctx.destroy()

@@ -1,0 +1,131 @@
+"""Parity of the composite stages (velocity subproblem, density subproblem,
+full ADMM solve, simulation step and its adjoint) with the FP64 oracle,
+through the C interface, with identical control flow (fixed counts)."""
+import numpy as np
+import pytest
+
+import synthetic
+from gpu_common import TOL, empty, flag, rel, to_dev, to_np, zeros
+from oracle import admm, ao, kkt, step, stfas
+from oracle.grid import Grid
+
+pytestmark = pytest.mark.gpu
+
+
+def _q(x, prec):
+    return np.asarray(x, dtype=np.float32).astype(np.float64) if prec == "mixed" else np.asarray(x)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,N", [((16, 16), 4), ((8, 8, 8), 3)])
+def test_nso_vcycles(n, N, prec):
+    from paper_1608_01102_amd import stfas as S
+    g = Grid(n)
+    dt, r = g.h, 1e-2
+    K = r / dt ** 2
+    prob = S.make_problem(n, N, r, dt=dt, K=K, max_vcycles=3, fixed_counts=True, precision=prec)
+    ctx = S.stfas_create(prob)
+    rng = np.random.default_rng(21)
+    w = _q(np.stack([synthetic.curl_noise_velocity(n, rng, 1.0, 0.8) for _ in range(N)]), prec)
+    x = [np.zeros((N, g.nface)), np.zeros((N, g.ncell)), np.zeros((N, g.nface)), np.zeros((N, g.ncell))]
+    xd = tuple(to_dev(a, prec) for a in x)
+    flag(f"nso n={n} N={N} {prec}")
+    nv, hist = S.stfas_op_nso(ctx, xd, to_dev(w, prec))
+    H = stfas.Hierarchy(g, N, dt, K / r)
+    nv_ref, hist_ref = stfas.nso(H, x, w, max_vcycles=3, fixed_counts=True)
+    assert nv == nv_ref == 3
+    for k in range(4):
+        assert rel(to_np(xd[k]), x[k]) <= TOL[prec] * (1 if prec == "fp64" else 10), k
+    assert np.allclose(hist, hist_ref, rtol=1e-8 if prec == "fp64" else 1e-2)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_density_subproblem(prec):
+    from paper_1608_01102_amd import stfas as S
+    w = synthetic.c1_plain_2d_32(3)
+    g = Grid(w["n"])
+    N, dt, r = w["num_steps"], w["dt"], w["r"]
+    K = r / dt ** 2
+    prob = S.make_problem(w["n"], N, r, dt=dt, K=K, ao_iters=2, metric_levels=3, precision=prec)
+    ctx = S.stfas_create(prob)
+    rng = np.random.default_rng(22)
+    vt = _q(np.stack([synthetic.curl_noise_velocity(w["n"], rng, 2.0, 0.5) for _ in range(N)]), prec)
+    rho0 = _q(w["rho0"], prec)
+    keys = {t: _q(v, prec) for t, v in w["keys"].items()}
+    ks = sorted(keys)
+    vs = empty(N * g.nface, prec)
+    rho = empty((N + 1) * g.ncell, prec)
+    flag(f"ao c1-shape {prec}")
+    hist = S.stfas_op_ao(ctx, to_dev(rho0, prec), ks, to_dev(np.stack([keys[k] for k in ks]), prec),
+                         to_dev(vt, prec), vs, rho)
+    vs_ref, rho_ref, hist_ref = ao.solve(g, rho0, keys, vt, K, dt, 3, iters=2)
+    tol = TOL[prec] if prec == "fp64" else 1e-3
+    assert rel(to_np(vs), vs_ref) <= tol
+    assert rel(to_np(rho), rho_ref) <= tol
+    assert np.allclose(hist, hist_ref, rtol=1e-9 if prec == "fp64" else 1e-4)
+    assert all(hist[i + 1] <= hist[i] for i in range(len(hist) - 1))
+    ctx.destroy()
+
+
+def _solve_pair(w, prec, max_admm, max_vcycles, **kw):
+    from paper_1608_01102_amd import stfas as S
+    g = Grid(w["n"])
+    N = w["num_steps"]
+    args = dict(n=w["n"], num_steps=N, r=w["r"], dt=w["dt"], max_admm=max_admm, max_vcycles=max_vcycles,
+                fixed_counts=True, **kw)
+    prob = S.make_problem(precision=prec, **args)
+    ctx = S.stfas_create(prob)
+    rho0 = _q(w["rho0"], prec)
+    keys = {t: _q(v, prec) for t, v in w["keys"].items()}
+    ks = sorted(keys)
+    u = empty(N * g.nface, prec)
+    flag(f"solve n={w['n']} N={N} {prec} admm={max_admm} vc={max_vcycles}")
+    st = S.stfas_solve(ctx, to_dev(rho0, prec), ks, to_dev(np.stack([keys[k] for k in ks]), prec), u)
+    ref = admm.solve(admm.Problem(**args), rho0, keys)
+    ctx.destroy()
+    return to_np(u).reshape(N, -1), st, ref
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_small(prec):
+    w = synthetic.small_problem((8, 8), 4, seed=0, r=1e-2)
+    u, st, ref = _solve_pair(w, prec, 3, 3)
+    tol = TOL[prec] if prec == "fp64" else 1e-3
+    assert rel(u, ref.u) <= tol
+    assert abs(st["objective"] - ref.objective) <= tol * ref.objective
+    assert st["admm_iters"] == ref.admm_iters and st["vcycles"] == ref.vcycles
+
+
+def test_solve_c1_fp64():
+    """The 32x32x10 workload (FP64), two ADMM iterations of four V-cycles."""
+    w = synthetic.c1_plain_2d_32(0)
+    u, st, ref = _solve_pair(w, "fp64", 2, 4)
+    assert rel(u, ref.u) <= 1e-10
+    assert abs(st["objective"] - ref.objective) <= 1e-10 * ref.objective
+    assert abs(st["reg_term"] - ref.reg_term) <= 1e-10 * ref.reg_term
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [(16, 12), (8, 8, 8)])
+def test_step_forward_backward(n, prec):
+    from paper_1608_01102_amd import stfas as S
+    g = Grid(n)
+    dt = 0.9 * g.h
+    prob = S.make_problem(n, 1, 1.0, dt=dt, precision=prec)
+    rng = np.random.default_rng(23)
+    rho = _q(synthetic.smooth_noise_density(n, rng, 1.0), prec)
+    v = _q(synthetic.curl_noise_velocity(n, rng, 1.0, 1.5, dt / g.h), prec)
+    u = _q(synthetic.random_faces(n, rng, 2.0), prec)
+    ro, vo, po = empty(g.ncell, prec), empty(g.nface, prec), empty(g.ncell, prec)
+    flag(f"step n={n} {prec}")
+    S.stfas_step_forward(prob, to_dev(rho, prec), to_dev(v, prec), to_dev(u, prec), ro, vo, po)
+    rr, vr, pr = step.step_forward(g, rho, v, u, dt)
+    tol = TOL[prec] if prec == "fp64" else 2e-5
+    assert rel(to_np(ro), rr) <= tol and rel(to_np(vo), vr) <= tol and rel(to_np(po), pr) <= 10 * tol
+    grn = _q(rng.standard_normal(g.ncell), prec)
+    gvn = _q(synthetic.random_faces(n, rng), prec)
+    gr, gv, gu = empty(g.ncell, prec), empty(g.nface, prec), empty(g.nface, prec)
+    S.stfas_step_backward(prob, to_dev(rho, prec), to_dev(v, prec), to_dev(grn, prec), to_dev(gvn, prec), gr, gv, gu)
+    a, b, c = step.step_backward(g, rho, v, grn, gvn, dt)
+    assert rel(to_np(gr), a) <= tol and rel(to_np(gv), b) <= tol and rel(to_np(gu), c) <= tol

@@ -1,0 +1,59 @@
+"""CPU checks of the C interface: the library loads, exports every function
+the headers declare, and validates problems without a device."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(stfas_[a-zA-Z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_function():
+    from paper_1608_01102_amd import _lib
+    lib = _lib.load()
+    declared = _declared()
+    assert len(declared) >= 20
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_lib.EXPORTED) == declared
+
+
+def test_workspace_bytes_and_validation():
+    from paper_1608_01102_amd import stfas as S
+    ok = S.make_problem((32, 32), 10, 1e-3)
+    b = S.stfas_workspace_bytes(ok)
+    assert b > 0
+    # more steps -> more memory, and 3D footprint within the paper's bound
+    # M = 8 n^d (1+d) N values (memory analysis of Sec. 5) times the word size
+    assert S.stfas_workspace_bytes(S.make_problem((32, 32), 20, 1e-3)) > b
+    p3 = S.make_problem((64, 64, 64), 60, 1e-3, precision="mixed")
+    b3 = S.stfas_workspace_bytes(p3)
+    assert 0 < b3 < 2 * (4 * 8 * 64 ** 3 * 4 * 60)
+    bad = [S.make_problem((2, 32), 10, 1e-3), S.make_problem((32, 32), 0, 1e-3), S.make_problem((32, 32), 10, 0.0),
+           S.make_problem((32, 32), 10, -1.0), S.make_problem((33, 33), 4, 1.0)]
+    bad[-1].dim = 4
+    for p in bad:
+        assert S.stfas_workspace_bytes(p) == 0
+    # a grid whose coarsest Poisson level would be too large for the dense solve
+    assert S.stfas_workspace_bytes(S.make_problem((97, 97), 2, 1.0)) == 0
+    assert S.stfas_step_work_bytes(S.make_problem((128, 128, 128), 1, 1.0, precision="mixed")) > 0
+    assert S.stfas_step_vcycles(ok) > 0
+
+
+def test_status_strings():
+    from paper_1608_01102_amd import _lib
+    lib = _lib.load()
+    assert lib.stfas_status_string(1) == b"invalid argument"
+    assert b"gfx950" in lib.stfas_build_info()
