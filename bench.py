@@ -1,0 +1,168 @@
+"""Benchmark: the STFAS keyframe smoke-control solve on one MI355X.
+
+One step = one full solve (ADMM with density and velocity subproblems,
+then the re-simulated outputs) of the 128x128, 40-step 2D workload in the
+mixed-precision form (FP32 bulk, FP64 coarsest projection level and
+reductions), regularisation 1e-4, ADMM stopped at 1e-4 * max(rho_0)
+visual difference or 50 iterations.  Inputs are synthetic and seeded
+(a blurred disk to a union of strokes), already resident on the device.
+
+Prints one JSON line (see the design doc for every field)."""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--max-admm", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-check", action="store_true")
+    ap.add_argument("--trace-kernel", default="scgs_thomas",
+                    help="kernel family whose launches on the finest level are timed with HIP events")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only (the solve is not sharded across GPUs); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_1608_01102_amd import stfas as S
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synthetic.c2_plain_2d_128(args.seed)
+    n, N = w["n"], w["num_steps"]
+    rho_max = float(np.max(w["rho0"]))
+    kw = dict(dt=w["dt"], eps_admm=1e-4 * rho_max, max_admm=args.max_admm)
+    prob = S.make_problem(n, N, w["r"], precision="mixed", **kw)
+    ctx = S.stfas_create(prob)
+    ks = sorted(w["keys"])
+    rho0 = torch.tensor(w["rho0"], dtype=torch.float32, device=dev)
+    keys = torch.tensor(np.stack([w["keys"][k] for k in ks]), dtype=torch.float32, device=dev)
+    u = torch.zeros(N * ctx.faces, dtype=torch.float32, device=dev)
+
+    for _ in range(args.warmup):
+        S.stfas_solve(ctx, rho0, ks, keys, u)
+    torch.cuda.synchronize()
+    S.stfas_trace_enable(ctx, args.trace_kernel, 8192)
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(S.stfas_solve(ctx, rho0, ks, keys, u))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    nlaunch, tms, tbytes = S.stfas_trace_read(ctx)
+    S.stfas_trace_enable(ctx, 0, 0)
+    vcycles = sum(s["vcycles"] for s in stats) / len(stats)
+    cells = n[0] * n[1]
+    value = cells * N * vcycles / (ms * 1e-3)
+    last = stats[-1]
+    out = {
+        "metric": "KKT solve s to 1e-4 keyframe err; spacetime cell-upd/s; serve p50/p99",
+        "value": value,
+        "unit": "spacetime cell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "2D 128x128 MAC grid, 40 steps, r=1e-4, stroke keyframe at t=40 (mixed precision)",
+                   "grid": list(n), "num_steps": N, "precision": "mixed", "parallelism": "single GPU"},
+        "solve_s": ms * 1e-3,
+        "admm_iters": last["admm_iters"], "vcycles": last["vcycles"], "converged": bool(last["converged"]),
+        "objective": last["objective"], "kkt_res_inf": last["kkt_res_inf"], "visual_diff": last["visual_diff"],
+    }
+    if nlaunch:
+        avg_us = tms * 1e3 / nlaunch
+        achieved = tbytes / (tms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": args.trace_kernel, "achieved": achieved, "peak": 8000.0,
+                           "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
+                           "avg_launch_us": avg_us, "launches_timed": nlaunch,
+                           "alg_bytes_per_launch": tbytes / nlaunch}
+    u_mixed = u.double().cpu().numpy()
+    if not args.no_fp64_check:
+        # same solve in FP64 on the GPU (untimed): the mixed form's keyframe error against it
+        p64 = S.make_problem(n, N, w["r"], precision="fp64", **kw)
+        c64 = S.stfas_create(p64)
+        u64 = torch.zeros(N * ctx.faces, dtype=torch.float64, device=dev)
+        s64 = S.stfas_solve(c64, rho0.double(), ks, keys.double(), u64)
+        kf = keyframe_error(S, p64, w, u_mixed, u64.cpu().numpy())
+        out["fp64_gpu"] = {"objective": s64["objective"], "admm_iters": s64["admm_iters"],
+                           "seconds": s64["seconds"], "kf_err_mixed_vs_fp64": kf}
+        c64.destroy()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    ctx.destroy()
+    print(json.dumps(out), flush=True)
+
+
+def keyframe_error(S, p64, w, u_a, u_b):
+    """max over keyframes of |rho_a - rho_b| / |rho_b| after re-simulating both
+    control sequences with the FP64 step of the library."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    N = w["num_steps"]
+    cells, faces = S.counts(p64)
+    work = torch.empty(S.stfas_step_work_bytes(p64), dtype=torch.uint8, device=dev)
+
+    def run(u):
+        ut = torch.tensor(u.reshape(N, faces), dtype=torch.float64, device=dev)
+        rho = torch.tensor(w["rho0"], dtype=torch.float64, device=dev)
+        v = torch.zeros(faces, dtype=torch.float64, device=dev)
+        out = {}
+        for i in range(N):
+            rn, vn = torch.empty_like(rho), torch.empty_like(v)
+            S.stfas_step_forward(p64, rho, v, ut[i], rn, vn, work=work)
+            rho, v = rn, vn
+            if i + 1 in w["keys"]:
+                out[i + 1] = rho.cpu().numpy()
+        return out
+    a, b = run(u_a), run(u_b)
+    return max(float(np.linalg.norm(a[t] - b[t]) / np.linalg.norm(b[t])) for t in b)
+
+
+def cpu_baseline(w):
+    """The FP64 oracle timed on this host: one FAS V-cycle on the same 128x128
+    grid restricted to the first 10 of the 40 steps (same operators and
+    levels; per-step cost is uniform, so the rate scales)."""
+    import numpy as np
+    import synthetic
+    from oracle import kkt, stfas
+    from oracle.grid import Grid
+    n = w["n"]
+    Ns = 10
+    g = Grid(n)
+    dt, r = w["dt"], w["r"]
+    K = r / dt ** 2
+    H = stfas.Hierarchy(g, Ns, dt, K / r)
+    rng = np.random.default_rng(0)
+    tw = np.stack([synthetic.curl_noise_velocity(n, rng, 4.0, 0.5) for _ in range(Ns)])
+    x = kkt.zeros_state(H.levels[0])
+    ws = H.targets(tw)
+    res = [np.zeros_like(a) for a in x]
+    t0 = time.perf_counter()
+    stfas.vcycle(H, 0, x, ws, res)
+    t = time.perf_counter() - t0
+    return {"value": n[0] * n[1] * Ns / t, "unit": "spacetime cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 oracle V-cycle on 128x128 x {Ns} steps ({t:.1f} s, NumPy, single thread)",
+            "host_cpus": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

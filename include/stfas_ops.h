@@ -99,6 +99,20 @@ stfas_status stfas_op_nso(stfas_ctx* ctx, stfas_state x, const void* w, int32_t*
 stfas_status stfas_op_ao(stfas_ctx* ctx, const void* rho0, int32_t num_key, const int32_t* key_steps,
                          const void* key_rho, const void* vt, void* vstar, void* rho, double* phi_hist);
 
+/* Event tracing of one kernel family (for roofline measurements): after
+ * stfas_trace_enable(ctx, kernel, max_launches), up to max_launches
+ * launches of that family on the finest level (level 0) made by later
+ * calls on this context are
+ * bracketed by HIP events on the context's stream, and the algorithmic
+ * bytes each launch must move (its inputs and outputs once) are summed.
+ * kernel = 0 disables tracing.  Families: 1 SCGS recurrence, 2 SCGS
+ * projection, 3 KKT face rows, 4 velocity-advection transpose, 5 Poisson
+ * red-black sweep, 6 density advection, 7 KKT cell rows, 8 SCGS pressure.
+ * stfas_trace_read synchronises and returns the recorded launch count,
+ * their summed duration in milliseconds and their algorithmic bytes. */
+stfas_status stfas_trace_enable(stfas_ctx* ctx, int32_t kernel, int32_t max_launches);
+stfas_status stfas_trace_read(stfas_ctx* ctx, int64_t* launches, double* total_ms, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,6 +71,9 @@ _SIGS = {
     "stfas_op_nso": (c_int32, [c_void_p, StfasState, c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
     "stfas_op_ao": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.POINTER(c_int32), c_void_p, c_void_p, c_void_p,
                               c_void_p, ctypes.POINTER(c_double)]),
+    "stfas_trace_enable": (c_int32, [c_void_p, c_int32, c_int32]),
+    "stfas_trace_read": (c_int32, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_double),
+                                   ctypes.POINTER(c_double)]),
 }
 
 EXPORTED = tuple(_SIGS)

@@ -99,6 +99,35 @@ __device__ inline Axis<T> locate(T y, int M) {
     return s;
 }
 
+// The same axis for a backtrace Y = X + delta from an integer node X.  The
+// base cell and the fraction come from delta alone (floor(X + delta) =
+// X + floor(delta)), which keeps the fraction accurate in FP32 where X is
+// large and delta small.  Identical to locate(X + delta, M) in exact
+// arithmetic, including the clamp and its derivative on the closed box.
+template <typename T>
+__device__ inline Axis<T> locate_disp(int X, T delta, int M) {
+    Axis<T> s;
+    const T lim = (T)(2 * M + 2);
+    const T d = fmin(fmax(delta, -lim), lim);      // also maps NaN to -lim
+    const T fl = floor(d);
+    int i = X + (int)fl;
+    T t = d - fl;
+    if (i < 0) {                                    // Y < 0: clamped to node 0
+        s.i0 = 0;
+        s.t = (T)0;
+        s.in = (T)0;
+    } else if (i >= M - 1) {                        // Y >= M-1: clamped to the top node
+        s.i0 = M - 2;
+        s.t = (T)1;
+        s.in = (i == M - 1 && t == (T)0) ? (T)1 : (T)0;
+    } else {
+        s.i0 = i;
+        s.t = t;
+        s.in = (T)1;
+    }
+    return s;
+}
+
 // Lattice with extents ex, ey (ez implied) and x-fastest strides.
 template <typename T, int D>
 struct Interp {
@@ -110,6 +139,16 @@ struct Interp {
         ax[0] = locate<T>(y[0], ex);
         ax[1] = locate<T>(y[1], ey);
         if (D == 3) ax[2] = locate<T>(y[2], ez);
+        sy = ex;
+        sz = ex * ey;
+        base = ax[0].i0 + ax[1].i0 * sy + (D == 3 ? ax[2].i0 * sz : 0);
+    }
+
+    // Backtrace from integer node X by displacement delta (see locate_disp).
+    __device__ inline void setup_disp(const int* X, const T* delta, int ex, int ey, int ez) {
+        ax[0] = locate_disp<T>(X[0], delta[0], ex);
+        ax[1] = locate_disp<T>(X[1], delta[1], ey);
+        if (D == 3) ax[2] = locate_disp<T>(X[2], delta[2], ez);
         sy = ex;
         sz = ex * ey;
         base = ax[0].i0 + ax[1].i0 * sy + (D == 3 ? ax[2].i0 * sz : 0);

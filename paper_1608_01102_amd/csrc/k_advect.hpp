@@ -52,9 +52,9 @@ __global__ void k_advect(Grid g, T cfl, const T* __restrict__ rho, const T* __re
     const int i = c % g.n[0], j = (c / g.n[0]) % g.n[1], k = c / (g.n[0] * g.n[1]);
     const int idx[3] = {i, j, k};
     T y[3];
-    for (int a = 0; a < D; ++a) y[a] = (T)idx[a] - cfl * vbar(g, v, a, i, j, k);
+    for (int a = 0; a < D; ++a) y[a] = -cfl * vbar(g, v, a, i, j, k);
     Interp<T, D> it;
-    it.setup(y, g.n[0], g.n[1], g.n[2]);
+    it.setup_disp(idx, y, g.n[0], g.n[1], g.n[2]);
     out[c] = it.value(rho);
 }
 
@@ -72,9 +72,9 @@ __global__ void k_advect_T(Grid g, T cfl, const T* __restrict__ mu, const T* __r
     const int i = c % g.n[0], j = (c / g.n[0]) % g.n[1], k = c / (g.n[0] * g.n[1]);
     const int idx[3] = {i, j, k};
     T y[3];
-    for (int a = 0; a < D; ++a) y[a] = (T)idx[a] - cfl * vbar(g, v, a, i, j, k);
+    for (int a = 0; a < D; ++a) y[a] = -cfl * vbar(g, v, a, i, j, k);
     Interp<T, D> it;
-    it.setup(y, g.n[0], g.n[1], g.n[2]);
+    it.setup_disp(idx, y, g.n[0], g.n[1], g.n[2]);
 #pragma unroll
     for (int q = 0; q < (1 << D); ++q) {
         const T w = it.weight(q) * m;
@@ -110,9 +110,9 @@ __global__ void k_advect_dv_T(Grid g, T cfl, const T* __restrict__ mu, const T* 
         if (m == (T)0) continue;
         const int idx[3] = {ci, cj, ck};
         T y[3];
-        for (int b = 0; b < D; ++b) y[b] = (T)idx[b] - cfl * vbar(g, v, b, ci, cj, ck);
+        for (int b = 0; b < D; ++b) y[b] = -cfl * vbar(g, v, b, ci, cj, ck);
         Interp<T, D> it;
-        it.setup(y, g.n[0], g.n[1], g.n[2]);
+        it.setup_disp(idx, y, g.n[0], g.n[1], g.n[2]);
         T gr[3];
         it.grad(rho, gr);
         acc += (T)0.5 * (-cfl) * m * gr[a];
@@ -140,9 +140,9 @@ __global__ void k_self_advect(Grid g, T cfl, T dt, const T* __restrict__ v, cons
     face_velocity<T, D>(g, v, a, i, j, k, vh);
     const int idx[3] = {i, j, k};
     T y[3];
-    for (int b = 0; b < D; ++b) y[b] = (T)idx[b] - cfl * vh[b];
+    for (int b = 0; b < D; ++b) y[b] = -cfl * vh[b];
     Interp<T, D> it;
-    it.setup(y, face_ext(g, a, 0), face_ext(g, a, 1), face_ext(g, a, 2));
+    it.setup_disp(idx, y, face_ext(g, a, 0), face_ext(g, a, 1), face_ext(g, a, 2));
     T s = it.value(v + g.foff[a]);
     if (u) s += dt * u[f];
     out[f] = s;
@@ -170,10 +170,10 @@ __global__ void k_self_advect_T(Grid g, T cfl, const T* __restrict__ v, const T*
     face_velocity<T, D>(g, v, a, i, j, k, vh);
     const int idx[3] = {i, j, k};
     T yy[3];
-    for (int b = 0; b < D; ++b) yy[b] = (T)idx[b] - cfl * vh[b];
+    for (int b = 0; b < D; ++b) yy[b] = -cfl * vh[b];
     const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
     Interp<T, D> it;
-    it.setup(yy, ex, ey, ez);
+    it.setup_disp(idx, yy, ex, ey, ez);
     const T* va = v + g.foff[a];
     T* oa = out + g.foff[a];
     T gr[3];

@@ -48,9 +48,9 @@ __global__ void k_kkt_faces(Grid g, int N, T dt, T kr, T cfl, T sgn, const T* __
         face_velocity<T, D>(g, vp, a, i, jj, k, vh);
         const int idx[3] = {i, jj, k};
         T y[3];
-        for (int b = 0; b < D; ++b) y[b] = (T)idx[b] - cfl * vh[b];
+        for (int b = 0; b < D; ++b) y[b] = -cfl * vh[b];
         Interp<T, D> it;
-        it.setup(y, face_ext(g, a, 0), face_ext(g, a, 1), face_ext(g, a, 2));
+        it.setup_disp(idx, y, face_ext(g, a, 0), face_ext(g, a, 1), face_ext(g, a, 2));
         s = it.value(vp + g.foff[a]);
     }
     const T f3 = (v[e] - s) / dt - u[e] + (p[j * C + c] - p[j * C + cm]) * ih;
@@ -138,47 +138,117 @@ __device__ inline void colour_cell(const ColourSet& cs, int q, int& i, int& j, i
 //   ghat^T x_k = xi_k = s_k/|g|   (s = divergence-row residual)
 // so dx_k = (T^-1 P r)_k + ghat xi_k.  T is shared by all cells: the host
 // passes its Thomas factors (sub-diagonal, c', 1/pivot).
+//
+// Two kernels: k_scgs_project forms (P r)_k for every (cell, face, block) in
+// parallel into scratch[k][cell*2d + face]; k_scgs_thomas runs the
+// recurrence per (cell, face) in place on that column and applies dx.
+
 template <typename T, int D>
-__global__ void k_scgs_faces(Grid g, int N, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ r2,
-                             const T* __restrict__ r3, const T* __restrict__ r4, T* v, T* u,
-                             const T* __restrict__ tsub, const T* __restrict__ tcp, const T* __restrict__ tinv,
-                             T* __restrict__ scratch) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nthreads = cs.total * 2 * D;
-    if (tid >= nthreads) return;
-    const int q = tid / (2 * D), s = tid % (2 * D);
+__global__ void k_scgs_project(Grid g, int N, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ r3,
+                               T* __restrict__ scratch) {
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncol = cs.total * 2 * D;
+    if (tid >= (long)ncol * 2 * N) return;
+    const int kk = (int)(tid / ncol);
+    const int col = (int)(tid % ncol);
+    const int q = col / (2 * D), s = col % (2 * D);
     int i, j, k;
     colour_cell(cs, q, i, j, k);
     CellFaces<D> cf;
     cell_faces<D>(g, i, j, k, cf);
     if (!cf.inner[s]) return;
-    const T ginv = (T)1 / sqrt((T)cf.m);        // |ghat_s| = 1/sqrt(m)
-    T gh[2 * D];
-    for (int t = 0; t < 2 * D; ++t) gh[t] = cf.inner[t] ? ((t & 1) ? ginv : -ginv) : (T)0;
+    const T ginv = (T)1 / sqrt((T)cf.m);
+    const long jo = (long)(kk >> 1) * g.nface;
+    const T* r = (kk & 1) ? r1 + jo : r3 + jo;
+    T gr = 0;
+#pragma unroll
+    for (int t = 0; t < 2 * D; ++t)
+        if (cf.inner[t]) gr += ((t & 1) ? ginv : -ginv) * r[cf.face[t]];
+    const T ghs = (s & 1) ? ginv : -ginv;
+    scratch[tid] = r[cf.face[s]] - ghs * gr;
+}
+
+// Recurrence of the face solve, one thread per (cell, face) column.  The
+// Thomas factors are staged in LDS (dynamic, 3 * 2N values) so that the
+// recurrence reads them with LDS latency; each chunk of U blocks issues its
+// loads before the dependent arithmetic.
+template <typename T, int D>
+__global__ void k_scgs_thomas(Grid g, int N, ColourSet cs, const T* __restrict__ r2, const T* __restrict__ r4, T* v,
+                              T* u, const T* __restrict__ tsub, const T* __restrict__ tcp,
+                              const T* __restrict__ tinv, T* __restrict__ scratch) {
+    extern __shared__ unsigned char smem_raw[];
+    T* tc = reinterpret_cast<T*>(smem_raw);
+    const int M = 2 * N;
+    for (int e = threadIdx.x; e < M; e += blockDim.x) {
+        tc[e] = tsub[e];
+        tc[M + e] = tinv[e];
+        tc[2 * M + e] = tcp[e];
+    }
+    __syncthreads();
+    const T* sub = tc;
+    const T* inv = tc + M;
+    const T* cp = tc + 2 * M;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncol = cs.total * 2 * D;
+    if (col >= ncol) return;
+    const int q = col / (2 * D), s = col % (2 * D);
+    int i, j, k;
+    colour_cell(cs, q, i, j, k);
+    CellFaces<D> cf;
+    cell_faces<D>(g, i, j, k, cf);
+    if (!cf.inner[s]) return;
+    const T ginv = (T)1 / sqrt((T)cf.m);
+    const T ghs = (s & 1) ? ginv : -ginv;
+    const T gn_inv = (T)g.h * ginv;             // 1/|g| = h/sqrt(m)
     const long F = g.nface, C = g.ncell;
     const int c = cell_index(g, i, j, k);
     const int own = cf.face[s];
+    T* col_p = scratch + col;
+    constexpr int U = 16;
+    // forward elimination
     T dprev = 0;
-    for (int kk = 0; kk < 2 * N; ++kk) {
-        const long jo = (long)(kk >> 1) * F;
-        const T* r = (kk & 1) ? r1 + jo : r3 + jo;
-        T gr = 0;
-        for (int t = 0; t < 2 * D; ++t)
-            if (cf.inner[t]) gr += gh[t] * r[cf.face[t]];
-        const T pr = r[own] - gh[s] * gr;
-        const T d = (pr - tsub[kk] * dprev) * tinv[kk];
-        scratch[(long)kk * nthreads + tid] = d;
-        dprev = d;
+    int k0 = 0;
+    for (; k0 + U <= M; k0 += U) {
+        T buf[U];
+#pragma unroll
+        for (int t = 0; t < U; ++t) buf[t] = col_p[(long)(k0 + t) * ncol];
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            dprev = (buf[t] - sub[k0 + t] * dprev) * inv[k0 + t];
+            buf[t] = dprev;
+        }
+#pragma unroll
+        for (int t = 0; t < U; ++t) col_p[(long)(k0 + t) * ncol] = buf[t];
     }
-    const T gn_inv = (T)g.h * ginv;             // 1/|g| = h/sqrt(m)
+    for (; k0 < M; ++k0) {
+        dprev = (col_p[(long)k0 * ncol] - sub[k0] * dprev) * inv[k0];
+        col_p[(long)k0 * ncol] = dprev;
+    }
+    // back substitution and update (blocks M-1 down to 0)
     T x = 0;
-    for (int kk = 2 * N - 1; kk >= 0; --kk) {
-        x = scratch[(long)kk * nthreads + tid] - tcp[kk] * x;
-        const long jj = kk >> 1;
-        const T sk = (kk & 1) ? r2[jj * C + c] : r4[jj * C + c];
-        const T dx = x + gh[s] * sk * gn_inv;
-        T* fld = (kk & 1) ? v : u;
-        fld[jj * F + own] += dx;
+    int k1 = M - 1;
+    for (; k1 - (U - 1) >= 0; k1 -= U) {
+        T buf[U], sk[U], fv[U];
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int kk = k1 - t;
+            const long jj = kk >> 1;
+            buf[t] = col_p[(long)kk * ncol];
+            sk[t] = (kk & 1) ? r2[jj * C + c] : r4[jj * C + c];
+            fv[t] = ((kk & 1) ? v : u)[jj * F + own];
+        }
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int kk = k1 - t;
+            x = buf[t] - cp[kk] * x;
+            ((kk & 1) ? v : u)[(long)(kk >> 1) * F + own] = fv[t] + x + ghs * sk[t] * gn_inv;
+        }
+    }
+    for (; k1 >= 0; --k1) {
+        const long jj = k1 >> 1;
+        x = col_p[(long)k1 * ncol] - cp[k1] * x;
+        const T sk = (k1 & 1) ? r2[jj * C + c] : r4[jj * C + c];
+        ((k1 & 1) ? v : u)[jj * F + own] += x + ghs * sk * gn_inv;
     }
 }
 

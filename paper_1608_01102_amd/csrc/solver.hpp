@@ -74,7 +74,8 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     for (int a = 0; a < o.dim; ++a)
         if (o.n[a] < 4 || o.n[a] > (1 << 14)) return false;
     if (o.dim == 2 && p->n[2] > 1) return false;
-    if (p->num_steps < 1 || p->num_steps > 100000) return false;
+    // the SCGS recurrence stages 3 * 2N temporal factors in 64 KB of LDS
+    if (p->num_steps < 1 || p->num_steps > 1024) return false;
     if (!(p->r > 0) || !std::isfinite(p->r)) return false;
     if (p->precision != STFAS_FP64 && p->precision != STFAS_MIXED) return false;
     o.N = p->num_steps;
@@ -312,6 +313,53 @@ struct Poisson {
     }
 };
 
+// Event tracing of one kernel family: when enabled, launches of that
+// family on the finest level are bracketed by events on the context's
+// stream (up to `cap` launches per enable) and their algorithmic bytes are
+// summed on the host.
+enum TraceKernel {
+    TR_NONE = 0,
+    TR_SCGS_THOMAS = 1,
+    TR_SCGS_PROJECT = 2,
+    TR_KKT_FACES = 3,
+    TR_SELF_ADVECT_T = 4,
+    TR_RBGS = 5,
+    TR_ADVECT = 6,
+    TR_KKT_CELLS = 7,
+    TR_SCGS_CELLS = 8
+};
+
+struct Tracer {
+    int id = TR_NONE;
+    int cap = 0, used = 0;
+    long launches = 0;
+    double bytes = 0;
+    std::vector<hipEvent_t> ev;
+    bool on(int k) const { return id == k && used < cap; }
+    void reset() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        id = TR_NONE;
+        cap = used = 0;
+        launches = 0;
+        bytes = 0;
+    }
+};
+
+template <typename Launch>
+inline void traced(Tracer& tr, hipStream_t st, int kind, double bytes, Launch&& launch) {
+    if (!tr.on(kind)) {
+        launch();
+        return;
+    }
+    HCK(hipEventRecord(tr.ev[2 * tr.used], st));
+    launch();
+    HCK(hipEventRecord(tr.ev[2 * tr.used + 1], st));
+    ++tr.used;
+    ++tr.launches;
+    tr.bytes += bytes;
+}
+
 class SolverBase {
 public:
     virtual ~SolverBase() {}
@@ -339,6 +387,28 @@ public:
     virtual void op_prolong(int, stfas_state, double, stfas_state) = 0;
     virtual int op_nso(stfas_state, const void*, double*) = 0;
     virtual void op_ao(const void*, int, const int*, const void*, const void*, void*, void*, double*) = 0;
+    Tracer tr;
+    void trace_enable(int kind, int cap) {
+        tr.reset();
+        if (kind == TR_NONE || cap <= 0) return;
+        tr.ev.resize(2 * (size_t)cap);
+        for (auto& e : tr.ev) HCK(hipEventCreate(&e));
+        tr.id = kind;
+        tr.cap = cap;
+    }
+    // launches, total milliseconds, algorithmic bytes of the recorded launches
+    void trace_read(long* n, double* ms, double* bytes) {
+        double tot = 0;
+        for (int q = 0; q < tr.used; ++q) {
+            HCK(hipEventSynchronize(tr.ev[2 * q + 1]));
+            float t = 0;
+            HCK(hipEventElapsedTime(&t, tr.ev[2 * q], tr.ev[2 * q + 1]));
+            tot += t;
+        }
+        *n = tr.launches;
+        *ms = tot;
+        *bytes = tr.bytes;
+    }
 };
 
 template <typename T, int D>
@@ -571,10 +641,21 @@ public:
              const T* s3, const T* s4, T* o1, T* o2, T* o3, T* o4, T sgn) {
         const Grid& g = L[l];
         const T dt = (T)P.dt;
-        k_kkt_faces<T, D><<<dim3(blocks_for(g.nface, BS), N), BS, 0, st>>>(g, N, dt, (T)(P.K / P.r), cfl(l), sgn, v, pb,
-                                                                          u, p, w, s1, s3, o1, o3);
-        k_kkt_cells<T, D><<<dim3(blocks_for(g.ncell, BS), N), BS, 0, st>>>(g, sgn, v, u, s2, s4, o2, o4);
-        if (N > 1) self_advect_T(l, v, u + g.nface, (T)(-sgn / dt), o1, N - 1);
+        const double sz = sizeof(T);
+        const double fslots = (double)g.nface * N, cslots = (double)g.ncell * N;
+        // faces: v, v_{i-1} (for S), u, w, out1, out3 (+ res1, res3) per face; pbar, p per cell
+        traced(tr, st, l == 0 ? TR_KKT_FACES : TR_NONE, sz * (fslots * (6 + (s1 ? 2 : 0)) + cslots * 2), [&] {
+            k_kkt_faces<T, D><<<dim3(blocks_for(g.nface, BS), N), BS, 0, st>>>(g, N, dt, (T)(P.K / P.r), cfl(l), sgn,
+                                                                              v, pb, u, p, w, s1, s3, o1, o3);
+        });
+        traced(tr, st, l == 0 ? TR_KKT_CELLS : TR_NONE, sz * (fslots * 2 + cslots * (2 + (s2 ? 2 : 0))), [&] {
+            k_kkt_cells<T, D><<<dim3(blocks_for(g.ncell, BS), N), BS, 0, st>>>(g, sgn, v, u, s2, s4, o2, o4);
+        });
+        if (N > 1) {
+            // v, y read, out read-modify-write, per face
+            traced(tr, st, l == 0 ? TR_SELF_ADVECT_T : TR_NONE, sz * (double)g.nface * (N - 1) * 4,
+                   [&] { self_advect_T(l, v, u + g.nface, (T)(-sgn / dt), o1, N - 1); });
+        }
     }
     void kkt_level(int l, bool fas_rhs) {
         Lev& q = lev[l];
@@ -584,6 +665,23 @@ public:
             kkt(l, q.v, q.pb, q.u, q.p, q.w, q.s1, q.s2, q.s3, q.s4, q.r1, q.r2, q.r3, q.r4, (T)-1);
     }
 
+    // Interior face slots of the cells of one colour (sum of m over cells).
+    static long colour_inner_faces(const Grid& g, int colour) {
+        const ColourSet cs = colour_set(g, colour);
+        long tot = 0;
+        for (int a = 0; a < g.dim; ++a) {
+            long lo = 0, hi = 0;
+            for (int c = 0; c < cs.cnt[a]; ++c) {
+                const int idx = 2 * c + cs.p[a];
+                lo += idx >= 1;
+                hi += idx + 1 <= g.n[a] - 1;
+            }
+            const long other = (long)cs.total / cs.cnt[a];
+            tot += (lo + hi) * other;
+        }
+        return tot;
+    }
+
     void sweep(int l) {
         const Grid& g = L[l];
         Lev& q = lev[l];
@@ -591,11 +689,23 @@ public:
             kkt_level(l, false);
             const ColourSet cs = colour_set(g, colour);
             const int nf = cs.total * 2 * D;
-            k_scgs_faces<T, D><<<blocks_for(nf, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r2, q.r3, q.r4, q.v, q.u, t_sub,
-                                                                 t_cp, t_inv, scgs_scratch);
+            const double inner = (double)colour_inner_faces(g, colour);
+            const double sz = sizeof(T), M2 = 2.0 * N;
+            // project: read r1/r3 at the colour's faces, write (P r)
+            traced(tr, st, l == 0 ? TR_SCGS_PROJECT : TR_NONE, sz * M2 * inner * 2, [&] {
+                k_scgs_project<T, D><<<blocks_for((long)nf * 2 * N, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r3,
+                                                                                      scgs_scratch);
+            });
+            // thomas: read (P r), read the cells' divergence residual, update u/v at the faces
+            traced(tr, st, l == 0 ? TR_SCGS_THOMAS : TR_NONE, sz * M2 * (inner * 3 + cs.total), [&] {
+                k_scgs_thomas<T, D><<<blocks_for(nf, 64), 64, 3 * 2 * N * sizeof(T), st>>>(
+                    g, N, cs, q.r2, q.r4, q.v, q.u, t_sub, t_cp, t_inv, scgs_scratch);
+            });
             const int nc = cs.total * 2 * N;
-            k_scgs_cells<T, D><<<blocks_for(nc, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r2, q.r3, q.r4, q.pb, q.p, t_diag,
-                                                                 t_sub, t_sup);
+            traced(tr, st, l == 0 ? TR_SCGS_CELLS : TR_NONE, sz * M2 * (inner + cs.total * 3), [&] {
+                k_scgs_cells<T, D><<<blocks_for(nc, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r2, q.r3, q.r4, q.pb, q.p,
+                                                                     t_diag, t_sub, t_sup);
+            });
         }
     }
 

@@ -370,4 +370,24 @@ stfas_status stfas_op_ao(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
     });
 }
 
+stfas_status stfas_trace_enable(stfas_ctx* ctx, int32_t kernel, int32_t max_launches) {
+    if (!ctx || kernel < 0 || kernel > TR_SCGS_CELLS || max_launches < 0 || max_launches > (1 << 20))
+        return STFAS_E_INVALID;
+    return guard([&]() -> stfas_status {
+        HCK(hipStreamSynchronize(ctx->s->st));
+        ctx->s->trace_enable(kernel, max_launches);
+        return STFAS_OK;
+    });
+}
+
+stfas_status stfas_trace_read(stfas_ctx* ctx, int64_t* launches, double* total_ms, double* bytes) {
+    if (!ctx || !launches || !total_ms || !bytes) return STFAS_E_INVALID;
+    return guard([&]() -> stfas_status {
+        long n = 0;
+        ctx->s->trace_read(&n, total_ms, bytes);
+        *launches = n;
+        return STFAS_OK;
+    });
+}
+
 }  // extern "C"

@@ -267,3 +267,20 @@ def stfas_op_ao(ctx, rho0, key_steps, key_rho, vt, vstar, rho):
                                   _ptr(vt, ctx.dtype, N * f, "vt"), _ptr(vstar, ctx.dtype, N * f, "vstar"),
                                   _ptr(rho, ctx.dtype, (N + 1) * c, "rho"), hist), "stfas_op_ao")
     return list(hist)
+
+
+TRACE_KERNELS = {"scgs_thomas": 1, "scgs_project": 2, "kkt_faces": 3, "self_advect_T": 4, "rbgs": 5, "advect": 6,
+                 "kkt_cells": 7, "scgs_cells": 8}
+
+
+def stfas_trace_enable(ctx, kernel, max_launches=4096):
+    k = TRACE_KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    check(_lib.load().stfas_trace_enable(ctx.handle, k, int(max_launches)), "stfas_trace_enable")
+
+
+def stfas_trace_read(ctx):
+    """(launches, total_ms, algorithmic_bytes) of the traced kernel family."""
+    n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    check(_lib.load().stfas_trace_read(ctx.handle, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)),
+          "stfas_trace_read")
+    return n.value, ms.value, b.value

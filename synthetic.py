@@ -146,8 +146,10 @@ def random_faces(n, rng, scale=1.0):
 def curl_noise_velocity(n, rng, sigma=4.0, max_cells_per_step=2.0, dt_over_h=1.0):
     """Divergence-free MAC velocity: the discrete curl of a blurred random
     potential that vanishes on the boundary.  2D: scalar stream function at
-    nodes; 3D: vector potential on edges.  Scaled so max|v| dt/h equals
-    max_cells_per_step."""
+    nodes; 3D: vector potential on edges.  Scaled so max|v| dt/h is just
+    below max_cells_per_step (by 2^-10 relative), so that no backtrace of
+    the fastest face starts exactly on a lattice node when the bound is an
+    integer."""
     d = len(n)
     if d == 2:
         n0, n1 = n
@@ -177,7 +179,7 @@ def curl_noise_velocity(n, rng, sigma=4.0, max_cells_per_step=2.0, dt_over_h=1.0
     flat = np.concatenate([p.ravel() for p in parts])
     m = np.max(np.abs(flat))
     if m > 0:
-        flat = flat * (max_cells_per_step / (m * dt_over_h))
+        flat = flat * ((1.0 - 2.0 ** -10) * max_cells_per_step / (m * dt_over_h))
     return flat
 
 

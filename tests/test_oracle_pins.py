@@ -244,6 +244,28 @@ def test_step_adjoint_matches_fd(n, rng):
         assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1.0)
 
 
+@pytest.mark.parametrize("n", [(12, 10), (8, 6, 7)])
+def test_step_adjoint_fd_large_cfl(n, rng):
+    """Smooth divergence-free velocity moving up to 2 cells per step (foot
+    points leave the cell and the domain)."""
+    g = Grid(n)
+    dt = g.h
+    rho = synthetic.smooth_noise_density(n, rng, 1.0)
+    v = synthetic.curl_noise_velocity(n, rng, 1.5, 2.0, 1.0)
+    u = synthetic.random_faces(n, rng, 2.0)
+    grn = rng.standard_normal(g.ncell)
+    gvn = rand_faces(g, rng)
+    g_rho, g_v, g_u = step.step_backward(g, rho, v, grn, gvn, dt)
+
+    def loss(vv):
+        rn, vn, _ = step.step_forward(g, rho, vv, u, dt)
+        return rn @ grn + vn @ gvn
+    for _ in range(4):
+        dv = rand_faces(g, rng)
+        fd = (loss(v + 1e-7 * dv) - loss(v - 1e-7 * dv)) / 2e-7
+        assert abs(fd - dv @ g_v) <= 1e-6 * abs(fd)
+
+
 # ---------------------------------------------------------------- AO
 def test_ao_gradient_fd_and_monotone(rng):
     w = synthetic.small_problem((8, 8), 4, seed=3)
