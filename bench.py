@@ -91,7 +91,8 @@ def main():
         avg_us = tms * 1e3 / nlaunch
         achieved = tbytes / (tms * 1e-3) / 1e9
         out["roofline"] = {"bound": "hbm", "kernel": args.trace_kernel, "achieved": achieved, "peak": 8000.0,
-                           "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
+                           "unit": "GB/s", "frac": achieved / 8000.0,
+                           "traffic": measured_traffic(args.trace_kernel),
                            "avg_launch_us": avg_us, "launches_timed": nlaunch,
                            "alg_bytes_per_launch": tbytes / nlaunch}
     u_mixed = u.double().cpu().numpy()
@@ -109,6 +110,23 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w)
     ctx.destroy()
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary of this kernel,
+    or None when there is none or the kernel sources changed since."""
+    from paper_1608_01102_amd.profiling import kernel_source_hash
+    path = os.path.join(ROOT, "profiles", f"{kernel}_128x128x40_pmc.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_hash"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def keyframe_error(S, p64, w, u_a, u_b):

@@ -79,6 +79,7 @@ typedef struct {
     double poisson_rtol;    /* projection relative residual; default 1e-13 (FP64) / 1e-6 (MIXED) */
     int32_t fixed_counts;   /* 1: ignore eps_*, run exactly max_admm and max_vcycles (parity mode) */
     int32_t precision;      /* stfas_precision */
+    double scgs_omega;      /* relaxation weight of the SCGS smoother (Sec. 4.3), in (0, 2]; <= 0 selects 0.7 */
 } stfas_problem;
 
 typedef struct {

@@ -14,7 +14,10 @@ Start: v, u, p, pbar, lambda = 0, rho^last_i = rho_0.
 Readings: v_0 is the given initial state (zero) and is not optimised; the
 defaults rescale the paper's parameter table to a unit domain (h = 1/n0,
 dt = 1/n0, K = r/dt^2, beta = 1, 2 AO iterations, eps_STFAS = 1e-5
-relative, eps_ADMM = max(rho_0)/100).
+relative, eps_ADMM = max(rho_0)/100); the smoother is relaxed with
+omega = 0.7 (with omega = 1 the velocity subproblem diverges once the flow
+moves about 0.7 cells per step, because the smoother's local matrix leaves
+out the advection derivative).
 
 Outputs: u from the NSO; a re-simulation from (rho_0, 0) with u; the
 objective J = 1/2 sum_k <e_k, C e_k> + r/2 sum|u_i|^2, its plain-L2 variant
@@ -44,6 +47,7 @@ class Problem:
     max_vcycles: int = 30
     metric_levels: int = -1
     fixed_counts: bool = False
+    scgs_omega: float = 0.7
 
     def resolved(self, rho0):
         p = Problem(**self.__dict__)
@@ -101,7 +105,7 @@ def solve(prob: Problem, rho0, keys):
     g = Grid(p.n)
     N = p.num_steps
     kr = p.K / p.r
-    H = stfas.Hierarchy(g, N, p.dt, kr)
+    H = stfas.Hierarchy(g, N, p.dt, kr, omega=p.scgs_omega)
     F = g.nface
     v_all = np.zeros((N, F))          # v_i, i = 0..N-1 as seen by AO (v_0 = 0)
     lam = np.zeros((N, F))

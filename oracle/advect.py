@@ -21,7 +21,7 @@ Every function accepts one field (1-D) or a batch of independent fields
 import numpy as np
 
 from .grid import Grid
-from .interp import interp, interp_grad, interp_transpose
+from .interp import Stencil, interp, interp_grad, interp_transpose
 
 
 def _batch(x):
@@ -167,8 +167,9 @@ def self_advect_T(g: Grid, v, y, dt, h=None):
         Y = _interior_positions(g, a)[None] - (dt / h) * face_velocity(g, v, a)
         yin = yparts[a][_sl(g, a, 1, n[a])]
         ya = yin.reshape(B, -1)
-        acc[a] += interp_transpose(ya, Y, ext).reshape(acc[a].shape)
-        gp = ya[..., None] * (-dt / h) * interp_grad(vparts[a].reshape(B, -1), Y, ext)
+        st = Stencil(Y, ext)
+        acc[a] += interp_transpose(ya, Y, ext, st).reshape(acc[a].shape)
+        gp = ya[..., None] * (-dt / h) * interp_grad(vparts[a].reshape(B, -1), Y, ext, st)
         for b in range(g.dim):
             comp = gp[..., b].reshape(yin.shape)
             if b == a:

@@ -19,63 +19,85 @@ import itertools
 import numpy as np
 
 
+class Stencil:
+    """Corner indices, weights and (on demand) position-derivative weights of
+    the interpolation at points Y (shape (..., d), x first)."""
+
+    def __init__(self, Y, extent):
+        d = Y.shape[-1]
+        self.d = d
+        self.i0, self.t, self.inside = [], [], []
+        for a in range(d):
+            M = extent[a]
+            y = Y[..., a]
+            yc = np.clip(y, 0.0, M - 1.0)
+            i = np.minimum(np.floor(yc), M - 2).astype(np.int64)
+            self.i0.append(i)
+            self.t.append(yc - i)
+            self.inside.append(((y >= 0.0) & (y <= M - 1.0)).astype(np.float64))
+        self.stride = [1] * d
+        for a in range(1, d):
+            self.stride[a] = self.stride[a - 1] * extent[a - 1]
+        self.bits = list(itertools.product((0, 1), repeat=d))
+        self.idx, self.w = [], []
+        fac = [(1.0 - self.t[a], self.t[a]) for a in range(d)]
+        for bits in self.bits:
+            idx = sum((self.i0[a] + bits[a]) * self.stride[a] for a in range(d))
+            w = fac[0][bits[0]]
+            for a in range(1, d):
+                w = w * fac[a][bits[a]]
+            self.idx.append(idx)
+            self.w.append(w)
+        self._fac = fac
+
+    def dweights(self):
+        """d weight / d Y_a for every corner: list of d arrays per corner."""
+        out = []
+        for bits in self.bits:
+            per = []
+            for a in range(self.d):
+                prod = self.inside[a] if bits[a] else -self.inside[a]
+                for b in range(self.d):
+                    if b != a:
+                        prod = prod * self._fac[b][bits[b]]
+                per.append(prod)
+            out.append(per)
+        return out
+
+
 def stencil(Y, extent):
-    """Corner indices (flat, within one lattice) and weights for points Y of
-    shape (..., d), x first.  Returns a list of (flat_index, weight, dweight)
-    with dweight of shape (..., d)."""
-    d = Y.shape[-1]
-    i0, t, inside = [], [], []
-    for a in range(d):
-        M = extent[a]
-        y = Y[..., a]
-        yc = np.clip(y, 0.0, M - 1.0)
-        i = np.minimum(np.floor(yc), M - 2).astype(np.int64)
-        i0.append(i)
-        t.append(yc - i)
-        inside.append(((y >= 0.0) & (y <= M - 1.0)).astype(np.float64))
-    stride = [1] * d
-    for a in range(1, d):
-        stride[a] = stride[a - 1] * extent[a - 1]
-    out = []
-    for bits in itertools.product((0, 1), repeat=d):
-        idx = np.zeros(Y.shape[:-1], dtype=np.int64)
-        w = np.ones(Y.shape[:-1])
-        for a in range(d):
-            idx += (i0[a] + bits[a]) * stride[a]
-            w = w * (t[a] if bits[a] else 1.0 - t[a])
-        dw = np.zeros(Y.shape)
-        for a in range(d):
-            prod = (1.0 if bits[a] else -1.0) * inside[a]
-            for b in range(d):
-                if b != a:
-                    prod = prod * (t[b] if bits[b] else 1.0 - t[b])
-            dw[..., a] = prod
-        out.append((idx, w, dw))
-    return out
+    """List of (flat_index, weight, dweight) per corner, dweight of shape (..., d)."""
+    st = Stencil(Y, extent)
+    return [(i, w, np.stack(dw, axis=-1)) for i, w, dw in zip(st.idx, st.w, st.dweights())]
 
 
-def interp(q, Y, extent):
+def interp(q, Y, extent, st=None):
     """Values, shape (B, P)."""
+    st = Stencil(Y, extent) if st is None else st
     val = np.zeros(Y.shape[:-1])
-    for idx, w, _ in stencil(Y, extent):
+    for idx, w in zip(st.idx, st.w):
         val += w * np.take_along_axis(q, idx, axis=1)
     return val
 
 
-def interp_grad(q, Y, extent):
+def interp_grad(q, Y, extent, st=None):
     """Derivative of the interpolant with respect to the position, (B, P, d)."""
+    st = Stencil(Y, extent) if st is None else st
     g = np.zeros(Y.shape)
-    for idx, _, dw in stencil(Y, extent):
-        g += dw * np.take_along_axis(q, idx, axis=1)[..., None]
+    for idx, dw in zip(st.idx, st.dweights()):
+        qv = np.take_along_axis(q, idx, axis=1)
+        for a in range(st.d):
+            g[..., a] += dw[a] * qv
     return g
 
 
-def interp_transpose(mu, Y, extent):
+def interp_transpose(mu, Y, extent, st=None):
     """Transpose of q -> interp(q, Y) applied to mu (shape (B, P)); (B, M)."""
+    st = Stencil(Y, extent) if st is None else st
     B = Y.shape[0]
     M = int(np.prod(extent))
     out = np.zeros(B * M)
     base = (np.arange(B, dtype=np.int64) * M)[:, None]
-    for idx, w, _ in stencil(Y, extent):
+    for idx, w in zip(st.idx, st.w):
         out += np.bincount((idx + base).ravel(), weights=(w * mu).ravel(), minlength=B * M)
     return out.reshape(B, M)

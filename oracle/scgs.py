@@ -10,6 +10,8 @@ every cell first forms its local residual from the state at the start of the
 colour, then all cells apply their corrections (Jacobi within a colour,
 colours in lexicographic order).
 
+The correction is relaxed by the weight omega of the level (1 unless set).
+
 Local unknown blocks, in time order k = 0..2N-1:
   k = 2i     (u_i, p_{i+1})        row F3_i (faces), F4_i (centre)
   k = 2i + 1 (v_{i+1}, pbar_{i+1}) row F1_{i+1},     F2_{i+1}
@@ -141,7 +143,8 @@ def smooth_colour(L: Level, x, w, res, colour):
         Uk = off[k] * E
         t = dhat[k] - np.einsum("cij,cj->ci", Uk, xs[k + 1])
         xs[k] = np.linalg.solve(Ahat[k], t[..., None])[..., 0]
-    # apply the corrections (disjoint unknowns within a colour)
+    # apply the corrections (disjoint unknowns within a colour), relaxed by omega
+    xs = [L.omega * xk for xk in xs]
     for k in range(2 * N):
         j = k // 2
         fx, cx = (u, p) if k % 2 == 0 else (v, pb)

@@ -24,6 +24,7 @@ class StfasProblem(ctypes.Structure):
         ("max_admm", c_int32), ("max_vcycles", c_int32), ("metric_levels", c_int32),
         ("poisson_rtol", c_double),
         ("fixed_counts", c_int32), ("precision", c_int32),
+        ("scgs_omega", c_double),
     ]
 
 

@@ -141,7 +141,8 @@ __device__ inline void colour_cell(const ColourSet& cs, int q, int& i, int& j, i
 //
 // Two kernels: k_scgs_project forms (P r)_k for every (cell, face, block) in
 // parallel into scratch[k][cell*2d + face]; k_scgs_thomas runs the
-// recurrence per (cell, face) in place on that column and applies dx.
+// recurrence per (cell, face) in place on that column and applies omega dx
+// (omega is the relaxation weight of the smoother).
 
 template <typename T, int D>
 __global__ void k_scgs_project(Grid g, int N, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ r3,
@@ -175,7 +176,7 @@ __global__ void k_scgs_project(Grid g, int N, ColourSet cs, const T* __restrict_
 template <typename T, int D>
 __global__ void k_scgs_thomas(Grid g, int N, ColourSet cs, const T* __restrict__ r2, const T* __restrict__ r4, T* v,
                               T* u, const T* __restrict__ tsub, const T* __restrict__ tcp,
-                              const T* __restrict__ tinv, T* __restrict__ scratch) {
+                              const T* __restrict__ tinv, T omega, T* __restrict__ scratch) {
     extern __shared__ unsigned char smem_raw[];
     T* tc = reinterpret_cast<T*>(smem_raw);
     const int M = 2 * N;
@@ -241,14 +242,14 @@ __global__ void k_scgs_thomas(Grid g, int N, ColourSet cs, const T* __restrict__
         for (int t = 0; t < U; ++t) {
             const int kk = k1 - t;
             x = buf[t] - cp[kk] * x;
-            ((kk & 1) ? v : u)[(long)(kk >> 1) * F + own] = fv[t] + x + ghs * sk[t] * gn_inv;
+            ((kk & 1) ? v : u)[(long)(kk >> 1) * F + own] = fv[t] + omega * (x + ghs * sk[t] * gn_inv);
         }
     }
     for (; k1 >= 0; --k1) {
         const long jj = k1 >> 1;
         x = col_p[(long)k1 * ncol] - cp[k1] * x;
         const T sk = (k1 & 1) ? r2[jj * C + c] : r4[jj * C + c];
-        ((k1 & 1) ? v : u)[jj * F + own] += x + ghs * sk * gn_inv;
+        ((k1 & 1) ? v : u)[jj * F + own] += omega * (x + ghs * sk * gn_inv);
     }
 }
 
@@ -257,7 +258,8 @@ __global__ void k_scgs_thomas(Grid g, int N, ColourSet cs, const T* __restrict__
 template <typename T, int D>
 __global__ void k_scgs_cells(Grid g, int N, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ r2,
                              const T* __restrict__ r3, const T* __restrict__ r4, T* pb, T* p,
-                             const T* __restrict__ tdiag, const T* __restrict__ tsub, const T* __restrict__ tsup) {
+                             const T* __restrict__ tdiag, const T* __restrict__ tsub, const T* __restrict__ tsup,
+                             T omega) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= cs.total * 2 * N) return;
     const int q = tid % cs.total, kk = tid / cs.total;
@@ -282,7 +284,7 @@ __global__ void k_scgs_cells(Grid g, int N, ColourSet cs, const T* __restrict__ 
     for (int t = 0; t < 2 * D; ++t)
         if (cf.inner[t]) gr += ((t & 1) ? ginv : -ginv) * r[cf.face[t]];
     T* fld = (kk & 1) ? pb : p;
-    fld[(long)(kk >> 1) * C + c] += (acc - gr) * gn_inv;
+    fld[(long)(kk >> 1) * C + c] += omega * (acc - gr) * gn_inv;
 }
 
 // ---------------------------------------------------------------- transfers

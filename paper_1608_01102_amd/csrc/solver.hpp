@@ -54,7 +54,7 @@ struct Arena {
 // Resolved problem constants (defaults of stfas.h applied).
 struct Params {
     int dim, n[3], N;
-    double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol;
+    double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol, omega;
     int ao_iters, max_admm, max_vcycles, metric_levels, fixed_counts, precision;
 };
 
@@ -92,6 +92,8 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     o.precision = p->precision;
     o.poisson_rtol = p->poisson_rtol > 0 ? p->poisson_rtol : (o.precision == STFAS_FP64 ? 1e-13 : 1e-6);
     o.fixed_counts = p->fixed_counts ? 1 : 0;
+    o.omega = p->scgs_omega > 0 ? p->scgs_omega : 0.7;
+    if (!(o.omega <= 2.0)) return false;
     const double total = (double)o.n[0] * o.n[1] * o.n[2];
     if (total > 2.0e9 / (o.dim + 1)) return false;
     return true;
@@ -699,12 +701,12 @@ public:
             // thomas: read (P r), read the cells' divergence residual, update u/v at the faces
             traced(tr, st, l == 0 ? TR_SCGS_THOMAS : TR_NONE, sz * M2 * (inner * 3 + cs.total), [&] {
                 k_scgs_thomas<T, D><<<blocks_for(nf, 64), 64, 3 * 2 * N * sizeof(T), st>>>(
-                    g, N, cs, q.r2, q.r4, q.v, q.u, t_sub, t_cp, t_inv, scgs_scratch);
+                    g, N, cs, q.r2, q.r4, q.v, q.u, t_sub, t_cp, t_inv, (T)P.omega, scgs_scratch);
             });
             const int nc = cs.total * 2 * N;
             traced(tr, st, l == 0 ? TR_SCGS_CELLS : TR_NONE, sz * M2 * (inner + cs.total * 3), [&] {
                 k_scgs_cells<T, D><<<blocks_for(nc, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r2, q.r3, q.r4, q.pb, q.p,
-                                                                     t_diag, t_sub, t_sup);
+                                                                     t_diag, t_sub, t_sup, (T)P.omega);
             });
         }
     }

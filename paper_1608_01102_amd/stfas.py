@@ -16,7 +16,8 @@ PRECISIONS = {"fp64": _lib.STFAS_FP64, "mixed": _lib.STFAS_MIXED}
 
 
 def make_problem(n, num_steps, r, dt=0.0, K=0.0, beta=0.0, ao_iters=0, eps_stfas=0.0, eps_admm=0.0, max_admm=0,
-                 max_vcycles=0, metric_levels=-1, poisson_rtol=0.0, fixed_counts=False, precision="fp64"):
+                 max_vcycles=0, metric_levels=-1, poisson_rtol=0.0, fixed_counts=False, precision="fp64",
+                 scgs_omega=0.0):
     """stfas_problem with the C defaults for every field left at 0 (-1 for metric_levels)."""
     p = StfasProblem()
     n = tuple(int(x) for x in n)
@@ -31,6 +32,7 @@ def make_problem(n, num_steps, r, dt=0.0, K=0.0, beta=0.0, ao_iters=0, eps_stfas
     p.poisson_rtol = float(poisson_rtol)
     p.fixed_counts = 1 if fixed_counts else 0
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.scgs_omega = float(scgs_omega)
     return p
 
 

@@ -188,3 +188,39 @@ def smooth_noise_density(n, rng, sigma=2.0):
     x = ndimage.gaussian_filter(rng.uniform(0.0, 1.0, shape), sigma, mode="constant")
     ones = ndimage.gaussian_filter(np.ones(shape), sigma, mode="constant")
     return (x / ones).ravel()
+
+
+# ---------------------------------------------------------------- serving stream
+def c5_requests(seed=0, count=64, rate=1.0, sizes2d=(64, 128, 256), sizes3d=(32, 64, 96),
+                steps2d=(20, 80), steps3d=(20, 60), r=1e-3):
+    """Control requests arriving by a Poisson process of the given rate (per
+    second): 2D grids from sizes2d with N ~ U{steps2d}, or 3D grids from
+    sizes3d with N ~ U{steps3d}, each with probability 1/2; 1-3 keyframes at
+    distinct steps, the last at N (blobs, or strokes in 2D); dt = 1/n.
+    Returns dicts with the fields of a serving request."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(count):
+        t += rng.exponential(1.0 / rate)
+        if rng.uniform() < 0.5:
+            m = int(rng.choice(sizes2d))
+            n = (m, m)
+            N = int(rng.integers(steps2d[0], steps2d[1] + 1))
+        else:
+            m = int(rng.choice(sizes3d))
+            n = (m, m, m)
+            N = int(rng.integers(steps3d[0], steps3d[1] + 1))
+        nk = int(rng.integers(1, 4))
+        steps = sorted(set(rng.choice(np.arange(1, N), size=nk - 1, replace=False).tolist()) | {N}) if N > 1 else [N]
+        c = np.array(n) / 2.0 + rng.uniform(-m / 8.0, m / 8.0, size=len(n))
+        rho0 = gaussian_ball(n, c, m / 10.0)
+        keys = []
+        for _ in steps:
+            if len(n) == 2 and rng.uniform() < 0.5:
+                keys.append(strokes(n, rng, int(rng.integers(2, 5)), width=max(2.0, m / 20.0)))
+            else:
+                keys.append(blobs(n, rng, int(rng.integers(1, 4)), m / 16.0, m / 8.0))
+        out.append(dict(rid=rid, arrival=t, n=n, num_steps=N, r=r, rho0=rho0, key_steps=steps,
+                        key_rho=np.stack(keys), dt=1.0 / m))
+    return out

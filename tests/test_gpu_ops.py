@@ -19,6 +19,7 @@ def _ctx(n, N, prec, dt=None, K=None, r=1e-2, **kw):
     g = Grid(n)
     dt = 0.7 * g.h if dt is None else dt
     K = 3.0 * r / dt ** 2 if K is None else K
+    kw.setdefault("scgs_omega", 1.0)
     prob = S.make_problem(n, N, r, dt=dt, K=K, precision=prec, **kw)
     return S, S.stfas_create(prob), g, dt, K
 
@@ -142,15 +143,16 @@ def test_kkt_residual_all_levels(n, N, prec):
     ctx.destroy()
 
 
+@pytest.mark.parametrize("omega", [1.0, 0.7])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,N", CASES)
-def test_scgs_sweep(n, N, prec):
-    S, ctx, g, dt, K = _ctx(n, N, prec)
+def test_scgs_sweep(n, N, prec, omega):
+    S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=omega)
     kr = K / 1e-2
     rng = np.random.default_rng(16)
     for level in (0, ctx.num_levels() - 1):
         gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
-        L = kkt.Level(gl, N, dt, kr)
+        L = kkt.Level(gl, N, dt, kr, omega=omega)
         x = _state(gl, N, rng, 0.3, prec)
         w = _q(_faces(gl, rng, N), prec)
         res = _state(gl, N, rng, 1.0, prec) if level > 0 else None

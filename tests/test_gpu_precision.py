@@ -1,0 +1,89 @@
+"""Precision form: FP32 bulk arithmetic with FP64 only for the coarsest
+projection level and the reductions.  Each check states the error of the
+mixed form against the FP64 oracle (16^3 instance of the 3D workload) or the
+FP64 GPU run (64^3 x 60)."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from gpu_common import flag, rel
+from oracle import admm
+from oracle.grid import Grid
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(w, prec, **kw):
+    from paper_1608_01102_amd import stfas as S
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    prob = S.make_problem(w["n"], w["num_steps"], w["r"], dt=w["dt"], precision=prec, **kw)
+    ctx = S.stfas_create(prob)
+    ks = sorted(w["keys"])
+    rho0 = torch.tensor(w["rho0"], dtype=dt, device="cuda")
+    keys = torch.tensor(np.stack([w["keys"][k] for k in ks]), dtype=dt, device="cuda")
+    u = torch.zeros(w["num_steps"] * ctx.faces, dtype=dt, device="cuda")
+    st = S.stfas_solve(ctx, rho0, ks, keys, u)
+    ctx.destroy()
+    return u.double().cpu().numpy().reshape(w["num_steps"], -1), st
+
+
+def _resim_keys(w, u):
+    """Keyframe-time densities of the FP64 oracle re-simulation of u."""
+    g = Grid(w["n"])
+    rho, _ = admm.resimulate(g, w["rho0"], u, w["dt"])
+    return {t: rho[t] for t in w["keys"]}
+
+
+def test_mixed_vs_oracle_on_16cubed_instance():
+    w = synthetic.c3_precision_3d(0, scale=4)
+    kw = dict(max_admm=1, max_vcycles=1, ao_iters=1, fixed_counts=True)
+    flag("precision 16^3 x 60 mixed and fp64")
+    um, sm = _run(w, "mixed", **kw)
+    ud, sd = _run(w, "fp64", **kw)
+    ref = admm.solve(admm.Problem(n=w["n"], num_steps=w["num_steps"], r=w["r"], dt=w["dt"], **kw), w["rho0"],
+                     w["keys"])
+    e_mixed = rel(um, ref.u)
+    e_fp64 = rel(ud, ref.u)
+    print(f"16^3x60: |u_mixed - u_oracle|/|u_oracle| = {e_mixed:.2e}, fp64 GPU: {e_fp64:.2e}")
+    assert e_fp64 <= 1e-10
+    assert e_mixed <= 1e-4
+    km, ko = _resim_keys(w, um), _resim_keys(w, ref.u)
+    ekf = max(rel(km[t], ko[t]) for t in ko)
+    print(f"16^3x60: keyframe error of the mixed form vs oracle = {ekf:.2e}")
+    assert ekf <= 1e-4
+    assert abs(sm["objective"] - ref.objective) <= 1e-4 * ref.objective
+
+
+def test_mixed_vs_fp64_gpu_on_64cubed():
+    from paper_1608_01102_amd import stfas as S
+    w = synthetic.c3_precision_3d(0)
+    kw = dict(max_admm=2, max_vcycles=4, fixed_counts=True)
+    flag("precision 64^3 x 60 mixed and fp64")
+    um, sm = _run(w, "mixed", **kw)
+    ud, sd = _run(w, "fp64", **kw)
+    e_u = rel(um, ud)
+    # keyframe densities: re-simulate both controls with the FP64 GPU step
+    p64 = S.make_problem(w["n"], 1, 1.0, dt=w["dt"], precision="fp64")
+    cells, faces = S.counts(p64)
+    work = torch.empty(S.stfas_step_work_bytes(p64), dtype=torch.uint8, device="cuda")
+
+    def resim(u):
+        rho = torch.tensor(w["rho0"], dtype=torch.float64, device="cuda")
+        v = torch.zeros(faces, dtype=torch.float64, device="cuda")
+        ut = torch.tensor(u, dtype=torch.float64, device="cuda")
+        out = {}
+        for i in range(w["num_steps"]):
+            rn, vn = torch.empty_like(rho), torch.empty_like(v)
+            S.stfas_step_forward(p64, rho, v, ut[i], rn, vn, work=work)
+            rho, v = rn, vn
+            if i + 1 in w["keys"]:
+                out[i + 1] = rho.cpu().numpy()
+        return out
+    km, kd = resim(um), resim(ud)
+    ekf = max(rel(km[t], kd[t]) for t in kd)
+    eobj = abs(sm["objective"] - sd["objective"]) / abs(sd["objective"])
+    print(f"64^3x60: |u_mixed - u_fp64|/|u_fp64| = {e_u:.2e}, keyframe error = {ekf:.2e}, objective = {eobj:.2e}")
+    # controls differ most where a foot point sits near a lattice line; the keyframe
+    # densities (the metric) and the objective are far tighter
+    assert e_u <= 5e-3 and ekf <= 1e-4 and eobj <= 1e-5

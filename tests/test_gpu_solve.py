@@ -23,7 +23,7 @@ def test_nso_vcycles(n, N, prec):
     g = Grid(n)
     dt, r = g.h, 1e-2
     K = r / dt ** 2
-    prob = S.make_problem(n, N, r, dt=dt, K=K, max_vcycles=3, fixed_counts=True, precision=prec)
+    prob = S.make_problem(n, N, r, dt=dt, K=K, max_vcycles=3, fixed_counts=True, precision=prec, scgs_omega=0.7)
     ctx = S.stfas_create(prob)
     rng = np.random.default_rng(21)
     w = _q(np.stack([synthetic.curl_noise_velocity(n, rng, 1.0, 0.8) for _ in range(N)]), prec)
@@ -31,7 +31,7 @@ def test_nso_vcycles(n, N, prec):
     xd = tuple(to_dev(a, prec) for a in x)
     flag(f"nso n={n} N={N} {prec}")
     nv, hist = S.stfas_op_nso(ctx, xd, to_dev(w, prec))
-    H = stfas.Hierarchy(g, N, dt, K / r)
+    H = stfas.Hierarchy(g, N, dt, K / r, omega=0.7)
     nv_ref, hist_ref = stfas.nso(H, x, w, max_vcycles=3, fixed_counts=True)
     assert nv == nv_ref == 3
     for k in range(4):

@@ -5,6 +5,7 @@ import glob
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -57,3 +58,24 @@ def test_status_strings():
     lib = _lib.load()
     assert lib.stfas_status_string(1) == b"invalid argument"
     assert b"gfx950" in lib.stfas_build_info()
+
+
+def test_serving_footprint_is_exact_and_monotone():
+    from paper_1608_01102_amd import serving, stfas as S
+    raw = synthetic_requests()
+    fps = []
+    for q in raw:
+        req = serving.Request(q["rid"], q["arrival"], q["n"], q["num_steps"], q["r"], q["rho0"], q["key_steps"],
+                              q["key_rho"], dict(dt=q["dt"]))
+        fp = serving.footprint(req, "mixed")
+        prob = serving.problem_of(req, "mixed")
+        assert fp > S.stfas_workspace_bytes(prob) > 0
+        fps.append((int(np.prod(q["n"])) * q["num_steps"], fp))
+    fps.sort()
+    # larger spacetime problems never need less memory
+    assert all(fps[i][1] <= fps[i + 1][1] for i in range(len(fps) - 1) if fps[i][0] < fps[i + 1][0])
+
+
+def synthetic_requests():
+    import synthetic
+    return synthetic.c5_requests(0, 12, rate=1.0)
