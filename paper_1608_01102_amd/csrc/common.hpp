@@ -194,6 +194,15 @@ struct Interp {
     }
 };
 
+// a[i] for a small array and a runtime index, by selects (no private memory).
+template <typename U, int K>
+__device__ inline U pick(const U (&a)[K], int i) {
+    U r = a[0];
+#pragma unroll
+    for (int e = 1; e < K; ++e) r = (e == i) ? a[e] : r;
+    return r;
+}
+
 template <typename T>
 __device__ inline void atomic_add(T* p, T v) {
     atomicAdd(p, v);

@@ -115,7 +115,7 @@ __global__ void k_advect_dv_T(Grid g, T cfl, const T* __restrict__ mu, const T* 
         it.setup_disp(idx, y, g.n[0], g.n[1], g.n[2]);
         T gr[3];
         it.grad(rho, gr);
-        acc += (T)0.5 * (-cfl) * m * gr[a];
+        acc += (T)0.5 * (-cfl) * m * (a == 0 ? gr[0] : (a == 1 ? gr[1] : gr[D - 1]));
     }
     gv[f] = (vt ? vt[f] : (T)0) + scale * acc;
 }
@@ -183,7 +183,8 @@ __global__ void k_self_advect_T(Grid g, T cfl, const T* __restrict__ v, const T*
         const T w = it.weight(q) * yv;
         if (w == (T)0) continue;
         // corner lattice coordinate along a decides whether it is a wall
-        const int ca = it.ax[a].i0 + ((q >> a) & 1);
+        const int ia0 = a == 0 ? it.ax[0].i0 : (a == 1 ? it.ax[1].i0 : it.ax[D - 1].i0);
+        const int ca = ia0 + ((q >> a) & 1);
         if (ca == 0 || ca == g.n[a]) continue;
         atomic_add(oa + it.corner(q), w);
     }

@@ -112,6 +112,7 @@ template <int D>
 __device__ inline void cell_faces(const Grid& g, int i, int j, int k, CellFaces<D>& cf) {
     const int idx[3] = {i, j, k};
     cf.m = 0;
+#pragma unroll
     for (int a = 0; a < D; ++a) {
         cf.face[2 * a] = face_index(g, a, i, j, k);
         cf.face[2 * a + 1] = face_index(g, a, i + (a == 0), j + (a == 1), k + (a == 2));
@@ -157,7 +158,7 @@ __global__ void k_scgs_project(Grid g, int N, ColourSet cs, const T* __restrict_
     colour_cell(cs, q, i, j, k);
     CellFaces<D> cf;
     cell_faces<D>(g, i, j, k, cf);
-    if (!cf.inner[s]) return;
+    if (!pick(cf.inner, s)) return;
     const T ginv = (T)1 / sqrt((T)cf.m);
     const long jo = (long)(kk >> 1) * g.nface;
     const T* r = (kk & 1) ? r1 + jo : r3 + jo;
@@ -166,7 +167,7 @@ __global__ void k_scgs_project(Grid g, int N, ColourSet cs, const T* __restrict_
     for (int t = 0; t < 2 * D; ++t)
         if (cf.inner[t]) gr += ((t & 1) ? ginv : -ginv) * r[cf.face[t]];
     const T ghs = (s & 1) ? ginv : -ginv;
-    scratch[tid] = r[cf.face[s]] - ghs * gr;
+    scratch[tid] = r[pick(cf.face, s)] - ghs * gr;
 }
 
 // Recurrence of the face solve, one thread per (cell, face) column.  The
@@ -197,13 +198,13 @@ __global__ void k_scgs_thomas(Grid g, int N, ColourSet cs, const T* __restrict__
     colour_cell(cs, q, i, j, k);
     CellFaces<D> cf;
     cell_faces<D>(g, i, j, k, cf);
-    if (!cf.inner[s]) return;
+    if (!pick(cf.inner, s)) return;
     const T ginv = (T)1 / sqrt((T)cf.m);
     const T ghs = (s & 1) ? ginv : -ginv;
     const T gn_inv = (T)g.h * ginv;             // 1/|g| = h/sqrt(m)
     const long F = g.nface, C = g.ncell;
     const int c = cell_index(g, i, j, k);
-    const int own = cf.face[s];
+    const int own = pick(cf.face, s);
     T* col_p = scratch + col;
     constexpr int U = 16;
     // forward elimination
@@ -248,6 +249,113 @@ __global__ void k_scgs_thomas(Grid g, int N, ColourSet cs, const T* __restrict__
     for (; k1 >= 0; --k1) {
         const long jj = k1 >> 1;
         x = col_p[(long)k1 * ncol] - cp[k1] * x;
+        const T sk = (k1 & 1) ? r2[jj * C + c] : r4[jj * C + c];
+        ((k1 & 1) ? v : u)[jj * F + own] += omega * (x + ghs * sk * gn_inv);
+    }
+}
+
+// Fused face solve for problems whose columns fit in LDS: one wave of 64
+// (cell, face) columns per workgroup; the projection (P r)_k is formed on the
+// fly from the cell's face residuals, the forward elimination keeps the
+// column in LDS (scol[k][lane]) and the back substitution applies omega dx.
+// Dynamic LDS: 3 * 2N Thomas factors + 2N * 64 column values.
+template <typename T, int D>
+__global__ void __launch_bounds__(64) k_scgs_faces_lds(Grid g, int N, ColourSet cs, const T* __restrict__ r1,
+                                                      const T* __restrict__ r2, const T* __restrict__ r3,
+                                                      const T* __restrict__ r4, T* v, T* u,
+                                                      const T* __restrict__ tsub, const T* __restrict__ tcp,
+                                                      const T* __restrict__ tinv, T omega) {
+    extern __shared__ unsigned char smem_raw[];
+    T* tc = reinterpret_cast<T*>(smem_raw);
+    const int M = 2 * N;
+    for (int e = threadIdx.x; e < M; e += blockDim.x) {
+        tc[e] = tsub[e];
+        tc[M + e] = tinv[e];
+        tc[2 * M + e] = tcp[e];
+    }
+    __syncthreads();
+    const T* sub = tc;
+    const T* inv = tc + M;
+    const T* cp = tc + 2 * M;
+    T* scol = tc + 3 * M + threadIdx.x;          // column of this lane, stride 64
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncol = cs.total * 2 * D;
+    if (col >= ncol) return;
+    const int q = col / (2 * D), s = col % (2 * D);
+    int i, j, k;
+    colour_cell(cs, q, i, j, k);
+    CellFaces<D> cf;
+    cell_faces<D>(g, i, j, k, cf);
+    if (!pick(cf.inner, s)) return;
+    const T ginv = (T)1 / sqrt((T)cf.m);
+    T gh[2 * D];
+#pragma unroll
+    for (int t = 0; t < 2 * D; ++t) gh[t] = cf.inner[t] ? ((t & 1) ? ginv : -ginv) : (T)0;
+    const T ghs = (s & 1) ? ginv : -ginv;
+    const T gn_inv = (T)g.h * ginv;
+    const long F = g.nface, C = g.ncell;
+    const int c = cell_index(g, i, j, k);
+    const int own = pick(cf.face, s);
+    // wall slots read a valid interior-or-wall index with weight 0
+    int fidx[2 * D];
+#pragma unroll
+    for (int t = 0; t < 2 * D; ++t) fidx[t] = cf.face[t];
+    constexpr int U = (sizeof(T) == 8 || D == 3) ? 4 : 8;
+    T dprev = 0;
+    int k0 = 0;
+    for (; k0 + U <= M; k0 += U) {
+        T rv[U][2 * D];
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int kk = k0 + t;
+            const T* r = ((kk & 1) ? r1 : r3) + (long)(kk >> 1) * F;
+#pragma unroll
+            for (int e = 0; e < 2 * D; ++e) rv[t][e] = r[fidx[e]];
+        }
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            T gr = 0, ro = 0;
+#pragma unroll
+            for (int e = 0; e < 2 * D; ++e) {
+                gr += gh[e] * rv[t][e];
+                ro = (e == s) ? rv[t][e] : ro;       // own face, selected without a runtime index
+            }
+            const T pr = ro - ghs * gr;
+            dprev = (pr - sub[k0 + t] * dprev) * inv[k0 + t];
+            scol[(k0 + t) * 64] = dprev;
+        }
+    }
+    for (; k0 < M; ++k0) {
+        const T* r = ((k0 & 1) ? r1 : r3) + (long)(k0 >> 1) * F;
+        T gr = 0;
+#pragma unroll
+        for (int e = 0; e < 2 * D; ++e) gr += gh[e] * r[fidx[e]];
+        const T pr = r[own] - ghs * gr;
+        dprev = (pr - sub[k0] * dprev) * inv[k0];
+        scol[k0 * 64] = dprev;
+    }
+    constexpr int V = 16;
+    T x = 0;
+    int k1 = M - 1;
+    for (; k1 - (V - 1) >= 0; k1 -= V) {
+        T sk[V], fv[V];
+#pragma unroll
+        for (int t = 0; t < V; ++t) {
+            const int kk = k1 - t;
+            const long jj = kk >> 1;
+            sk[t] = (kk & 1) ? r2[jj * C + c] : r4[jj * C + c];
+            fv[t] = ((kk & 1) ? v : u)[jj * F + own];
+        }
+#pragma unroll
+        for (int t = 0; t < V; ++t) {
+            const int kk = k1 - t;
+            x = scol[kk * 64] - cp[kk] * x;
+            ((kk & 1) ? v : u)[(long)(kk >> 1) * F + own] = fv[t] + omega * (x + ghs * sk[t] * gn_inv);
+        }
+    }
+    for (; k1 >= 0; --k1) {
+        const long jj = k1 >> 1;
+        x = scol[k1 * 64] - cp[k1] * x;
         const T sk = (k1 & 1) ? r2[jj * C + c] : r4[jj * C + c];
         ((k1 & 1) ? v : u)[jj * F + own] += omega * (x + ghs * sk * gn_inv);
     }

@@ -693,16 +693,26 @@ public:
             const int nf = cs.total * 2 * D;
             const double inner = (double)colour_inner_faces(g, colour);
             const double sz = sizeof(T), M2 = 2.0 * N;
-            // project: read r1/r3 at the colour's faces, write (P r)
-            traced(tr, st, l == 0 ? TR_SCGS_PROJECT : TR_NONE, sz * M2 * inner * 2, [&] {
-                k_scgs_project<T, D><<<blocks_for((long)nf * 2 * N, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r3,
-                                                                                      scgs_scratch);
-            });
-            // thomas: read (P r), read the cells' divergence residual, update u/v at the faces
-            traced(tr, st, l == 0 ? TR_SCGS_THOMAS : TR_NONE, sz * M2 * (inner * 3 + cs.total), [&] {
-                k_scgs_thomas<T, D><<<blocks_for(nf, 64), 64, 3 * 2 * N * sizeof(T), st>>>(
-                    g, N, cs, q.r2, q.r4, q.v, q.u, t_sub, t_cp, t_inv, (T)P.omega, scgs_scratch);
-            });
+            const size_t lds = (size_t)(3 * 2 * N + 2 * N * 64) * sizeof(T);
+            if (lds <= 65536) {
+                // fused: read r1/r3 at the colour's faces, r2/r4 at its cells, update u/v
+                traced(tr, st, l == 0 ? TR_SCGS_THOMAS : TR_NONE, sz * M2 * (inner * 3 + cs.total), [&] {
+                    k_scgs_faces_lds<T, D><<<blocks_for(nf, 64), 64, lds, st>>>(g, N, cs, q.r1, q.r2, q.r3, q.r4,
+                                                                               q.v, q.u, t_sub, t_cp, t_inv,
+                                                                               (T)P.omega);
+                });
+            } else {
+                // project: read r1/r3 at the colour's faces, write (P r)
+                traced(tr, st, l == 0 ? TR_SCGS_PROJECT : TR_NONE, sz * M2 * inner * 2, [&] {
+                    k_scgs_project<T, D><<<blocks_for((long)nf * 2 * N, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r3,
+                                                                                          scgs_scratch);
+                });
+                // thomas: read (P r), read the cells' divergence residual, update u/v at the faces
+                traced(tr, st, l == 0 ? TR_SCGS_THOMAS : TR_NONE, sz * M2 * (inner * 3 + cs.total), [&] {
+                    k_scgs_thomas<T, D><<<blocks_for(nf, 64), 64, 3 * 2 * N * sizeof(T), st>>>(
+                        g, N, cs, q.r2, q.r4, q.v, q.u, t_sub, t_cp, t_inv, (T)P.omega, scgs_scratch);
+                });
+            }
             const int nc = cs.total * 2 * N;
             traced(tr, st, l == 0 ? TR_SCGS_CELLS : TR_NONE, sz * M2 * (inner + cs.total * 3), [&] {
                 k_scgs_cells<T, D><<<blocks_for(nc, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r2, q.r3, q.r4, q.pb, q.p,
