@@ -29,6 +29,9 @@ def parse():
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--trace-kernel", default="scgs_thomas",
                     help="kernel family whose launches on the finest level are timed with HIP events")
+    ap.add_argument("--serve-requests", type=int, default=16, help="0 skips the serving run")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=24.0)
     return ap.parse_args()
 
 
@@ -106,9 +109,11 @@ def main():
         out["fp64_gpu"] = {"objective": s64["objective"], "admm_iters": s64["admm_iters"],
                            "seconds": s64["seconds"], "kf_err_mixed_vs_fp64": kf}
         c64.destroy()
+    ctx.destroy()
+    if args.serve_requests > 0:
+        out["serving"] = serving_run(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
-    ctx.destroy()
     print(json.dumps(out), flush=True)
 
 
@@ -153,6 +158,45 @@ def keyframe_error(S, p64, w, u_a, u_b):
         return out
     a, b = run(u_a), run(u_b)
     return max(float(np.linalg.norm(a[t] - b[t]) / np.linalg.norm(b[t])) for t in b)
+
+
+def serving_run(args):
+    """Continuous batching of the mixed 2D/3D request stream against a FIFO
+    loop.  Each request runs 2 ADMM iterations of 4 V-cycles (fixed counts)
+    so that the stream finishes within a minute; arrivals are a Poisson
+    process at 0.8 x the FIFO loop's measured throughput."""
+    import numpy as np
+    import synthetic
+    from paper_1608_01102_amd import serving
+    raw = synthetic.c5_requests(args.seed, args.serve_requests, rate=1.0)
+    reqs = [serving.Request(q["rid"], q["arrival"], q["n"], q["num_steps"], q["r"], q["rho0"], q["key_steps"],
+                            q["key_rho"], dict(dt=q["dt"], max_admm=2, max_vcycles=4, fixed_counts=True))
+            for q in raw]
+    # FIFO loop, closed (back to back): service times and throughput
+    seq, seq_span = serving.run_sequential(reqs, realtime=False)
+    service = {r.rid: r.finished - r.admitted for r in seq}
+    rate = 0.8 * len(reqs) / seq_span
+    for q, r0 in zip(reqs, raw):
+        q.arrival = r0["arrival"] / rate
+    # FIFO latencies under these arrivals: finish_i = max(arrival_i, finish_{i-1}) + service_i
+    fin = 0.0
+    fifo_lat = []
+    for q in sorted(reqs, key=lambda x: x.arrival):
+        fin = max(q.arrival, fin) + service[q.rid]
+        fifo_lat.append(fin - q.arrival)
+    srv = serving.Server(budget_bytes=int(args.serve_budget_gb * 2 ** 30), max_slots=args.serve_slots,
+                         precision="mixed")
+    res, span = srv.run(reqs, realtime=True)
+    summ = serving.summary(res, span)
+    lat = np.array(fifo_lat)
+    return {"requests": len(reqs), "arrival_rate_per_s": rate, "slots": args.serve_slots,
+            "budget_gb": args.serve_budget_gb,
+            "mix": {"2d": sum(len(q.n) == 2 for q in reqs), "3d": sum(len(q.n) == 3 for q in reqs)},
+            "continuous": {"p50_s": summ["p50_s"], "p99_s": summ["p99_s"], "solves_per_hour": summ["solves_per_hour"],
+                           "makespan_s": summ["makespan_s"]},
+            "fifo": {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                     "solves_per_hour": 3600.0 * len(reqs) / seq_span, "closed_loop_makespan_s": seq_span},
+            "per_request": "2 ADMM iterations x 4 V-cycles, fixed counts, mixed precision"}
 
 
 def cpu_baseline(w):

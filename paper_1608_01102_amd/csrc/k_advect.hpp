@@ -153,61 +153,117 @@ __global__ void k_self_advect(Grid g, T cfl, T dt, const T* __restrict__ v, cons
 // y_I (-dt/h) grad_Y I[v_a] returns to the sampled velocities (component a
 // to v_a[I], component b != a by quarters to the four v_b faces averaged at
 // I).  Contributions that land on wall faces are dropped.
+// The scatter is tiled: each workgroup takes a tile of a-faces of
+// one time slice (blockIdx.y = slice, blockIdx.z = axis a), accumulates all
+// its contributions into LDS windows that cover the tile plus a halo of H
+// nodes on each of the d face lattices, then adds every touched window node
+// to global memory once.  A contribution outside its window (a backtrace
+// longer than the halo) goes straight to global memory.  Far fewer global
+// atomics than one per contribution.
+template <int D>
+struct TileShape;
+template <>
+struct TileShape<2> {
+    static constexpr int X = 32, Y = 8, Z = 1, H = 3;
+};
+template <>
+struct TileShape<3> {
+    static constexpr int X = 8, Y = 8, Z = 4, H = 2;
+};
+
 template <typename T, int D>
-__global__ void k_self_advect_T(Grid g, T cfl, const T* __restrict__ v, const T* __restrict__ y, T scale, T* out,
-                                long vs) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= g.nface) return;
+__global__ void __launch_bounds__(256) k_self_advect_T_tiled(Grid g, T cfl, const T* __restrict__ v,
+                                                             const T* __restrict__ y, T scale, T* out, long vs) {
+    using TS = TileShape<D>;
+    constexpr int H = TS::H;
+    constexpr int WX = TS::X + 2 * H, WY = TS::Y + 2 * H, WZ = (D == 3) ? TS::Z + 2 * H : 1;
+    constexpr int WN = WX * WY * WZ;
+    __shared__ T win[D][WN];
+    const int a = blockIdx.z;
     v += blockIdx.y * vs;
     y += blockIdx.y * vs;
     out += blockIdx.y * vs;
-    int a, i, j, k;
-    face_decode(g, f, a, i, j, k);
-    if (!face_interior(g, a, i, j, k)) return;
-    const T yv = y[f] * scale;
-    if (yv == (T)0) return;
-    T vh[3];
-    face_velocity<T, D>(g, v, a, i, j, k, vh);
-    const int idx[3] = {i, j, k};
-    T yy[3];
-    for (int b = 0; b < D; ++b) yy[b] = -cfl * vh[b];
+    // tile origin in a-lattice coordinates
     const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
-    Interp<T, D> it;
-    it.setup_disp(idx, yy, ex, ey, ez);
-    const T* va = v + g.foff[a];
-    T* oa = out + g.foff[a];
-    T gr[3];
-    it.grad(va, gr);
+    const int ntx = (ex + TS::X - 1) / TS::X, nty = (ey + TS::Y - 1) / TS::Y;
+    const int ntz = (D == 3) ? (ez + TS::Z - 1) / TS::Z : 1;
+    const int tile = blockIdx.x;
+    // the launch covers the axis with the most tiles; the others' extra
+    // workgroups have nothing to do (uniform exit before any barrier)
+    if (tile >= ntx * nty * ntz) return;
+    const int tx0 = (tile % ntx) * TS::X;
+    const int ty0 = ((tile / ntx) % nty) * TS::Y;
+    const int tz0 = (D == 3) ? (tile / (ntx * nty)) * TS::Z : 0;
+    const int ox = tx0 - H, oy = ty0 - H, oz = (D == 3) ? tz0 - H : 0;
+    for (int e = threadIdx.x; e < D * WN; e += blockDim.x) (&win[0][0])[e] = (T)0;
+    __syncthreads();
+    const int lx = threadIdx.x % TS::X, ly = (threadIdx.x / TS::X) % TS::Y, lz = threadIdx.x / (TS::X * TS::Y);
+    const int i = tx0 + lx, j = ty0 + ly, k = tz0 + lz;
+    // add val at lattice-b node (ci, cj, ck): into the window when it is inside
+    auto add = [&](int b, int ci, int cj, int ck, T val) {
+        const int wx = ci - ox, wy = cj - oy, wz = ck - oz;
+        if (wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
+            atomicAdd(&win[b][(wz * WY + wy) * WX + wx], val);
+        else
+            atomic_add(out + face_index(g, b, ci, cj, ck), val);
+    };
+    const bool valid = i < ex && j < ey && (D == 2 || k < ez);
+    if (valid && face_interior(g, a, i, j, k)) {
+        const int f = face_index(g, a, i, j, k);
+        const T yv = y[f] * scale;
+        if (yv != (T)0) {
+            T vh[3];
+            face_velocity<T, D>(g, v, a, i, j, k, vh);
+            const int idx[3] = {i, j, k};
+            T dl[3];
+            for (int b = 0; b < D; ++b) dl[b] = -cfl * vh[b];
+            Interp<T, D> it;
+            it.setup_disp(idx, dl, ex, ey, ez);
+            T gr[3];
+            it.grad(v + g.foff[a], gr);
+            const int c0[3] = {it.ax[0].i0, it.ax[1].i0, D == 3 ? it.ax[D - 1].i0 : 0};
 #pragma unroll
-    for (int q = 0; q < (1 << D); ++q) {
-        const T w = it.weight(q) * yv;
-        if (w == (T)0) continue;
-        // corner lattice coordinate along a decides whether it is a wall
-        const int ia0 = a == 0 ? it.ax[0].i0 : (a == 1 ? it.ax[1].i0 : it.ax[D - 1].i0);
-        const int ca = ia0 + ((q >> a) & 1);
-        if (ca == 0 || ca == g.n[a]) continue;
-        atomic_add(oa + it.corner(q), w);
+            for (int q = 0; q < (1 << D); ++q) {
+                const T w = it.weight(q) * yv;
+                if (w == (T)0) continue;
+                const int ci = c0[0] + (q & 1), cj = c0[1] + ((q >> 1) & 1), ck = D == 3 ? c0[2] + ((q >> 2) & 1) : 0;
+                const int ca = a == 0 ? ci : (a == 1 ? cj : ck);
+                if (ca == 0 || ca == g.n[a]) continue;          // wall node of the a-lattice
+                add(a, ci, cj, ck, w);
+            }
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const T gb = yv * (-cfl) * gr[b];
+                if (gb == (T)0) continue;
+                if (b == a) {
+                    add(a, i, j, k, gb);
+                    continue;
+                }
+                const T qv = (T)0.25 * gb;
+                const int ia = i - (a == 0), ja = j - (a == 1), ka = k - (a == 2);
+                const int db0 = (b == 0), db1 = (b == 1), db2 = (b == 2);
+                const int bi = b == 0 ? i : (b == 1 ? j : k);
+                if (bi != 0) {
+                    add(b, ia, ja, ka, qv);
+                    add(b, i, j, k, qv);
+                }
+                if (bi + 1 != g.n[b]) {
+                    add(b, ia + db0, ja + db1, ka + db2, qv);
+                    add(b, i + db0, j + db1, k + db2, qv);
+                }
+            }
+        }
     }
-    for (int b = 0; b < D; ++b) {
-        const T gb = yv * (-cfl) * gr[b];
-        if (gb == (T)0) continue;
-        if (b == a) {
-            atomic_add(out + f, gb);
-            continue;
-        }
-        const T qv = (T)0.25 * gb;
-        const int ia = i - (a == 0), ja = j - (a == 1), ka = k - (a == 2);
-        const int db0 = (b == 0), db1 = (b == 1), db2 = (b == 2);
-        const int bi = b == 0 ? i : (b == 1 ? j : k);   // b-coordinate of I (and of I - e_a)
-        // faces at b-coordinate bi (I, I - e_a) are walls when bi == 0; at bi + 1 when bi + 1 == n_b
-        if (bi != 0) {
-            atomic_add(out + face_index(g, b, ia, ja, ka), qv);
-            atomic_add(out + face_index(g, b, i, j, k), qv);
-        }
-        if (bi + 1 != g.n[b]) {
-            atomic_add(out + face_index(g, b, ia + db0, ja + db1, ka + db2), qv);
-            atomic_add(out + face_index(g, b, i + db0, j + db1, k + db2), qv);
-        }
+    __syncthreads();
+    // flush: every nonzero window node inside its lattice, once
+    for (int e = threadIdx.x; e < D * WN; e += blockDim.x) {
+        const int b = e / WN, r = e % WN;
+        const T val = win[b][r];
+        if (val == (T)0) continue;
+        const int ci = ox + r % WX, cj = oy + (r / WX) % WY, ck = oz + r / (WX * WY);
+        if (ci < 0 || cj < 0 || ck < 0) continue;
+        if (ci >= face_ext(g, b, 0) || cj >= face_ext(g, b, 1) || (D == 3 && ck >= face_ext(g, b, 2))) continue;
+        atomic_add(out + face_index(g, b, ci, cj, ck), val);
     }
 }
 

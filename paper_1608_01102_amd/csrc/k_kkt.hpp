@@ -17,7 +17,7 @@
 
 namespace stfas {
 
-// Face rows F1, F3 without the J_S^T term of F1 (added by k_self_advect_T).
+// Face rows F1, F3 without the J_S^T term of F1 (added by k_self_advect_T_tiled).
 template <typename T, int D>
 __global__ void k_kkt_faces(Grid g, int N, T dt, T kr, T cfl, T sgn, const T* __restrict__ v,
                             const T* __restrict__ pb, const T* __restrict__ u, const T* __restrict__ p,

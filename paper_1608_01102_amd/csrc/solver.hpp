@@ -413,6 +413,21 @@ public:
     }
 };
 
+// out[b] += scale J_S(v[b])^T y[b] for `batch` slices (tiled scatter).
+template <typename T, int D>
+inline void launch_self_advect_T(const Grid& g, T cfl, const T* v, const T* y, T scale, T* out, int batch,
+                                 hipStream_t st) {
+    using TS = TileShape<D>;
+    int tiles = 0;
+    for (int a = 0; a < D; ++a) {
+        const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
+        const int t = ((ex + TS::X - 1) / TS::X) * ((ey + TS::Y - 1) / TS::Y) * (D == 3 ? (ez + TS::Z - 1) / TS::Z : 1);
+        tiles = std::max(tiles, t);
+    }
+    // blocks whose tile lies beyond a smaller lattice exit after the (empty) flush
+    k_self_advect_T_tiled<T, D><<<dim3(tiles, batch, D), 256, 0, st>>>(g, cfl, v, y, scale, out, g.nface);
+}
+
 template <typename T, int D>
 class Solver : public SolverBase {
 public:
@@ -607,9 +622,7 @@ public:
     }
     void self_advect_T(int l, const T* v, const T* y, T scale, T* out, int batch) {
         if (batch <= 0) return;
-        const Grid& g = L[l];
-        k_self_advect_T<T, D><<<dim3(blocks_for(g.nface, BS), batch), BS, 0, st>>>(g, cfl(l), v, y, scale, out,
-                                                                                  g.nface);
+        launch_self_advect_T<T, D>(L[l], cfl(l), v, y, scale, out, batch, st);
     }
 
     // ------------------------------------------------------------ projection

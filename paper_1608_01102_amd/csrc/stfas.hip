@@ -98,7 +98,7 @@ struct Step {
         // g_v = (dA/dv)^T g_rho' + J_S^T g_w
         k_advect_dv_T<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, grho_o, rho, v, nullptr, (T)1, gv,
                                                                    g.ncell, g.nface);
-        k_self_advect_T<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, v, gw, (T)1, gv, g.nface);
+        launch_self_advect_T<T, D>(g, cfl, v, gw, (T)1, gv, 1, st);
         k_fill<T><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g.ncell, grho, (T)0);
         k_advect_T<T, D><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g, cfl, grho_o, v, grho, g.ncell, g.nface);
     }

@@ -10,7 +10,7 @@ from oracle.grid import Grid
 
 pytestmark = pytest.mark.gpu
 
-CASES = [((16, 12), 4), ((8, 8, 8), 3), ((20, 12), 5)]
+CASES = [((16, 12), 4), ((8, 8, 8), 3), ((20, 12), 5), ((16, 16), 3), ((12, 8, 16), 2)]
 PRECS = ["fp64", "mixed"]
 
 
