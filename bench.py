@@ -184,6 +184,7 @@ def serving_run(args):
     for q in sorted(reqs, key=lambda x: x.arrival):
         fin = max(q.arrival, fin) + service[q.rid]
         fifo_lat.append(fin - q.arrival)
+    fifo_span = fin
     srv = serving.Server(budget_bytes=int(args.serve_budget_gb * 2 ** 30), max_slots=args.serve_slots,
                          precision="mixed")
     res, span = srv.run(reqs, realtime=True)
@@ -195,7 +196,8 @@ def serving_run(args):
             "continuous": {"p50_s": summ["p50_s"], "p99_s": summ["p99_s"], "solves_per_hour": summ["solves_per_hour"],
                            "makespan_s": summ["makespan_s"]},
             "fifo": {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-                     "solves_per_hour": 3600.0 * len(reqs) / seq_span, "closed_loop_makespan_s": seq_span},
+                     "solves_per_hour": 3600.0 * len(reqs) / fifo_span, "makespan_s": fifo_span,
+                     "closed_loop_solves_per_hour": 3600.0 * len(reqs) / seq_span},
             "per_request": "2 ADMM iterations x 4 V-cycles, fixed counts, mixed precision"}
 
 

@@ -102,6 +102,16 @@ size_t stfas_workspace_bytes(const stfas_problem* prob);
  * the context to hip_stream (a hipStream_t; NULL = default stream). */
 stfas_status stfas_create(const stfas_problem* prob, void* hip_stream, stfas_ctx** out);
 
+/* Same as stfas_create, but the workspace is caller memory: `workspace`
+ * points to at least stfas_workspace_bytes(prob) bytes of device memory on
+ * the stream's device (256-byte aligned), which the caller keeps alive until
+ * stfas_destroy and frees itself.  The context then makes no device
+ * allocation and its destroy frees nothing, so contexts can come and go
+ * while other streams run (a device free would wait for all of them).
+ * workspace_bytes too small or a misaligned pointer: STFAS_E_INVALID. */
+stfas_status stfas_create_in(const stfas_problem* prob, void* hip_stream, void* workspace, size_t workspace_bytes,
+                             stfas_ctx** out);
+
 /* Solve (Alg:outter).  rho0: initial density [cells].  key_steps: host array
  * of num_key step indices in 1..N, strictly increasing.  key_rho: keyframe
  * densities [num_key][cells].  u_out: the control sequence [N][faces].

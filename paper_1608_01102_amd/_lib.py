@@ -43,6 +43,8 @@ class StfasState(ctypes.Structure):
 _SIGS = {
     "stfas_workspace_bytes": (c_size_t, [ctypes.POINTER(StfasProblem)]),
     "stfas_create": (c_int32, [ctypes.POINTER(StfasProblem), c_void_p, ctypes.POINTER(c_void_p)]),
+    "stfas_create_in": (c_int32, [ctypes.POINTER(StfasProblem), c_void_p, c_void_p, c_size_t,
+                                  ctypes.POINTER(c_void_p)]),
     "stfas_solve": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.POINTER(c_int32), c_void_p, c_void_p,
                               ctypes.POINTER(StfasStats)]),
     "stfas_step_forward": (c_int32, [ctypes.POINTER(StfasProblem), c_void_p, c_void_p, c_void_p, c_void_p,

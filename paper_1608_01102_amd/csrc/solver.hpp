@@ -362,6 +362,14 @@ inline void traced(Tracer& tr, hipStream_t st, int kind, double bytes, Launch&& 
     tr.bytes += bytes;
 }
 
+// Pinned host buffer for scalar readbacks, one per host thread, kept for the
+// life of the process (freeing pinned memory would synchronise the device).
+inline double* thread_pinned() {
+    thread_local double* buf = nullptr;
+    if (!buf) HCK(hipHostMalloc((void**)&buf, 64 * sizeof(double), hipHostMallocDefault));
+    return buf;
+}
+
 class SolverBase {
 public:
     virtual ~SolverBase() {}
@@ -369,6 +377,7 @@ public:
     hipStream_t st = nullptr;
     size_t bytes = 0;
     char* mem = nullptr;
+    bool owns_mem = true;
     virtual size_t plan() = 0;
     virtual bool valid() const = 0;
     virtual void carve(char* base) = 0;
@@ -467,9 +476,7 @@ public:
         L = stfas_levels(g0);
         pois.init(g0, p.N, s);
     }
-    ~Solver() override {
-        if (host_out) (void)hipHostFree(host_out);
-    }
+    ~Solver() override {}
 
     int nlevels() const override { return (int)L.size(); }
     const Grid& level(int l) const override { return L[l]; }
@@ -555,7 +562,7 @@ public:
     }
 
     void init_tables() override {
-        HCK(hipHostMalloc((void**)&host_out, 64 * sizeof(double), hipHostMallocDefault));
+        host_out = thread_pinned();
         TFactors f = temporal_factors(N, P.dt, P.K / P.r);
         upload(t_diag, f.diag);
         upload(t_sub, f.sub);

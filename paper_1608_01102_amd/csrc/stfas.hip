@@ -189,11 +189,34 @@ stfas_status stfas_create(const stfas_problem* prob, void* hip_stream, stfas_ctx
     });
 }
 
+stfas_status stfas_create_in(const stfas_problem* prob, void* hip_stream, void* workspace, size_t workspace_bytes,
+                             stfas_ctx** out) {
+    if (!out) return STFAS_E_INVALID;
+    *out = nullptr;
+    Params p;
+    if (!resolve(prob, p) || !workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return STFAS_E_INVALID;
+    return guard([&]() -> stfas_status {
+        auto c = std::make_unique<stfas_ctx>();
+        c->s = make_solver(p, (hipStream_t)hip_stream);
+        if (!c->s->valid()) return STFAS_E_INVALID;
+        const size_t bytes = c->s->plan();
+        if (workspace_bytes < bytes) return STFAS_E_INVALID;
+        HCK(hipGetDevice(&c->device));
+        c->s->mem = (char*)workspace;
+        c->s->bytes = bytes;
+        c->s->owns_mem = false;
+        c->s->carve((char*)workspace);
+        c->s->init_tables();
+        *out = c.release();
+        return STFAS_OK;
+    });
+}
+
 void stfas_destroy(stfas_ctx* ctx) {
     if (!ctx) return;
     if (ctx->s && ctx->s->mem) {
         (void)hipStreamSynchronize(ctx->s->st);
-        (void)hipFree(ctx->s->mem);
+        if (ctx->s->owns_mem) (void)hipFree(ctx->s->mem);
     }
     delete ctx;
 }

@@ -63,7 +63,7 @@ def footprint(req, precision):
     cells, faces = S.counts(prob)
     word = 8 if precision == "fp64" else 4
     io = word * (cells * (1 + len(req.key_steps)) + faces * req.num_steps)
-    return ws + io
+    return ws + 256 + io            # + alignment slack of the workspace
 
 
 def _solve_on(req, precision, stream):
@@ -71,7 +71,11 @@ def _solve_on(req, precision, stream):
     prob = problem_of(req, precision)
     dt = S.dtype_of(prob)
     with torch.cuda.stream(stream):
-        ctx = S.stfas_create(prob, stream=stream)
+        # workspace from torch's caching allocator on this stream: no device
+        # allocation or free (both would wait for the other slots) per request
+        ws = torch.empty(S.stfas_workspace_bytes(prob) + 256, dtype=torch.uint8, device="cuda")
+        off = (-ws.data_ptr()) % 256
+        ctx = S.stfas_create_in(prob, ws[off:], stream=stream)
         try:
             rho0 = torch.tensor(req.rho0, dtype=dt, device="cuda").contiguous()
             keys = torch.tensor(req.key_rho, dtype=dt, device="cuda").contiguous()

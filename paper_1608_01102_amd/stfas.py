@@ -90,24 +90,33 @@ def stfas_build_info():
 class Context:
     """Owns one stfas_ctx (its workspace lives on the device until destroy)."""
 
-    def __init__(self, prob, stream=None):
+    def __init__(self, prob, stream=None, workspace=None):
         lib = _lib.load()
         self.prob = prob
         self.dtype = dtype_of(prob)
         self.stream = torch.cuda.current_stream() if stream is None else stream
         self.cells, self.faces = counts(prob)
         self.N = prob.num_steps
+        self.workspace = workspace          # keeps caller memory alive until destroy
         h = ctypes.c_void_p()
-        check(lib.stfas_create(ctypes.byref(prob), _stream(self.stream), ctypes.byref(h)), "stfas_create")
+        if workspace is None:
+            check(lib.stfas_create(ctypes.byref(prob), _stream(self.stream), ctypes.byref(h)), "stfas_create")
+        else:
+            if not (isinstance(workspace, torch.Tensor) and workspace.is_cuda and workspace.is_contiguous()):
+                raise TypeError("workspace must be a contiguous device tensor")
+            nbytes = workspace.numel() * workspace.element_size()
+            check(lib.stfas_create_in(ctypes.byref(prob), _stream(self.stream), ctypes.c_void_p(workspace.data_ptr()),
+                                      nbytes, ctypes.byref(h)), "stfas_create_in")
         self.handle = h
 
     def __del__(self):
         self.destroy()
 
     def destroy(self):
-        if getattr(self, "handle", None) and self.handle.value:
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
             _lib.load().stfas_destroy(self.handle)
             self.handle = ctypes.c_void_p()
+        self.workspace = None
 
     def num_levels(self):
         return int(_lib.load().stfas_num_levels(self.handle))
@@ -131,6 +140,12 @@ class Context:
 
 def stfas_create(prob, stream=None):
     return Context(prob, stream)
+
+
+def stfas_create_in(prob, workspace, stream=None):
+    """Context on caller device memory (a contiguous tensor of at least
+    stfas_workspace_bytes(prob) bytes, 256-byte aligned)."""
+    return Context(prob, stream, workspace)
 
 
 def stfas_destroy(ctx):
