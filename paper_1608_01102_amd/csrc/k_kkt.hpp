@@ -254,110 +254,168 @@ __global__ void k_scgs_thomas(Grid g, int N, ColourSet cs, const T* __restrict__
     }
 }
 
-// Fused face solve for problems whose columns fit in LDS: one wave of 64
-// (cell, face) columns per workgroup; the projection (P r)_k is formed on the
-// fly from the cell's face residuals, the forward elimination keeps the
-// column in LDS (scol[k][lane]) and the back substitution applies omega dx.
-// Dynamic LDS: 3 * 2N Thomas factors + 2N * 64 column values.
-template <typename T, int D>
-__global__ void __launch_bounds__(64) k_scgs_faces_lds(Grid g, int N, ColourSet cs, const T* __restrict__ r1,
-                                                      const T* __restrict__ r2, const T* __restrict__ r3,
-                                                      const T* __restrict__ r4, T* v, T* u,
-                                                      const T* __restrict__ tsub, const T* __restrict__ tcp,
-                                                      const T* __restrict__ tinv, T omega) {
-    extern __shared__ unsigned char smem_raw[];
-    T* tc = reinterpret_cast<T*>(smem_raw);
+// Whole colour in one kernel, time-parallel.  One lane per (cell, chunk of
+// L <= CH consecutive blocks, chunks starting at even blocks); the G lanes
+// of a cell are adjacent.  The lane reads its cell's 2d face residuals once
+// per block, forms ghat^T r and P r for every face, and runs the two Thomas
+// passes of all 2d faces together (T is shared, so the running product of
+// multipliers is too); chunk maps are joined across lanes by a log2(G)-step
+// shuffle scan.  The same lane applies the pressure correction of its
+// blocks, which needs only the divergence residual of the neighbouring
+// blocks.  Every load is unconditional (blocks past the end read a clamped
+// block of the same parity and are masked), so all of a lane's loads are in
+// flight together.
+template <typename T, int D, int G, int CH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_scgs_colour(Grid g, int N, int L, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ r2,
+              const T* __restrict__ r3, const T* __restrict__ r4, T* v, T* pb, T* u, T* p,
+              const T* __restrict__ tdiag, const T* __restrict__ tsub, const T* __restrict__ tsup,
+              const T* __restrict__ tcp, const T* __restrict__ tinv, T omega) {
+    constexpr int NF = 2 * D;
     const int M = 2 * N;
-    for (int e = threadIdx.x; e < M; e += blockDim.x) {
-        tc[e] = tsub[e];
-        tc[M + e] = tinv[e];
-        tc[2 * M + e] = tcp[e];
-    }
-    __syncthreads();
-    const T* sub = tc;
-    const T* inv = tc + M;
-    const T* cp = tc + 2 * M;
-    T* scol = tc + 3 * M + threadIdx.x;          // column of this lane, stride 64
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ncol = cs.total * 2 * D;
-    if (col >= ncol) return;
-    const int q = col / (2 * D), s = col % (2 * D);
+    const int lane = threadIdx.x % G;
+    const int q = (blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const bool active = q < cs.total;
+    // lanes past the last cell work on the last cell and write nothing
     int i, j, k;
-    colour_cell(cs, q, i, j, k);
+    colour_cell(cs, min(q, cs.total - 1), i, j, k);
     CellFaces<D> cf;
     cell_faces<D>(g, i, j, k, cf);
-    if (!pick(cf.inner, s)) return;
     const T ginv = (T)1 / sqrt((T)cf.m);
-    T gh[2 * D];
-#pragma unroll
-    for (int t = 0; t < 2 * D; ++t) gh[t] = cf.inner[t] ? ((t & 1) ? ginv : -ginv) : (T)0;
-    const T ghs = (s & 1) ? ginv : -ginv;
     const T gn_inv = (T)g.h * ginv;
+    T gh[NF];
+#pragma unroll
+    for (int e = 0; e < NF; ++e) gh[e] = cf.inner[e] ? ((e & 1) ? ginv : -ginv) : (T)0;
     const long F = g.nface, C = g.ncell;
     const int c = cell_index(g, i, j, k);
-    const int own = pick(cf.face, s);
-    // wall slots read a valid interior-or-wall index with weight 0
-    int fidx[2 * D];
+    const int k0 = lane * L;
+    const int len = active ? max(0, min(L, M - k0)) : 0;
+    // ---- loads: face residuals, old unknowns, divergence residual of the
+    // blocks k0-1 .. k0+CH, old pressures, temporal factors
+    T rv[CH][NF], fo[CH][NF], po[CH], sk[CH + 2];
+    T iv[CH], cm[CH], td[CH], ts[CH], tp[CH];
 #pragma unroll
-    for (int t = 0; t < 2 * D; ++t) fidx[t] = cf.face[t];
-    constexpr int U = (sizeof(T) == 8 || D == 3) ? 4 : 8;
-    T dprev = 0;
-    int k0 = 0;
-    for (; k0 + U <= M; k0 += U) {
-        T rv[U][2 * D];
+    for (int t = 0; t < CH; ++t) {
+        const int kk = min(k0 + t, M - 2 + (t & 1));
+        const long jf = (long)(kk >> 1) * F;
+        const T* r = (t & 1) ? r1 : r3;
+        const T* x = (t & 1) ? v : u;
 #pragma unroll
-        for (int t = 0; t < U; ++t) {
+        for (int e = 0; e < NF; ++e) {
+            rv[t][e] = r[jf + cf.face[e]];
+            fo[t][e] = x[jf + cf.face[e]];
+        }
+        po[t] = ((t & 1) ? pb : p)[(long)(kk >> 1) * C + c];
+        iv[t] = tinv[kk];
+        cm[t] = tcp[kk];
+        td[t] = tdiag[kk];
+        ts[t] = tsub[kk];
+        tp[t] = tsup[kk];
+    }
+#pragma unroll
+    for (int t = -1; t <= CH; ++t) {
+        // block k0+t, clamped into range with its parity kept (odd t: v-block)
+        const int kk = (t & 1) ? min(max(k0 + t, 1), M - 1) : min(k0 + t, M - 2);
+        sk[t + 1] = ((t & 1) ? r2 : r4)[(long)(kk >> 1) * C + c];
+    }
+    // ---- projection: gr_t = ghat^T r_t, P r_t = r_t - ghat gr_t
+    T gr[CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+        T acc = 0;
+#pragma unroll
+        for (int e = 0; e < NF; ++e) acc += gh[e] * rv[t][e];
+        gr[t] = acc;
+#pragma unroll
+        for (int e = 0; e < NF; ++e) rv[t][e] -= gh[e] * acc;
+    }
+    // ---- forward elimination, chunk-local from a zero carry
+    T pv[CH], val[NF], prod = 1;
+#pragma unroll
+    for (int e = 0; e < NF; ++e) val[e] = 0;
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+        const bool on = t < len;
+        const T a = -ts[t] * iv[t];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) {
+            val[e] = on ? a * val[e] + rv[t][e] * iv[t] : val[e];
+            rv[t][e] = val[e];
+        }
+        prod = on ? a * prod : prod;
+        pv[t] = prod;
+    }
+    T A = prod;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+        const T Ap = __shfl_up(A, off, G);
+        T Bp[NF];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) Bp[e] = __shfl_up(val[e], off, G);
+        if (lane >= off) {
+#pragma unroll
+            for (int e = 0; e < NF; ++e) val[e] = A * Bp[e] + val[e];
+            A = A * Ap;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < NF; ++e) {
+        T cin = __shfl_up(val[e], 1, G);
+        cin = lane == 0 ? (T)0 : cin;
+#pragma unroll
+        for (int t = 0; t < CH; ++t) rv[t][e] += pv[t] * cin;
+    }
+    // ---- back substitution, chunk-local from a zero carry
+    prod = 1;
+#pragma unroll
+    for (int e = 0; e < NF; ++e) val[e] = 0;
+#pragma unroll
+    for (int t = CH - 1; t >= 0; --t) {
+        const bool on = t < len;
+        const T cc = -cm[t];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) {
+            val[e] = on ? cc * val[e] + rv[t][e] : val[e];
+            rv[t][e] = val[e];
+        }
+        prod = on ? cc * prod : prod;
+        pv[t] = prod;
+    }
+    A = prod;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+        const T An = __shfl_down(A, off, G);
+        T Bn[NF];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) Bn[e] = __shfl_down(val[e], off, G);
+        if (lane + off < G) {
+#pragma unroll
+            for (int e = 0; e < NF; ++e) val[e] = A * Bn[e] + val[e];
+            A = A * An;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < NF; ++e) {
+        T cin = __shfl_down(val[e], 1, G);
+        cin = lane == G - 1 ? (T)0 : cin;
+#pragma unroll
+        for (int t = 0; t < CH; ++t) rv[t][e] += pv[t] * cin;
+    }
+    // ---- apply the corrections of this chunk (relaxed by omega)
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+        if (t < len) {
             const int kk = k0 + t;
-            const T* r = ((kk & 1) ? r1 : r3) + (long)(kk >> 1) * F;
-#pragma unroll
-            for (int e = 0; e < 2 * D; ++e) rv[t][e] = r[fidx[e]];
-        }
-#pragma unroll
-        for (int t = 0; t < U; ++t) {
-            T gr = 0, ro = 0;
-#pragma unroll
-            for (int e = 0; e < 2 * D; ++e) {
-                gr += gh[e] * rv[t][e];
-                ro = (e == s) ? rv[t][e] : ro;       // own face, selected without a runtime index
-            }
-            const T pr = ro - ghs * gr;
-            dprev = (pr - sub[k0 + t] * dprev) * inv[k0 + t];
-            scol[(k0 + t) * 64] = dprev;
-        }
-    }
-    for (; k0 < M; ++k0) {
-        const T* r = ((k0 & 1) ? r1 : r3) + (long)(k0 >> 1) * F;
-        T gr = 0;
-#pragma unroll
-        for (int e = 0; e < 2 * D; ++e) gr += gh[e] * r[fidx[e]];
-        const T pr = r[own] - ghs * gr;
-        dprev = (pr - sub[k0] * dprev) * inv[k0];
-        scol[k0 * 64] = dprev;
-    }
-    constexpr int V = 16;
-    T x = 0;
-    int k1 = M - 1;
-    for (; k1 - (V - 1) >= 0; k1 -= V) {
-        T sk[V], fv[V];
-#pragma unroll
-        for (int t = 0; t < V; ++t) {
-            const int kk = k1 - t;
             const long jj = kk >> 1;
-            sk[t] = (kk & 1) ? r2[jj * C + c] : r4[jj * C + c];
-            fv[t] = ((kk & 1) ? v : u)[jj * F + own];
-        }
+            T* x = (t & 1) ? v : u;
 #pragma unroll
-        for (int t = 0; t < V; ++t) {
-            const int kk = k1 - t;
-            x = scol[kk * 64] - cp[kk] * x;
-            ((kk & 1) ? v : u)[(long)(kk >> 1) * F + own] = fv[t] + omega * (x + ghs * sk[t] * gn_inv);
+            for (int e = 0; e < NF; ++e)
+                if (cf.inner[e]) x[jj * F + cf.face[e]] = fo[t][e] + omega * (rv[t][e] + gh[e] * sk[t + 1] * gn_inv);
+            T acc = td[t] * sk[t + 1];
+            if (kk > 0) acc += ts[t] * sk[t];
+            if (kk < M - 1) acc += tp[t] * sk[t + 2];
+            ((t & 1) ? pb : p)[jj * C + c] = po[t] + omega * (acc * gn_inv - gr[t]) * gn_inv;
         }
-    }
-    for (; k1 >= 0; --k1) {
-        const long jj = k1 >> 1;
-        x = scol[k1 * 64] - cp[k1] * x;
-        const T sk = (k1 & 1) ? r2[jj * C + c] : r4[jj * C + c];
-        ((k1 & 1) ? v : u)[jj * F + own] += omega * (x + ghs * sk * gn_inv);
     }
 }
 

@@ -328,7 +328,8 @@ enum TraceKernel {
     TR_RBGS = 5,
     TR_ADVECT = 6,
     TR_KKT_CELLS = 7,
-    TR_SCGS_CELLS = 8
+    TR_SCGS_CELLS = 8,
+    TR_SCGS_COLOUR = 9
 };
 
 struct Tracer {
@@ -421,6 +422,52 @@ public:
         *bytes = tr.bytes;
     }
 };
+
+// Launch shape of the whole-colour SCGS kernel for 2N = M blocks and `cells`
+// cells of the colour: G lanes per cell (a power of two <= 64), chunks of L
+// blocks (even), unrolled to CH >= L.  The longest chunk is bounded by the
+// registers a lane holds (2d face values per block); small levels take more
+// lanes per cell so that the launch has enough lanes to hide latency.
+// Returns false when 2N does not fit in 64 chunks (the two-kernel path).
+template <typename T, int D>
+inline bool colour_shape(int M, long cells, int& G, int& L, int& CH) {
+    const int chmax = (sizeof(T) == 4 && D == 2) ? 16 : 8;
+    G = 1;
+    while (G < 64 && (M + G - 1) / G > chmax) G <<= 1;
+    if ((M + G - 1) / G > chmax) return false;
+    while (G < 64 && cells * G < 65536 && (M + 2 * G - 1) / (2 * G) >= 2) G <<= 1;
+    L = (M + G - 1) / G;
+    L += L & 1;
+    while (G > 1 && (long)(G / 2) * L >= M) G >>= 1;
+    CH = L <= 2 ? 2 : (L + 3) & ~3;
+    return CH <= chmax;
+}
+
+template <typename T, int D>
+inline void launch_scgs_colour(int G, int L, int CH, const Grid& g, int N, const ColourSet& cs, const T* r1,
+                               const T* r2, const T* r3, const T* r4, T* v, T* pb, T* u, T* p, const T* tdiag,
+                               const T* tsub, const T* tsup, const T* tcp, const T* tinv, T omega, hipStream_t st) {
+    const long threads = (long)cs.total * G;
+    const int blocks = (int)((threads + 255) / 256);
+    constexpr int CHMAX = (sizeof(T) == 4 && D == 2) ? 16 : 8;
+#define STFAS_COLOUR_CASE(GG, CC)                                                                                \
+    if constexpr (CC <= CHMAX)                                                                                   \
+        if (G == GG && CH == CC)                                                                                 \
+            k_scgs_colour<T, D, GG, CC><<<blocks, 256, 0, st>>>(g, N, L, cs, r1, r2, r3, r4, v, pb, u, p, tdiag,  \
+                                                                tsub, tsup, tcp, tinv, omega);
+#define STFAS_COLOUR_G(GG)                                                                                       \
+    STFAS_COLOUR_CASE(GG, 2) STFAS_COLOUR_CASE(GG, 4) STFAS_COLOUR_CASE(GG, 8) STFAS_COLOUR_CASE(GG, 12)          \
+    STFAS_COLOUR_CASE(GG, 16)
+    STFAS_COLOUR_G(1)
+    STFAS_COLOUR_G(2)
+    STFAS_COLOUR_G(4)
+    STFAS_COLOUR_G(8)
+    STFAS_COLOUR_G(16)
+    STFAS_COLOUR_G(32)
+    STFAS_COLOUR_G(64)
+#undef STFAS_COLOUR_G
+#undef STFAS_COLOUR_CASE
+}
 
 // out[b] += scale J_S(v[b])^T y[b] for `batch` slices (tiled scatter).
 template <typename T, int D>
@@ -713,26 +760,25 @@ public:
             const int nf = cs.total * 2 * D;
             const double inner = (double)colour_inner_faces(g, colour);
             const double sz = sizeof(T), M2 = 2.0 * N;
-            const size_t lds = (size_t)(3 * 2 * N + 2 * N * 64) * sizeof(T);
-            if (lds <= 65536) {
-                // fused: read r1/r3 at the colour's faces, r2/r4 at its cells, update u/v
-                traced(tr, st, l == 0 ? TR_SCGS_THOMAS : TR_NONE, sz * M2 * (inner * 3 + cs.total), [&] {
-                    k_scgs_faces_lds<T, D><<<blocks_for(nf, 64), 64, lds, st>>>(g, N, cs, q.r1, q.r2, q.r3, q.r4,
-                                                                               q.v, q.u, t_sub, t_cp, t_inv,
-                                                                               (T)P.omega);
+            int G = 1, Lc = 0, CH = 0;
+            if (colour_shape<T, D>(2 * N, cs.total, G, Lc, CH)) {
+                // one kernel: read r1..r4 once, update u/v at the faces and p/pbar at the cells
+                traced(tr, st, l == 0 ? TR_SCGS_COLOUR : TR_NONE, sz * M2 * (inner * 3 + cs.total * 3), [&] {
+                    launch_scgs_colour<T, D>(G, Lc, CH, g, N, cs, q.r1, q.r2, q.r3, q.r4, q.v, q.pb, q.u, q.p,
+                                             t_diag, t_sub, t_sup, t_cp, t_inv, (T)P.omega, st);
                 });
-            } else {
-                // project: read r1/r3 at the colour's faces, write (P r)
-                traced(tr, st, l == 0 ? TR_SCGS_PROJECT : TR_NONE, sz * M2 * inner * 2, [&] {
-                    k_scgs_project<T, D><<<blocks_for((long)nf * 2 * N, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r3,
-                                                                                          scgs_scratch);
-                });
-                // thomas: read (P r), read the cells' divergence residual, update u/v at the faces
-                traced(tr, st, l == 0 ? TR_SCGS_THOMAS : TR_NONE, sz * M2 * (inner * 3 + cs.total), [&] {
-                    k_scgs_thomas<T, D><<<blocks_for(nf, 64), 64, 3 * 2 * N * sizeof(T), st>>>(
-                        g, N, cs, q.r2, q.r4, q.v, q.u, t_sub, t_cp, t_inv, (T)P.omega, scgs_scratch);
-                });
+                continue;
             }
+            // long horizons: project: read r1/r3 at the colour's faces, write (P r)
+            traced(tr, st, l == 0 ? TR_SCGS_PROJECT : TR_NONE, sz * M2 * inner * 2, [&] {
+                k_scgs_project<T, D><<<blocks_for((long)nf * 2 * N, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r3,
+                                                                                      scgs_scratch);
+            });
+            // thomas: read (P r), read the cells' divergence residual, update u/v at the faces
+            traced(tr, st, l == 0 ? TR_SCGS_THOMAS : TR_NONE, sz * M2 * (inner * 3 + cs.total), [&] {
+                k_scgs_thomas<T, D><<<blocks_for(nf, 64), 64, 3 * 2 * N * sizeof(T), st>>>(
+                    g, N, cs, q.r2, q.r4, q.v, q.u, t_sub, t_cp, t_inv, (T)P.omega, scgs_scratch);
+            });
             const int nc = cs.total * 2 * N;
             traced(tr, st, l == 0 ? TR_SCGS_CELLS : TR_NONE, sz * M2 * (inner + cs.total * 3), [&] {
                 k_scgs_cells<T, D><<<blocks_for(nc, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r2, q.r3, q.r4, q.pb, q.p,

@@ -167,6 +167,49 @@ def test_scgs_sweep(n, N, prec, omega):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", [((8, 8), 9), ((12, 8), 37), ((8, 8), 300), ((4, 4, 4), 70), ((8, 4), 512), ((4, 4, 4), 200),
+                                 ((4, 4, 4), 300)])
+def test_scgs_sweep_long_horizon(n, N, prec):
+    """Horizons whose 2N blocks split over 2..64 lanes per column, with a
+    ragged last chunk (the face solve runs as a chunked scan in time)."""
+    S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=0.7)
+    kr = K / 1e-2
+    rng = np.random.default_rng(18)
+    L = kkt.Level(g, N, dt, kr, omega=0.7)
+    x = _state(g, N, rng, 0.3, prec)
+    w = _q(_faces(g, rng, N), prec)
+    xd = _dev_state(x, prec)
+    flag(f"scgs long n={n} N={N} {prec}")
+    S.stfas_op_scgs_sweep(ctx, 0, xd, to_dev(w, prec), None)
+    ref = [a.copy() for a in x]
+    scgs.sweep(L, ref, w, [np.zeros_like(a) for a in x])
+    for k in range(4):
+        assert rel(to_np(xd[k]), ref[k]) <= TOL[prec], k
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", [((128, 128), 40)])
+def test_scgs_sweep_benchmark_shapes(n, N, prec):
+    """The 128x128 x 40 grid: the whole-colour kernel takes the launch shape
+    the benchmark times (16 lanes per cell, chunks of 6 blocks)."""
+    S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=0.7)
+    kr = K / 1e-2
+    rng = np.random.default_rng(19)
+    L = kkt.Level(g, N, dt, kr, omega=0.7)
+    x = _state(g, N, rng, 0.3, prec)
+    w = _q(_faces(g, rng, N), prec)
+    xd = _dev_state(x, prec)
+    flag(f"scgs shapes n={n} N={N} {prec}")
+    S.stfas_op_scgs_sweep(ctx, 0, xd, to_dev(w, prec), None)
+    ref = [a.copy() for a in x]
+    scgs.sweep(L, ref, w, [np.zeros_like(a) for a in x])
+    for k in range(4):
+        assert rel(to_np(xd[k]), ref[k]) <= TOL[prec], k
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,N", [((16, 12), 3), ((8, 8, 8), 2)])
 def test_transfers(n, N, prec):
     S, ctx, g, dt, K = _ctx(n, N, prec)
