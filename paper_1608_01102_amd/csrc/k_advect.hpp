@@ -150,16 +150,21 @@ __global__ void k_self_advect(Grid g, T cfl, T dt, const T* __restrict__ v, cons
 
 // out += scale * J_S(v)^T y.  Per interior a-face I: the interpolation
 // weights scatter y_I onto the a-face lattice, and the foot-point term
-// y_I (-dt/h) grad_Y I[v_a] returns to the sampled velocities (component a
-// to v_a[I], component b != a by quarters to the four v_b faces averaged at
-// I).  Contributions that land on wall faces are dropped.
-// The scatter is tiled: each workgroup takes a tile of a-faces of
-// one time slice (blockIdx.y = slice, blockIdx.z = axis a), accumulates all
-// its contributions into LDS windows that cover the tile plus a halo of H
-// nodes on each of the d face lattices, then adds every touched window node
-// to global memory once.  A contribution outside its window (a backtrace
-// longer than the halo) goes straight to global memory.  Far fewer global
-// atomics than one per contribution.
+// g_I = y_I (-dt/h) grad_Y I[v_a] returns to the sampled velocities
+// (component a to v_a[I], component b != a by quarters to the four v_b
+// faces averaged at I).  Contributions that land on wall faces are dropped.
+// Tiled: each workgroup takes a tile of a-faces of one time slice
+// (blockIdx.y = slice, blockIdx.z = axis a).
+//  * weights: accumulated with LDS atomics into a window that covers the
+//    tile plus a halo of H nodes; a weight outside the window (a backtrace
+//    longer than the halo) goes straight to global memory;
+//  * foot-point term: each source stores its d components g_I in an LDS slot
+//    of its own (no atomics), and the flush gathers them: an a-node takes
+//    the slot of the source at the same node, a b-node J (b != a) a quarter
+//    of the b-components of the sources J, J + e_a (when J_b != 0) and
+//    J - e_b, J - e_b + e_a (when J_b != n_b) that lie in the tile;
+//  * flush: every touched a-window node and every b-node next to the tile
+//    is added to global memory once (neighbouring tiles overlap there).
 template <int D>
 struct TileShape;
 template <>
@@ -178,7 +183,12 @@ __global__ void __launch_bounds__(256) k_self_advect_T_tiled(Grid g, T cfl, cons
     constexpr int H = TS::H;
     constexpr int WX = TS::X + 2 * H, WY = TS::Y + 2 * H, WZ = (D == 3) ? TS::Z + 2 * H : 1;
     constexpr int WN = WX * WY * WZ;
-    __shared__ T win[D][WN];
+    constexpr int TN = TS::X * TS::Y * TS::Z;
+    // b-nodes next to the tile: the tile grown by one node on each side
+    constexpr int BX = TS::X + 2, BY = TS::Y + 2, BZ = (D == 3) ? TS::Z + 2 : 1;
+    constexpr int BN = BX * BY * BZ;
+    __shared__ T win[WN];
+    __shared__ T slot[D][TN];
     const int a = blockIdx.z;
     v += blockIdx.y * vs;
     y += blockIdx.y * vs;
@@ -195,18 +205,11 @@ __global__ void __launch_bounds__(256) k_self_advect_T_tiled(Grid g, T cfl, cons
     const int ty0 = ((tile / ntx) % nty) * TS::Y;
     const int tz0 = (D == 3) ? (tile / (ntx * nty)) * TS::Z : 0;
     const int ox = tx0 - H, oy = ty0 - H, oz = (D == 3) ? tz0 - H : 0;
-    for (int e = threadIdx.x; e < D * WN; e += blockDim.x) (&win[0][0])[e] = (T)0;
+    for (int e = threadIdx.x; e < WN; e += blockDim.x) win[e] = (T)0;
     __syncthreads();
     const int lx = threadIdx.x % TS::X, ly = (threadIdx.x / TS::X) % TS::Y, lz = threadIdx.x / (TS::X * TS::Y);
     const int i = tx0 + lx, j = ty0 + ly, k = tz0 + lz;
-    // add val at lattice-b node (ci, cj, ck): into the window when it is inside
-    auto add = [&](int b, int ci, int cj, int ck, T val) {
-        const int wx = ci - ox, wy = cj - oy, wz = ck - oz;
-        if (wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
-            atomicAdd(&win[b][(wz * WY + wy) * WX + wx], val);
-        else
-            atomic_add(out + face_index(g, b, ci, cj, ck), val);
-    };
+    T gs[3] = {0, 0, 0};
     const bool valid = i < ex && j < ey && (D == 2 || k < ez);
     if (valid && face_interior(g, a, i, j, k)) {
         const int f = face_index(g, a, i, j, k);
@@ -221,6 +224,8 @@ __global__ void __launch_bounds__(256) k_self_advect_T_tiled(Grid g, T cfl, cons
             it.setup_disp(idx, dl, ex, ey, ez);
             T gr[3];
             it.grad(v + g.foff[a], gr);
+#pragma unroll
+            for (int b = 0; b < D; ++b) gs[b] = yv * (-cfl) * gr[b];
             const int c0[3] = {it.ax[0].i0, it.ax[1].i0, D == 3 ? it.ax[D - 1].i0 : 0};
 #pragma unroll
             for (int q = 0; q < (1 << D); ++q) {
@@ -229,41 +234,49 @@ __global__ void __launch_bounds__(256) k_self_advect_T_tiled(Grid g, T cfl, cons
                 const int ci = c0[0] + (q & 1), cj = c0[1] + ((q >> 1) & 1), ck = D == 3 ? c0[2] + ((q >> 2) & 1) : 0;
                 const int ca = a == 0 ? ci : (a == 1 ? cj : ck);
                 if (ca == 0 || ca == g.n[a]) continue;          // wall node of the a-lattice
-                add(a, ci, cj, ck, w);
-            }
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                const T gb = yv * (-cfl) * gr[b];
-                if (gb == (T)0) continue;
-                if (b == a) {
-                    add(a, i, j, k, gb);
-                    continue;
-                }
-                const T qv = (T)0.25 * gb;
-                const int ia = i - (a == 0), ja = j - (a == 1), ka = k - (a == 2);
-                const int db0 = (b == 0), db1 = (b == 1), db2 = (b == 2);
-                const int bi = b == 0 ? i : (b == 1 ? j : k);
-                if (bi != 0) {
-                    add(b, ia, ja, ka, qv);
-                    add(b, i, j, k, qv);
-                }
-                if (bi + 1 != g.n[b]) {
-                    add(b, ia + db0, ja + db1, ka + db2, qv);
-                    add(b, i + db0, j + db1, k + db2, qv);
-                }
+                const int wx = ci - ox, wy = cj - oy, wz = ck - oz;
+                if (wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
+                    atomicAdd(&win[(wz * WY + wy) * WX + wx], w);
+                else
+                    atomic_add(out + face_index(g, a, ci, cj, ck), w);
             }
         }
     }
+#pragma unroll
+    for (int b = 0; b < D; ++b) slot[b][threadIdx.x] = gs[b];
     __syncthreads();
-    // flush: every nonzero window node inside its lattice, once
-    for (int e = threadIdx.x; e < D * WN; e += blockDim.x) {
-        const int b = e / WN, r = e % WN;
-        const T val = win[b][r];
+    // foot-point component b of the tile's source at a-lattice node (si, sj, sk), 0 outside the tile
+    auto src = [&](int b, int si, int sj, int sk) -> T {
+        const int px = si - tx0, py = sj - ty0, pz = sk - tz0;
+        if (px < 0 || px >= TS::X || py < 0 || py >= TS::Y || pz < 0 || pz >= TS::Z) return (T)0;
+        return slot[b][(pz * TS::Y + py) * TS::X + px];
+    };
+    // flush the a-window: weights plus the foot-point term of the source at the node
+    for (int e = threadIdx.x; e < WN; e += blockDim.x) {
+        const int ci = ox + e % WX, cj = oy + (e / WX) % WY, ck = oz + e / (WX * WY);
+        T val = win[e] + src(a, ci, cj, ck);
         if (val == (T)0) continue;
-        const int ci = ox + r % WX, cj = oy + (r / WX) % WY, ck = oz + r / (WX * WY);
-        if (ci < 0 || cj < 0 || ck < 0) continue;
-        if (ci >= face_ext(g, b, 0) || cj >= face_ext(g, b, 1) || (D == 3 && ck >= face_ext(g, b, 2))) continue;
-        atomic_add(out + face_index(g, b, ci, cj, ck), val);
+        if (ci < 0 || cj < 0 || ck < 0 || ci >= ex || cj >= ey || (D == 3 && ck >= ez)) continue;
+        atomic_add(out + face_index(g, a, ci, cj, ck), val);
+    }
+    // b-nodes next to the tile: gather the quarters of the b-components
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        if (b == a) continue;
+        const int da0 = a == 0, da1 = a == 1, da2 = a == 2;
+        const int db0 = b == 0, db1 = b == 1, db2 = b == 2;
+        const int bx = face_ext(g, b, 0), by = face_ext(g, b, 1), bz = face_ext(g, b, 2);
+        for (int e = threadIdx.x; e < BN; e += blockDim.x) {
+            const int ci = tx0 - 1 + e % BX, cj = ty0 - 1 + (e / BX) % BY, ck = (D == 3) ? tz0 - 1 + e / (BX * BY) : 0;
+            if (ci < 0 || cj < 0 || ck < 0 || ci >= bx || cj >= by || (D == 3 && ck >= bz)) continue;
+            const int Jb = b == 0 ? ci : (b == 1 ? cj : ck);
+            T s = 0;
+            if (Jb != 0) s += src(b, ci, cj, ck) + src(b, ci + da0, cj + da1, ck + da2);
+            if (Jb != g.n[b])
+                s += src(b, ci - db0, cj - db1, ck - db2) + src(b, ci - db0 + da0, cj - db1 + da1, ck - db2 + da2);
+            if (s == (T)0) continue;
+            atomic_add(out + face_index(g, b, ci, cj, ck), (T)0.25 * s);
+        }
     }
 }
 
