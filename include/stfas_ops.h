@@ -109,7 +109,9 @@ stfas_status stfas_op_ao(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
  * projection, 3 KKT face rows, 4 velocity-advection transpose, 5 Poisson
  * red-black sweep, 6 density advection, 7 KKT cell rows, 8 SCGS pressure
  * (1, 2 and 8 run only for horizons too long for the fused kernel), 9 SCGS
- * whole-colour kernel (faces and pressure of one colour, time-parallel).
+ * whole-colour kernel (faces and pressure of one colour, time-parallel),
+ * 10 the one-launch residual that precedes each fused colour pass (face
+ * rows, cell rows and the velocity-advection transpose side by side).
  * stfas_trace_read synchronises and returns the recorded launch count,
  * their summed duration in milliseconds and their algorithmic bytes. */
 stfas_status stfas_trace_enable(stfas_ctx* ctx, int32_t kernel, int32_t max_launches);

@@ -177,8 +177,8 @@ struct TileShape<3> {
 };
 
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_self_advect_T_tiled(Grid g, T cfl, const T* __restrict__ v,
-                                                             const T* __restrict__ y, T scale, T* out, long vs) {
+__device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restrict__ v, const T* __restrict__ y,
+                                          T scale, T* out, long vs, int tile, int slice, int a) {
     using TS = TileShape<D>;
     constexpr int H = TS::H;
     constexpr int WX = TS::X + 2 * H, WY = TS::Y + 2 * H, WZ = (D == 3) ? TS::Z + 2 * H : 1;
@@ -189,15 +189,13 @@ __global__ void __launch_bounds__(256) k_self_advect_T_tiled(Grid g, T cfl, cons
     constexpr int BN = BX * BY * BZ;
     __shared__ T win[WN];
     __shared__ T slot[D][TN];
-    const int a = blockIdx.z;
-    v += blockIdx.y * vs;
-    y += blockIdx.y * vs;
-    out += blockIdx.y * vs;
+    v += slice * vs;
+    y += slice * vs;
+    out += slice * vs;
     // tile origin in a-lattice coordinates
     const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
     const int ntx = (ex + TS::X - 1) / TS::X, nty = (ey + TS::Y - 1) / TS::Y;
     const int ntz = (D == 3) ? (ez + TS::Z - 1) / TS::Z : 1;
-    const int tile = blockIdx.x;
     // the launch covers the axis with the most tiles; the others' extra
     // workgroups have nothing to do (uniform exit before any barrier)
     if (tile >= ntx * nty * ntz) return;
@@ -278,6 +276,12 @@ __global__ void __launch_bounds__(256) k_self_advect_T_tiled(Grid g, T cfl, cons
             atomic_add(out + face_index(g, b, ci, cj, ck), (T)0.25 * s);
         }
     }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_self_advect_T_tiled(Grid g, T cfl, const T* __restrict__ v,
+                                                             const T* __restrict__ y, T scale, T* out, long vs) {
+    self_advect_T_tile<T, D>(g, cfl, v, y, scale, out, vs, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 }  // namespace stfas

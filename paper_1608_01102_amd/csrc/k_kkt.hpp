@@ -17,14 +17,13 @@
 
 namespace stfas {
 
-// Face rows F1, F3 without the J_S^T term of F1 (added by k_self_advect_T_tiled).
+// Face rows F1, F3 of face f, slice j, without the J_S^T term of F1 (added
+// by the velocity-advection transpose).
 template <typename T, int D>
-__global__ void k_kkt_faces(Grid g, int N, T dt, T kr, T cfl, T sgn, const T* __restrict__ v,
-                            const T* __restrict__ pb, const T* __restrict__ u, const T* __restrict__ p,
-                            const T* __restrict__ w, const T* res1, const T* res3, T* out1, T* out3) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= g.nface) return;
-    const int j = blockIdx.y;
+__device__ inline void kkt_face(const Grid& g, int N, T dt, T kr, T cfl, T sgn, const T* __restrict__ v,
+                                const T* __restrict__ pb, const T* __restrict__ u, const T* __restrict__ p,
+                                const T* __restrict__ w, const T* res1, const T* res3, T* out1, T* out3, int f,
+                                int j) {
     const long F = g.nface, C = g.ncell;
     int a, i, jj, k;
     face_decode(g, f, a, i, jj, k);
@@ -58,13 +57,10 @@ __global__ void k_kkt_faces(Grid g, int N, T dt, T kr, T cfl, T sgn, const T* __
     out3[e] = (res3 ? res3[e] : (T)0) + sgn * f3;
 }
 
-// Cell rows F2 = D v_i, F4 = D u_i.
+// Cell rows F2 = D v_j, F4 = D u_j of cell c, slice j.
 template <typename T, int D>
-__global__ void k_kkt_cells(Grid g, T sgn, const T* __restrict__ v, const T* __restrict__ u, const T* res2,
-                            const T* res4, T* out2, T* out4) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.ncell) return;
-    const int j = blockIdx.y;
+__device__ inline void kkt_cell(const Grid& g, T sgn, const T* __restrict__ v, const T* __restrict__ u,
+                                const T* res2, const T* res4, T* out2, T* out4, int c, int j) {
     const long F = g.nface;
     const int i = c % g.n[0], jj = (c / g.n[0]) % g.n[1], k = c / (g.n[0] * g.n[1]);
     const T* vj = v + j * F;
@@ -80,6 +76,67 @@ __global__ void k_kkt_cells(Grid g, T sgn, const T* __restrict__ v, const T* __r
     const long e = (long)j * g.ncell + c;
     out2[e] = (res2 ? res2[e] : (T)0) + sgn * dv * ih;
     out4[e] = (res4 ? res4[e] : (T)0) + sgn * du * ih;
+}
+
+template <typename T, int D>
+__global__ void k_kkt_faces(Grid g, int N, T dt, T kr, T cfl, T sgn, const T* __restrict__ v,
+                            const T* __restrict__ pb, const T* __restrict__ u, const T* __restrict__ p,
+                            const T* __restrict__ w, const T* res1, const T* res3, T* out1, T* out3) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= g.nface) return;
+    kkt_face<T, D>(g, N, dt, kr, cfl, sgn, v, pb, u, p, w, res1, res3, out1, out3, f, blockIdx.y);
+}
+
+template <typename T, int D>
+__global__ void k_kkt_cells(Grid g, T sgn, const T* __restrict__ v, const T* __restrict__ u, const T* res2,
+                            const T* res4, T* out2, T* out4) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell) return;
+    kkt_cell<T, D>(g, sgn, v, u, res2, res4, out2, out4, c, blockIdx.y);
+}
+
+// The whole residual of one level in one launch, for the SCGS colour passes:
+// blocks [0, nbf N) face rows, then [.., + nbc N) cell rows, then the tiles
+// of the velocity-advection transpose (slices 0..N-2, d axes), which add
+// their J_S^T term into t1 (zero on entry) instead of F1, then blocks that
+// clear t1z (the other t1 buffer, for the next pass).  All four parts read
+// only the state, so they run side by side; the SCGS pass reads F1 + t1.
+struct KktSplit {
+    int nbf, nbc, ntile, nbz;
+};
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T cfl, T sgn, KktSplit ks,
+                                                   const T* __restrict__ v, const T* __restrict__ pb,
+                                                   const T* __restrict__ u, const T* __restrict__ p,
+                                                   const T* __restrict__ w, const T* res1, const T* res2,
+                                                   const T* res3, const T* res4, T* out1, T* out2, T* out3,
+                                                   T* out4, T* t1, T* t1z) {
+    long b = blockIdx.x;
+    const long bf = (long)ks.nbf * N, bc = (long)ks.nbc * N, bt = (long)ks.ntile * (N - 1) * D;
+    if (b < bf) {
+        const int f = (int)(b % ks.nbf) * 256 + threadIdx.x;
+        if (f < g.nface) kkt_face<T, D>(g, N, dt, kr, cfl, sgn, v, pb, u, p, w, res1, res3, out1, out3, f, (int)(b / ks.nbf));
+        return;
+    }
+    b -= bf;
+    if (b < bc) {
+        const int c = (int)(b % ks.nbc) * 256 + threadIdx.x;
+        if (c < g.ncell) kkt_cell<T, D>(g, sgn, v, u, res2, res4, out2, out4, c, (int)(b / ks.nbc));
+        return;
+    }
+    b -= bc;
+    if (b < bt) {
+        // tile, slice, axis; y = u_{j+1} (the u slots shifted by one), scale -sgn/dt
+        const int tile = (int)(b % ks.ntile);
+        const int slice = (int)((b / ks.ntile) % (N - 1));
+        const int a = (int)(b / ((long)ks.ntile * (N - 1)));
+        self_advect_T_tile<T, D>(g, cfl, v, u + g.nface, -sgn / dt, t1, g.nface, tile, slice, a);
+        return;
+    }
+    b -= bt;
+    const long tot = (long)N * g.nface;
+    for (long e = b * 256 + threadIdx.x; e < tot; e += (long)ks.nbz * 256) t1z[e] = (T)0;
 }
 
 // ---------------------------------------------------------------- SCGS
@@ -254,7 +311,8 @@ __global__ void k_scgs_thomas(Grid g, int N, ColourSet cs, const T* __restrict__
     }
 }
 
-// Whole colour in one kernel, time-parallel.  One lane per (cell, chunk of
+// Whole colour in one kernel, time-parallel; the F1 rows arrive split as
+// r1 + t1 (k_kkt_split).  One lane per (cell, chunk of
 // L <= CH consecutive blocks, chunks starting at even blocks); the G lanes
 // of a cell are adjacent.  The lane reads its cell's 2d face residuals once
 // per block, forms ghat^T r and P r for every face, and runs the two Thomas
@@ -267,8 +325,8 @@ __global__ void k_scgs_thomas(Grid g, int N, ColourSet cs, const T* __restrict__
 // flight together.
 template <typename T, int D, int G, int CH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
-k_scgs_colour(Grid g, int N, int L, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ r2,
-              const T* __restrict__ r3, const T* __restrict__ r4, T* v, T* pb, T* u, T* p,
+k_scgs_colour(Grid g, int N, int L, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ t1,
+              const T* __restrict__ r2, const T* __restrict__ r3, const T* __restrict__ r4, T* v, T* pb, T* u, T* p,
               const T* __restrict__ tdiag, const T* __restrict__ tsub, const T* __restrict__ tsup,
               const T* __restrict__ tcp, const T* __restrict__ tinv, T omega) {
     constexpr int NF = 2 * D;
@@ -298,11 +356,11 @@ k_scgs_colour(Grid g, int N, int L, ColourSet cs, const T* __restrict__ r1, cons
     for (int t = 0; t < CH; ++t) {
         const int kk = min(k0 + t, M - 2 + (t & 1));
         const long jf = (long)(kk >> 1) * F;
-        const T* r = (t & 1) ? r1 : r3;
         const T* x = (t & 1) ? v : u;
 #pragma unroll
         for (int e = 0; e < NF; ++e) {
-            rv[t][e] = r[jf + cf.face[e]];
+            // F1 rows (v-blocks) are split into r1 and the J_S^T term t1
+            rv[t][e] = (t & 1) ? r1[jf + cf.face[e]] + t1[jf + cf.face[e]] : r3[jf + cf.face[e]];
             fo[t][e] = x[jf + cf.face[e]];
         }
         po[t] = ((t & 1) ? pb : p)[(long)(kk >> 1) * C + c];

@@ -225,10 +225,82 @@ struct Poisson {
     int Bmax = 1;
     hipStream_t st = nullptr;
 
+    // single-launch projection in LDS (one workgroup per slice), when the
+    // hierarchy fits: at least two levels, a coarsest level of <= 256 cells,
+    // <= 16384 finest cells (16 per thread in registers) and LDS for every
+    // level's phi and every coarse level's right-hand side
+    PLevels plv{};
+    size_t lds_bytes = 0;
+    int lds_cpt = 0;
+    int* cyc_dev = nullptr;
+
     void init(const Grid& g0, int bmax, hipStream_t s) {
         PG = poisson_levels(g0);
         Bmax = bmax;
         st = s;
+        lds_cpt = 0;
+        lds_checked = false;
+        const int nl = (int)PG.size();
+        if (nl < 2 || nl > PL_MAX || PG.back().ncell > 256 || g0.ncell > 16 * 1024) return;
+        size_t off = 0;
+        for (int l = 0; l < nl; ++l) {
+            plv.g[l] = PG[l];
+            plv.dx[l] = make_fastdiv((unsigned)PG[l].n[0]);
+            plv.dy[l] = make_fastdiv((unsigned)PG[l].n[1]);
+            plv.dh[l] = make_fastdiv((unsigned)((PG[l].n[0] + 1) / 2));
+            plv.off_phi[l] = (int)off;
+            off += PG[l].ncell;
+            plv.off_b[l] = l == 0 ? -1 : (int)off;
+            if (l > 0) off += PG[l].ncell;
+        }
+        plv.n = nl;
+        plv.coarse_m = PG.back().ncell;
+        lds_bytes = 256 + off * sizeof(T);
+        lds_cpt = g0.ncell <= 2048 ? 2 : (g0.ncell <= 4096 ? 4 : (g0.ncell <= 8192 ? 8 : 16));
+    }
+    // first use on the device: keep the LDS path only if the device allows
+    // that much LDS per workgroup
+    bool lds_checked = false;
+    void check_lds() {
+        lds_checked = true;
+        if (lds_cpt == 0) return;
+        int dev = 0, maxlds = 0;
+        HCK(hipGetDevice(&dev));
+        HCK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        if (lds_bytes + sizeof(PLevels) > (size_t)maxlds) {
+            lds_cpt = 0;
+            return;
+        }
+        set_lds_attr();
+    }
+    void set_lds_attr() {
+        switch (lds_cpt) {
+            case 2: HCK(hipFuncSetAttribute((const void*)k_project_lds<T, D, 2>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes)); break;
+            case 4: HCK(hipFuncSetAttribute((const void*)k_project_lds<T, D, 4>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes)); break;
+            case 8: HCK(hipFuncSetAttribute((const void*)k_project_lds<T, D, 8>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes)); break;
+            case 16: HCK(hipFuncSetAttribute((const void*)k_project_lds<T, D, 16>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes)); break;
+            default: break;
+        }
+    }
+    void launch_lds(const T* w, T* o, T* phi_out, int B, double rtol, int fixed) {
+        const long F = PG[0].nface, C = PG[0].ncell;
+        switch (lds_cpt) {
+#define STFAS_PLDS(CC)                                                                                           \
+    case CC:                                                                                                     \
+        k_project_lds<T, D, CC><<<B, 1024, lds_bytes, st>>>(plv, pinv, w, o, phi_out, b[0], rtol, fixed,         \
+                                                            MAX_PROJECT_CYCLES, cyc_dev, F, C);                  \
+        break;
+            STFAS_PLDS(2)
+            STFAS_PLDS(4)
+            STFAS_PLDS(8)
+            STFAS_PLDS(16)
+#undef STFAS_PLDS
+            default: break;
+        }
     }
     bool coarse_ok() const { return PG.back().ncell <= MAX_COARSE_CELLS; }
     void layout(Arena& A, double* shared_pinv) {
@@ -241,6 +313,7 @@ struct Poisson {
         pinv = shared_pinv ? shared_pinv : A.take<double>((size_t)PG.back().ncell * PG.back().ncell);
         pool = A.take<double>((size_t)Bmax * RED_BLOCKS * 2);
         out = A.take<double>(8);
+        cyc_dev = A.take<int>(64);
     }
     void upload_pinv() {
         std::vector<double> pv;
@@ -288,12 +361,28 @@ struct Poisson {
     // out = Q w for B slices (out may alias w).  fixed > 0: exactly that many
     // cycles and no host synchronisation; otherwise cycles until the
     // relative residual of every slice is <= rtol.  Returns the cycle count.
-    int project(const T* w, T* o, T* phi_out, int B, double rtol, int fixed, double* host) {
+    // With the LDS kernel the cycle count is per slice and decided on the
+    // device; it is read back (synchronising) only when `count` is set, else
+    // -1 is returned.
+    int project(const T* w, T* o, T* phi_out, int B, double rtol, int fixed, double* host, bool count = true) {
         const Grid& g = PG[0];
         const long C = g.ncell;
+        if (!lds_checked) check_lds();
+        if (lds_cpt > 0) {
+            const bool want = count && fixed <= 0;
+            if (want) k_fill<int><<<1, 64, 0, st>>>(1, cyc_dev, 0);
+            launch_lds(w, o, phi_out, B, rtol, fixed);
+            if (fixed > 0) return fixed;
+            if (!want) return -1;
+            int c = 0;
+            HCK(hipMemcpyAsync(&c, cyc_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+            HCK(hipStreamSynchronize(st));
+            return c;
+        }
         k_divergence<T, D><<<dim3(blocks_for(C, BS), B), BS, 0, st>>>(g, w, b[0], g.nface, C);
         k_fill<T><<<blocks_for((long)B * C, BS), BS, 0, st>>>((long)B * C, phi[0], (T)0);
         int cycles = 0;
+        double prev = 0;
         for (;;) {
             vcycle(0, B);
             ++cycles;
@@ -304,6 +393,8 @@ struct Poisson {
             if (cycles >= MAX_PROJECT_CYCLES) break;
             const double r = ratio(B, host);
             if (!std::isfinite(r) || r <= rtol) break;
+            if (cycles >= 2 && r > PROJECT_STALL * prev) break;    // at the rounding floor
+            prev = r;
         }
         k_project_apply<T, D><<<dim3(blocks_for(g.nface, BS), B), BS, 0, st>>>(g, w, phi[0], o, g.nface, C);
         if (phi_out) {
@@ -329,7 +420,8 @@ enum TraceKernel {
     TR_ADVECT = 6,
     TR_KKT_CELLS = 7,
     TR_SCGS_CELLS = 8,
-    TR_SCGS_COLOUR = 9
+    TR_SCGS_COLOUR = 9,
+    TR_KKT_SPLIT = 10
 };
 
 struct Tracer {
@@ -445,16 +537,17 @@ inline bool colour_shape(int M, long cells, int& G, int& L, int& CH) {
 
 template <typename T, int D>
 inline void launch_scgs_colour(int G, int L, int CH, const Grid& g, int N, const ColourSet& cs, const T* r1,
-                               const T* r2, const T* r3, const T* r4, T* v, T* pb, T* u, T* p, const T* tdiag,
-                               const T* tsub, const T* tsup, const T* tcp, const T* tinv, T omega, hipStream_t st) {
+                               const T* t1, const T* r2, const T* r3, const T* r4, T* v, T* pb, T* u, T* p,
+                               const T* tdiag, const T* tsub, const T* tsup, const T* tcp, const T* tinv, T omega,
+                               hipStream_t st) {
     const long threads = (long)cs.total * G;
     const int blocks = (int)((threads + 255) / 256);
     constexpr int CHMAX = (sizeof(T) == 4 && D == 2) ? 16 : 8;
 #define STFAS_COLOUR_CASE(GG, CC)                                                                                \
     if constexpr (CC <= CHMAX)                                                                                   \
         if (G == GG && CH == CC)                                                                                 \
-            k_scgs_colour<T, D, GG, CC><<<blocks, 256, 0, st>>>(g, N, L, cs, r1, r2, r3, r4, v, pb, u, p, tdiag,  \
-                                                                tsub, tsup, tcp, tinv, omega);
+            k_scgs_colour<T, D, GG, CC><<<blocks, 256, 0, st>>>(g, N, L, cs, r1, t1, r2, r3, r4, v, pb, u, p,     \
+                                                                tdiag, tsub, tsup, tcp, tinv, omega);
 #define STFAS_COLOUR_G(GG)                                                                                       \
     STFAS_COLOUR_CASE(GG, 2) STFAS_COLOUR_CASE(GG, 4) STFAS_COLOUR_CASE(GG, 8) STFAS_COLOUR_CASE(GG, 12)          \
     STFAS_COLOUR_CASE(GG, 16)
@@ -498,7 +591,8 @@ public:
         T* w;                    // targets
     };
     std::vector<Lev> lev;
-    T* scgs_scratch = nullptr;
+    T* scgs_scratch = nullptr;   // two-kernel SCGS path only (horizons too long for the fused kernel)
+    T *t1a = nullptr, *t1b = nullptr;   // J_S^T part of F1 for the SCGS colour passes (any level)
     T *t_diag, *t_sub, *t_sup, *t_cp, *t_inv;
     Poisson<T, D> pois;      // projection, batched over up to N slices
     // density subproblem
@@ -555,9 +649,17 @@ public:
             q.w = A.take<T>(N * F);
         }
         // SCGS scratch: the largest colour of level 0, 2N blocks, 2d faces per cell
-        long maxcol = 0;
-        for (int c = 0; c < (1 << D); ++c) maxcol = std::max<long>(maxcol, colour_set(L[0], c).total);
-        scgs_scratch = A.take<T>((size_t)maxcol * 2 * D * 2 * N);
+        int Gs, Ls, CHs;
+        if (colour_shape<T, D>(2 * N, 1, Gs, Ls, CHs)) {
+            scgs_scratch = nullptr;
+            t1a = A.take<T>(N * F0);
+            t1b = A.take<T>(N * F0);
+        } else {
+            long maxcol = 0;
+            for (int c = 0; c < (1 << D); ++c) maxcol = std::max<long>(maxcol, colour_set(L[0], c).total);
+            scgs_scratch = A.take<T>((size_t)maxcol * 2 * D * 2 * N);
+            t1a = t1b = nullptr;
+        }
         t_diag = A.take<T>(2 * N);
         t_sub = A.take<T>(2 * N);
         t_sup = A.take<T>(2 * N);
@@ -680,8 +782,8 @@ public:
     }
 
     // ------------------------------------------------------------ projection
-    int project(const T* w, T* out, T* phi_out, int B, int fixed = 0) {
-        return pois.project(w, out, phi_out, B, P.poisson_rtol, fixed, host_out);
+    int project(const T* w, T* out, T* phi_out, int B, int fixed = 0, bool count = false) {
+        return pois.project(w, out, phi_out, B, P.poisson_rtol, fixed, host_out, count);
     }
 
     // ------------------------------------------------------------ metric
@@ -726,6 +828,37 @@ public:
                    [&] { self_advect_T(l, v, u + g.nface, (T)(-sgn / dt), o1, N - 1); });
         }
     }
+    // The residual r = res - f(x) of level l for an SCGS colour pass in one
+    // launch: F1 without its J_S^T term in r1, that term in t1 (zero on
+    // entry), and t1z cleared for the next pass.
+    void kkt_split(int l, T* t1, T* t1z) {
+        const Grid& g = L[l];
+        Lev& q = lev[l];
+        using TS = TileShape<D>;
+        KktSplit ks{};
+        ks.nbf = blocks_for(g.nface, 256);
+        ks.nbc = blocks_for(g.ncell, 256);
+        ks.ntile = 0;
+        for (int a = 0; a < D; ++a) {
+            const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
+            const int t = ((ex + TS::X - 1) / TS::X) * ((ey + TS::Y - 1) / TS::Y) *
+                          (D == 3 ? (ez + TS::Z - 1) / TS::Z : 1);
+            ks.ntile = std::max(ks.ntile, t);
+        }
+        ks.nbz = std::min(blocks_for((long)N * g.nface, 256), 2048);
+        const long blocks = (long)(ks.nbf + ks.nbc) * N + (long)ks.ntile * (N - 1) * D + ks.nbz;
+        const double sz = sizeof(T);
+        const double fslots = (double)g.nface * N, cslots = (double)g.ncell * N;
+        // faces as in kkt(), cells as in kkt(), the transpose's v, y, t1 read+write, and t1z written
+        const double bytes = sz * (fslots * (6 + (q.s1 ? 2 : 0)) + cslots * 2) +
+                             sz * (fslots * 2 + cslots * (2 + (q.s2 ? 2 : 0))) +
+                             sz * (double)g.nface * (N - 1) * 4 + sz * fslots;
+        traced(tr, st, l == 0 ? TR_KKT_SPLIT : TR_NONE, bytes, [&] {
+            k_kkt_split<T, D><<<(unsigned)blocks, 256, 0, st>>>(g, N, (T)P.dt, (T)(P.K / P.r), cfl(l), (T)-1, ks,
+                                                               q.v, q.pb, q.u, q.p, q.w, q.s1, q.s2, q.s3, q.s4,
+                                                               q.r1, q.r2, q.r3, q.r4, t1, t1z);
+        });
+    }
     void kkt_level(int l, bool fas_rhs) {
         Lev& q = lev[l];
         if (fas_rhs)
@@ -754,21 +887,27 @@ public:
     void sweep(int l) {
         const Grid& g = L[l];
         Lev& q = lev[l];
+        T* t1c = t1a;
+        T* t1n = t1b;
+        if (t1c) fill(t1c, (long)N * g.nface, (T)0);
         for (int colour = 0; colour < (1 << D); ++colour) {
-            kkt_level(l, false);
             const ColourSet cs = colour_set(g, colour);
             const int nf = cs.total * 2 * D;
             const double inner = (double)colour_inner_faces(g, colour);
             const double sz = sizeof(T), M2 = 2.0 * N;
             int G = 1, Lc = 0, CH = 0;
-            if (colour_shape<T, D>(2 * N, cs.total, G, Lc, CH)) {
-                // one kernel: read r1..r4 once, update u/v at the faces and p/pbar at the cells
-                traced(tr, st, l == 0 ? TR_SCGS_COLOUR : TR_NONE, sz * M2 * (inner * 3 + cs.total * 3), [&] {
-                    launch_scgs_colour<T, D>(G, Lc, CH, g, N, cs, q.r1, q.r2, q.r3, q.r4, q.v, q.pb, q.u, q.p,
-                                             t_diag, t_sub, t_sup, t_cp, t_inv, (T)P.omega, st);
+            if (t1c && colour_shape<T, D>(2 * N, cs.total, G, Lc, CH)) {
+                // two launches per colour: the residual (faces, cells and the J_S^T term side by side),
+                // then one kernel that reads r1 + t1, r2..r4 once and updates u/v and p/pbar
+                kkt_split(l, t1c, t1n);
+                traced(tr, st, l == 0 ? TR_SCGS_COLOUR : TR_NONE, sz * M2 * (inner * 4 + cs.total * 3), [&] {
+                    launch_scgs_colour<T, D>(G, Lc, CH, g, N, cs, q.r1, t1c, q.r2, q.r3, q.r4, q.v, q.pb, q.u,
+                                             q.p, t_diag, t_sub, t_sup, t_cp, t_inv, (T)P.omega, st);
                 });
+                std::swap(t1c, t1n);
                 continue;
             }
+            kkt_level(l, false);
             // long horizons: project: read r1/r3 at the colour's faces, write (P r)
             traced(tr, st, l == 0 ? TR_SCGS_PROJECT : TR_NONE, sz * M2 * inner * 2, [&] {
                 k_scgs_project<T, D><<<blocks_for((long)nf * 2 * N, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r3,
@@ -1042,7 +1181,7 @@ public:
         self_advect_T(l, (const T*)v, (const T*)y, (T)scale, (T*)out, batch);
     }
     int op_project(int batch, const void* w, void* out, void* phi) override {
-        return project((const T*)w, (T*)out, (T*)phi, batch);
+        return project((const T*)w, (T*)out, (T*)phi, batch, 0, true);
     }
     void op_metric(const void* e, void* out) override { metric((const T*)e, (T*)out); }
     void op_kkt(int l, stfas_state x, const void* w, stfas_state res, stfas_state out) override {

@@ -103,6 +103,30 @@ def test_projection_batched(n, N, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", [((128, 128), 8), ((64, 64), 3), ((16, 16, 16), 2), ((40, 24), 2)])
+def test_projection_benchmark_sizes(n, N, prec):
+    """Projection at the sizes the solver runs: 128x128 with 8 slices (the
+    single-launch LDS form in FP32; the multi-kernel form in FP64, whose
+    hierarchy does not fit in LDS), 64x64, 16^3, and a grid whose hierarchy
+    stops at an odd size."""
+    S, ctx, g, dt, K = _ctx(n, N, prec)
+    rng = np.random.default_rng(14)
+    w = _q(_faces(g, rng, N, 3.0), prec)
+    out = empty(N * g.nface, prec)
+    phi = empty(N * g.ncell, prec)
+    flag(f"project sizes n={n} N={N} {prec}")
+    cycles = S.stfas_op_project(ctx, N, to_dev(w, prec), out, phi)
+    refs = [poisson.project(g, w[b]) for b in range(N)]
+    ref = np.stack([r[0] for r in refs])
+    refphi = np.stack([r[1] for r in refs])
+    tol = TOL[prec] if prec == "fp64" else 2e-5
+    assert rel(to_np(out), ref) <= tol
+    assert rel(to_np(phi), refphi) <= 10 * tol
+    assert 1 <= cycles <= 60
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_metric(prec):
     S, ctx, g, dt, K = _ctx((24, 20), 2, prec, metric_levels=2)
     rng = np.random.default_rng(14)
