@@ -208,6 +208,10 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
     const int lx = threadIdx.x % TS::X, ly = (threadIdx.x / TS::X) % TS::Y, lz = threadIdx.x / (TS::X * TS::Y);
     const int i = tx0 + lx, j = ty0 + ly, k = tz0 + lz;
     T gs[3] = {0, 0, 0};
+    T wq[1 << D];
+    int c0[3] = {-4, 0, 0};            // x corner far from any real one when the lane has nothing to add
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) wq[q] = 0;
     const bool valid = i < ex && j < ey && (D == 2 || k < ez);
     if (valid && face_interior(g, a, i, j, k)) {
         const int f = face_index(g, a, i, j, k);
@@ -224,20 +228,38 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
             it.grad(v + g.foff[a], gr);
 #pragma unroll
             for (int b = 0; b < D; ++b) gs[b] = yv * (-cfl) * gr[b];
-            const int c0[3] = {it.ax[0].i0, it.ax[1].i0, D == 3 ? it.ax[D - 1].i0 : 0};
+            c0[0] = it.ax[0].i0;
+            c0[1] = it.ax[1].i0;
+            c0[2] = D == 3 ? it.ax[D - 1].i0 : 0;
 #pragma unroll
-            for (int q = 0; q < (1 << D); ++q) {
-                const T w = it.weight(q) * yv;
-                if (w == (T)0) continue;
-                const int ci = c0[0] + (q & 1), cj = c0[1] + ((q >> 1) & 1), ck = D == 3 ? c0[2] + ((q >> 2) & 1) : 0;
-                const int ca = a == 0 ? ci : (a == 1 ? cj : ck);
-                if (ca == 0 || ca == g.n[a]) continue;          // wall node of the a-lattice
-                const int wx = ci - ox, wy = cj - oy, wz = ck - oz;
-                if (wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
-                    atomicAdd(&win[(wz * WY + wy) * WX + wx], w);
-                else
-                    atomic_add(out + face_index(g, a, ci, cj, ck), w);
-            }
+            for (int q = 0; q < (1 << D); ++q) wq[q] = it.weight(q) * yv;
+        }
+    }
+    // Weights.  Neighbouring lanes of a row usually backtrace into
+    // neighbouring cells, so the +x corner of lane l is the 0 corner of lane
+    // l+1: that lane adds both (one LDS atomic instead of two).  The match
+    // compares the target nodes themselves, so any pairing it makes is exact.
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < (1 << (D - 1)); ++r) {
+        const int q0 = r << 1, q1 = q0 | 1;
+        const int pi = __shfl_up(c0[0], 1, 64), pj = __shfl_up(c0[1], 1, 64), pk = __shfl_up(c0[2], 1, 64);
+        const T pw = __shfl_up(wq[q1], 1, 64);
+        const bool match = lane > 0 && pi == c0[0] - 1 && pj == c0[1] && pk == c0[2];
+        const bool taken = __shfl_down(match ? 1 : 0, 1, 64) != 0 && lane < 63;
+        const int cj = c0[1] + (r & 1), ck = D == 3 ? c0[2] + ((r >> 1) & 1) : 0;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const T w = e == 0 ? wq[q0] + (match ? pw : (T)0) : (taken ? (T)0 : wq[q1]);
+            if (w == (T)0) continue;
+            const int ci = c0[0] + e;
+            const int ca = a == 0 ? ci : (a == 1 ? cj : ck);
+            if (ca == 0 || ca == g.n[a]) continue;          // wall node of the a-lattice
+            const int wx = ci - ox, wy = cj - oy, wz = ck - oz;
+            if (wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
+                atomicAdd(&win[(wz * WY + wy) * WX + wx], w);
+            else
+                atomic_add(out + face_index(g, a, ci, cj, ck), w);
         }
     }
 #pragma unroll
