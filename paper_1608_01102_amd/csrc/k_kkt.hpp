@@ -528,13 +528,10 @@ __device__ inline T fine_pos(int j, bool node) {
     return node ? (T)j * (T)0.5 : ((T)j + (T)0.5) * (T)0.5 - (T)0.5;
 }
 
-// coarse = 2^-d P^T fine on the cell lattice (gather form), batched over slots.
+// coarse = 2^-d P^T fine on the cell lattice (gather form), coarse cell c.
 template <typename T, int D>
-__global__ void k_restrict_cells(Grid gf, Grid gc, const T* __restrict__ fine, T* __restrict__ coarse) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= gc.ncell) return;
-    fine += (long)blockIdx.y * gf.ncell;
-    coarse += (long)blockIdx.y * gc.ncell;
+__device__ inline void restrict_cell_at(const Grid& gf, const Grid& gc, const T* __restrict__ fine,
+                                        T* __restrict__ coarse, int c) {
     const int I[3] = {c % gc.n[0], (c / gc.n[0]) % gc.n[1], c / (gc.n[0] * gc.n[1])};
     T s = 0;
     const int lo2 = D == 3 ? 2 * I[2] - 1 : 0, hi2 = D == 3 ? 2 * I[2] + 2 : 0;
@@ -556,13 +553,10 @@ __global__ void k_restrict_cells(Grid gf, Grid gc, const T* __restrict__ fine, T
     coarse[c] = s * (T)(D == 3 ? 0.125 : 0.25);
 }
 
-// Face lattices; coarse wall faces are set to zero.
+// Face lattices, coarse face f; coarse wall faces are set to zero.
 template <typename T, int D>
-__global__ void k_restrict_faces(Grid gf, Grid gc, const T* __restrict__ fine, T* __restrict__ coarse) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= gc.nface) return;
-    fine += (long)blockIdx.y * gf.nface;
-    coarse += (long)blockIdx.y * gc.nface;
+__device__ inline void restrict_face_at(const Grid& gf, const Grid& gc, const T* __restrict__ fine,
+                                        T* __restrict__ coarse, int f) {
     int a, I0, I1, I2;
     face_decode(gc, f, a, I0, I1, I2);
     if (!face_interior(gc, a, I0, I1, I2)) {
@@ -595,13 +589,10 @@ __global__ void k_restrict_faces(Grid gf, Grid gc, const T* __restrict__ fine, T
     coarse[f] = s * (T)(D == 3 ? 0.125 : 0.25);
 }
 
-// fine += sign * P coarse on the cell lattice.
+// fine += sign * P coarse on the cell lattice, fine cell c.
 template <typename T, int D>
-__global__ void k_prolong_cells(Grid gf, Grid gc, const T* __restrict__ coarse, T sign, T* __restrict__ fine) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= gf.ncell) return;
-    fine += (long)blockIdx.y * gf.ncell;
-    coarse += (long)blockIdx.y * gc.ncell;
+__device__ inline void prolong_cell_at(const Grid& gf, const Grid& gc, const T* __restrict__ coarse, T sign,
+                                       T* __restrict__ fine, int c) {
     const int idx[3] = {c % gf.n[0], (c / gf.n[0]) % gf.n[1], c / (gf.n[0] * gf.n[1])};
     T y[3];
     for (int b = 0; b < D; ++b) y[b] = fine_pos<T>(idx[b], false);
@@ -610,13 +601,10 @@ __global__ void k_prolong_cells(Grid gf, Grid gc, const T* __restrict__ coarse, 
     fine[c] += sign * it.value(coarse);
 }
 
-// fine += sign * P coarse on the face lattices (fine walls untouched).
+// fine += sign * P coarse on the face lattices (fine walls untouched), fine face f.
 template <typename T, int D>
-__global__ void k_prolong_faces(Grid gf, Grid gc, const T* __restrict__ coarse, T sign, T* __restrict__ fine) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= gf.nface) return;
-    fine += (long)blockIdx.y * gf.nface;
-    coarse += (long)blockIdx.y * gc.nface;
+__device__ inline void prolong_face_at(const Grid& gf, const Grid& gc, const T* __restrict__ coarse, T sign,
+                                       T* __restrict__ fine, int f) {
     int a, i, j, k;
     face_decode(gf, f, a, i, j, k);
     if (!face_interior(gf, a, i, j, k)) return;
@@ -626,6 +614,65 @@ __global__ void k_prolong_faces(Grid gf, Grid gc, const T* __restrict__ coarse, 
     Interp<T, D> it;
     it.setup(y, face_ext(gc, a, 0), face_ext(gc, a, 1), face_ext(gc, a, 2));
     fine[f] += sign * it.value(coarse + gc.foff[a]);
+}
+
+template <typename T, int D>
+__global__ void k_restrict_cells(Grid gf, Grid gc, const T* __restrict__ fine, T* __restrict__ coarse) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= gc.ncell) return;
+    restrict_cell_at<T, D>(gf, gc, fine + (long)blockIdx.y * gf.ncell, coarse + (long)blockIdx.y * gc.ncell, c);
+}
+template <typename T, int D>
+__global__ void k_restrict_faces(Grid gf, Grid gc, const T* __restrict__ fine, T* __restrict__ coarse) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= gc.nface) return;
+    restrict_face_at<T, D>(gf, gc, fine + (long)blockIdx.y * gf.nface, coarse + (long)blockIdx.y * gc.nface, f);
+}
+template <typename T, int D>
+__global__ void k_prolong_cells(Grid gf, Grid gc, const T* __restrict__ coarse, T sign, T* __restrict__ fine) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= gf.ncell) return;
+    prolong_cell_at<T, D>(gf, gc, coarse + (long)blockIdx.y * gc.ncell, sign, fine + (long)blockIdx.y * gf.ncell, c);
+}
+template <typename T, int D>
+__global__ void k_prolong_faces(Grid gf, Grid gc, const T* __restrict__ coarse, T sign, T* __restrict__ fine) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= gf.nface) return;
+    prolong_face_at<T, D>(gf, gc, coarse + (long)blockIdx.y * gc.nface, sign, fine + (long)blockIdx.y * gf.nface, f);
+}
+
+// Several transfers in one launch (blockIdx.z picks the array): the first
+// nf entries are face sequences, the rest cell sequences; blockIdx.y is the
+// time slot.  Restriction: dst (coarse) = R src (fine).  Prolongation:
+// dst (fine) += sign P src (coarse).
+template <typename T>
+struct XferSet {
+    const T* src[8];
+    T* dst[8];
+};
+
+template <typename T, int D>
+__global__ void k_restrict_set(Grid gf, Grid gc, XferSet<T> x, int nf) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int z = blockIdx.z;
+    const long s = blockIdx.y;
+    if (z < nf) {
+        if (e < gc.nface) restrict_face_at<T, D>(gf, gc, x.src[z] + s * gf.nface, x.dst[z] + s * gc.nface, e);
+    } else {
+        if (e < gc.ncell) restrict_cell_at<T, D>(gf, gc, x.src[z] + s * gf.ncell, x.dst[z] + s * gc.ncell, e);
+    }
+}
+
+template <typename T, int D>
+__global__ void k_prolong_set(Grid gf, Grid gc, XferSet<T> x, int nf, T sign) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int z = blockIdx.z;
+    const long s = blockIdx.y;
+    if (z < nf) {
+        if (e < gf.nface) prolong_face_at<T, D>(gf, gc, x.src[z] + s * gc.nface, sign, x.dst[z] + s * gf.nface, e);
+    } else {
+        if (e < gf.ncell) prolong_cell_at<T, D>(gf, gc, x.src[z] + s * gc.ncell, sign, x.dst[z] + s * gf.ncell, e);
+    }
 }
 
 }  // namespace stfas

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <vector>
 
 #include "../../include/stfas.h"
@@ -712,6 +713,9 @@ public:
 
     void init_tables() override {
         host_out = thread_pinned();
+        // t1a is all zero between SCGS sweeps: every sweep has an even number
+        // of colours and the last colour's residual launch clears t1a again
+        if (t1a) fill(t1a, (long)N * L[0].nface, (T)0);
         TFactors f = temporal_factors(N, P.dt, P.K / P.r);
         upload(t_diag, f.diag);
         upload(t_sub, f.sub);
@@ -887,9 +891,8 @@ public:
     void sweep(int l) {
         const Grid& g = L[l];
         Lev& q = lev[l];
-        T* t1c = t1a;
+        T* t1c = t1a;     // zero on entry (see init_tables)
         T* t1n = t1b;
-        if (t1c) fill(t1c, (long)N * g.nface, (T)0);
         for (int colour = 0; colour < (1 << D); ++colour) {
             const ColourSet cs = colour_set(g, colour);
             const int nf = cs.total * 2 * D;
@@ -926,6 +929,27 @@ public:
         }
     }
 
+    // n transfers in one launch, the first nf on face sequences
+    void restrict_set(int l, std::initializer_list<const T*> src, std::initializer_list<T*> dst, int nf, int n) {
+        XferSet<T> x{};
+        int z = 0;
+        for (const T* p : src) x.src[z++] = p;
+        z = 0;
+        for (T* p : dst) x.dst[z++] = p;
+        const Grid& gc = L[l + 1];
+        const int m = (int)std::max<long>(gc.nface, gc.ncell);
+        k_restrict_set<T, D><<<dim3(blocks_for(m, BS), N, n), BS, 0, st>>>(L[l], gc, x, nf);
+    }
+    void prolong_set(int l, std::initializer_list<const T*> src, std::initializer_list<T*> dst, int nf, int n, T sign) {
+        XferSet<T> x{};
+        int z = 0;
+        for (const T* p : src) x.src[z++] = p;
+        z = 0;
+        for (T* p : dst) x.dst[z++] = p;
+        const Grid& gf = L[l];
+        const int m = (int)std::max<long>(gf.nface, gf.ncell);
+        k_prolong_set<T, D><<<dim3(blocks_for(m, BS), N, n), BS, 0, st>>>(gf, L[l + 1], x, nf, sign);
+    }
     void restrict_faces(int l, const T* fine, T* coarse) {
         k_restrict_faces<T, D><<<dim3(blocks_for(L[l + 1].nface, BS), N), BS, 0, st>>>(L[l], L[l + 1], fine, coarse);
     }
@@ -949,24 +973,13 @@ public:
         sweep(l);
         kkt_level(l, false);                                   // r = res - f(x_s)
         Lev& c = lev[l + 1];
-        restrict_faces(l, q.v, c.v);                           // x^{2h} = R x_s
-        restrict_cells(l, q.pb, c.pb);
-        restrict_faces(l, q.u, c.u);
-        restrict_cells(l, q.p, c.p);
-        prolong_faces(l, c.v, (T)-1, q.v);                     // x = x_s - P x^{2h}
-        prolong_cells(l, c.pb, (T)-1, q.pb);
-        prolong_faces(l, c.u, (T)-1, q.u);
-        prolong_cells(l, c.p, (T)-1, q.p);
-        restrict_faces(l, q.r1, c.s1);                         // res^{2h} = R r + f(x^{2h})
-        restrict_cells(l, q.r2, c.s2);
-        restrict_faces(l, q.r3, c.s3);
-        restrict_cells(l, q.r4, c.s4);
+        // x^{2h} = R x_s and the residual part of res^{2h} = R r + f(x^{2h}), one launch
+        restrict_set(l, {q.v, q.u, q.r1, q.r3, q.pb, q.p, q.r2, q.r4}, {c.v, c.u, c.s1, c.s3, c.pb, c.p, c.s2, c.s4},
+                     4, 8);
+        prolong_set(l, {c.v, c.u, c.pb, c.p}, {q.v, q.u, q.pb, q.p}, 2, 4, (T)-1);   // x = x_s - P x^{2h}
         kkt_level(l + 1, true);
         vcycle(l + 1);
-        prolong_faces(l, c.v, (T)1, q.v);                      // x += P x^{2h}
-        prolong_cells(l, c.pb, (T)1, q.pb);
-        prolong_faces(l, c.u, (T)1, q.u);
-        prolong_cells(l, c.p, (T)1, q.p);
+        prolong_set(l, {c.v, c.u, c.pb, c.p}, {q.v, q.u, q.pb, q.p}, 2, 4, (T)1);    // x += P x^{2h}
         sweep(l);
         sweep(l);
     }
