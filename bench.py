@@ -27,7 +27,7 @@ def parse():
     ap.add_argument("--max-admm", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
-    ap.add_argument("--trace-kernel", default="scgs_thomas",
+    ap.add_argument("--trace-kernel", default="kkt_split",
                     help="kernel family whose launches on the finest level are timed with HIP events")
     ap.add_argument("--serve-requests", type=int, default=16, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=4)

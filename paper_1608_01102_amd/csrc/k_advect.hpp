@@ -214,18 +214,20 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
     for (int q = 0; q < (1 << D); ++q) wq[q] = 0;
     const bool valid = i < ex && j < ey && (D == 2 || k < ez);
     if (valid && face_interior(g, a, i, j, k)) {
+        // y and the velocities are loaded together; a zero y then drops
+        // the source (its results are not used, whatever they are)
         const int f = face_index(g, a, i, j, k);
         const T yv = y[f] * scale;
+        T vh[3];
+        face_velocity<T, D>(g, v, a, i, j, k, vh);
+        const int idx[3] = {i, j, k};
+        T dl[3];
+        for (int b = 0; b < D; ++b) dl[b] = -cfl * vh[b];
+        Interp<T, D> it;
+        it.setup_disp(idx, dl, ex, ey, ez);
+        T gr[3];
+        it.grad(v + g.foff[a], gr);
         if (yv != (T)0) {
-            T vh[3];
-            face_velocity<T, D>(g, v, a, i, j, k, vh);
-            const int idx[3] = {i, j, k};
-            T dl[3];
-            for (int b = 0; b < D; ++b) dl[b] = -cfl * vh[b];
-            Interp<T, D> it;
-            it.setup_disp(idx, dl, ex, ey, ez);
-            T gr[3];
-            it.grad(v + g.foff[a], gr);
 #pragma unroll
             for (int b = 0; b < D; ++b) gs[b] = yv * (-cfl) * gr[b];
             c0[0] = it.ax[0].i0;

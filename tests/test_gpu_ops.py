@@ -216,7 +216,7 @@ def test_scgs_sweep_long_horizon(n, N, prec):
 @pytest.mark.parametrize("n,N", [((128, 128), 40)])
 def test_scgs_sweep_benchmark_shapes(n, N, prec):
     """The 128x128 x 40 grid: the whole-colour kernel takes the launch shape
-    the benchmark times (16 lanes per cell, chunks of 6 blocks)."""
+    the benchmark times (8 lanes per cell, chunks of 10 blocks)."""
     S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=0.7)
     kr = K / 1e-2
     rng = np.random.default_rng(19)
