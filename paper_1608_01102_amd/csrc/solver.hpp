@@ -822,8 +822,8 @@ public:
         const T dt = (T)P.dt;
         const double sz = sizeof(T);
         const double fslots = (double)g.nface * N, cslots = (double)g.ncell * N;
-        // faces: v, v_{i-1} (for S), u, w, out1, out3 (+ res1, res3) per face; pbar, p per cell
-        traced(tr, st, l == 0 ? TR_KKT_FACES : TR_NONE, sz * (fslots * (6 + (s1 ? 2 : 0)) + cslots * 2), [&] {
+        // faces: v (also read as v_{i-1} for S), u, w, out1, out3 (+ res1, res3) per face; pbar, p per cell
+        traced(tr, st, l == 0 ? TR_KKT_FACES : TR_NONE, sz * (fslots * (5 + (s1 ? 2 : 0)) + cslots * 2), [&] {
             k_kkt_faces<T, D><<<dim3(blocks_for(g.nface, BS), N), BS, 0, st>>>(g, N, dt, (T)(P.K / P.r), cfl(l), sgn,
                                                                               v, pb, u, p, w, s1, s3, o1, o3);
         });
@@ -857,10 +857,9 @@ public:
         const long blocks = (long)(ks.nbf + ks.nbc) * N + (long)ks.ntile * (N - 1) * D + ks.nbz;
         const double sz = sizeof(T);
         const double fslots = (double)g.nface * N, cslots = (double)g.ncell * N;
-        // faces as in kkt(), cells as in kkt(), the transpose's v, y, t1 read+write, and t1z written
-        const double bytes = sz * (fslots * (6 + (q.s1 ? 2 : 0)) + cslots * 2) +
-                             sz * (fslots * 2 + cslots * (2 + (q.s2 ? 2 : 0))) +
-                             sz * (double)g.nface * (N - 1) * 4 + sz * fslots;
+        // every sequence the launch reads or writes, once: v, u, w in and r1, r3, t1, t1z out per
+        // face slot (+ s1, s3 on coarse levels); pbar, p in and r2, r4 out per cell slot (+ s2, s4)
+        const double bytes = sz * (fslots * (7 + (q.s1 ? 2 : 0)) + cslots * (4 + (q.s2 ? 2 : 0)));
         traced(tr, st, l == 0 ? TR_KKT_SPLIT : TR_NONE, bytes, [&] {
             k_kkt_split<T, D><<<(unsigned)blocks, 256, 0, st>>>(g, N, (T)P.dt, (T)(P.K / P.r), cfl(l), (T)-1, ks,
                                                                q.v, q.pb, q.u, q.p, q.w, q.s1, q.s2, q.s3, q.s4,
@@ -907,7 +906,9 @@ public:
                 // two launches per colour: the residual (faces, cells and the J_S^T term side by side),
                 // then one kernel that reads r1 + t1, r2..r4 once and updates u/v and p/pbar
                 kkt_split(l, t1c, t1n);
-                traced(tr, st, l == 0 ? TR_SCGS_COLOUR : TR_NONE, sz * M2 * (inner * 4 + cs.total * 3), [&] {
+                // per block pair: r1, t1, r3 read, u and v read + written at each interior face;
+                // per block: the divergence residual read, p or pbar read + written at each cell
+                traced(tr, st, l == 0 ? TR_SCGS_COLOUR : TR_NONE, sz * M2 * (inner * 3.5 + cs.total * 3), [&] {
                     launch_scgs_colour<T, D>(G, Lc, CH, g, N, cs, q.r1, t1c, q.r2, q.r3, q.r4, q.v, q.pb, q.u,
                                              q.p, t_diag, t_sub, t_sup, t_cp, t_inv, (T)P.omega, st);
                 });
