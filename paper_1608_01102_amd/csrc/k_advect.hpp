@@ -148,6 +148,61 @@ __global__ void k_self_advect(Grid g, T cfl, T dt, const T* __restrict__ v, cons
     out[f] = s;
 }
 
+// J_S(v)^T y for one source, a-face (i, j, k) of one slice, straight into
+// out with global atomics: the same contributions as the tiled kernel below,
+// without its LDS window and barriers.  Used on small levels, where a launch
+// is a chain of dependent memory steps and the atomics are few.
+template <typename T, int D>
+__device__ inline void self_advect_T_source(const Grid& g, T cfl, const T* __restrict__ v, const T* __restrict__ y,
+                                            T scale, T* out, int a, int i, int j, int k) {
+    if (!face_interior(g, a, i, j, k)) return;
+    const int f = face_index(g, a, i, j, k);
+    const T yv = y[f] * scale;
+    const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
+    T vh[3];
+    face_velocity<T, D>(g, v, a, i, j, k, vh);
+    const int idx[3] = {i, j, k};
+    T dl[3];
+    for (int b = 0; b < D; ++b) dl[b] = -cfl * vh[b];
+    Interp<T, D> it;
+    it.setup_disp(idx, dl, ex, ey, ez);
+    T gr[3];
+    it.grad(v + g.foff[a], gr);
+    if (yv == (T)0) return;
+    const int c0[3] = {it.ax[0].i0, it.ax[1].i0, D == 3 ? it.ax[D - 1].i0 : 0};
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) {
+        const T w = it.weight(q) * yv;
+        if (w == (T)0) continue;
+        const int ci = c0[0] + (q & 1), cj = c0[1] + ((q >> 1) & 1), ck = D == 3 ? c0[2] + ((q >> 2) & 1) : 0;
+        const int ca = a == 0 ? ci : (a == 1 ? cj : ck);
+        if (ca == 0 || ca == g.n[a]) continue;          // wall node of the a-lattice
+        atomic_add(out + face_index(g, a, ci, cj, ck), w);
+    }
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        const T gb = yv * (-cfl) * gr[b];
+        if (gb == (T)0) continue;
+        if (b == a) {
+            atomic_add(out + f, gb);
+            continue;
+        }
+        // a quarter to each of the four b-faces averaged at I (walls dropped)
+        const T qv = (T)0.25 * gb;
+        const int ia = i - (a == 0), ja = j - (a == 1), ka = k - (a == 2);
+        const int db0 = (b == 0), db1 = (b == 1), db2 = (b == 2);
+        const int bi = b == 0 ? i : (b == 1 ? j : k);
+        if (bi != 0) {
+            atomic_add(out + face_index(g, b, ia, ja, ka), qv);
+            atomic_add(out + face_index(g, b, i, j, k), qv);
+        }
+        if (bi + 1 != g.n[b]) {
+            atomic_add(out + face_index(g, b, ia + db0, ja + db1, ka + db2), qv);
+            atomic_add(out + face_index(g, b, i + db0, j + db1, k + db2), qv);
+        }
+    }
+}
+
 // out += scale * J_S(v)^T y.  Per interior a-face I: the interpolation
 // weights scatter y_I onto the a-face lattice, and the foot-point term
 // g_I = y_I (-dt/h) grad_Y I[v_a] returns to the sampled velocities
@@ -306,6 +361,18 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256) k_self_advect_T_tiled(Grid g, T cfl, const T* __restrict__ v,
                                                              const T* __restrict__ y, T scale, T* out, long vs) {
     self_advect_T_tile<T, D>(g, cfl, v, y, scale, out, vs, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Untiled form: one thread per (face, slice), blockIdx.y = slice.
+template <typename T, int D>
+__global__ void k_self_advect_T_direct(Grid g, T cfl, const T* __restrict__ v, const T* __restrict__ y, T scale,
+                                       T* out, long vs) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= g.nface) return;
+    int a, i, j, k;
+    face_decode(g, f, a, i, j, k);
+    const long o = (long)blockIdx.y * vs;
+    self_advect_T_source<T, D>(g, cfl, v + o, y + o, scale, out + o, a, i, j, k);
 }
 
 }  // namespace stfas

@@ -103,6 +103,7 @@ __global__ void k_kkt_cells(Grid g, T sgn, const T* __restrict__ v, const T* __r
 // only the state, so they run side by side; the SCGS pass reads F1 + t1.
 struct KktSplit {
     int nbf, nbc, ntile, nbz;
+    int direct;     // 1: the transpose part runs one thread per source (ntile = blocks per slice)
 };
 
 template <typename T, int D>
@@ -113,7 +114,8 @@ __global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T 
                                                    const T* res3, const T* res4, T* out1, T* out2, T* out3,
                                                    T* out4, T* t1, T* t1z) {
     long b = blockIdx.x;
-    const long bf = (long)ks.nbf * N, bc = (long)ks.nbc * N, bt = (long)ks.ntile * (N - 1) * D;
+    const long bf = (long)ks.nbf * N, bc = (long)ks.nbc * N;
+    const long bt = (long)ks.ntile * (N - 1) * (ks.direct ? 1 : D);
     if (b < bf) {
         const int f = (int)(b % ks.nbf) * 256 + threadIdx.x;
         if (f < g.nface) kkt_face<T, D>(g, N, dt, kr, cfl, sgn, v, pb, u, p, w, res1, res3, out1, out3, f, (int)(b / ks.nbf));
@@ -127,9 +129,20 @@ __global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T 
     }
     b -= bc;
     if (b < bt) {
+        const int slice = (int)((b / ks.ntile) % (N - 1));
+        if (ks.direct) {
+            // one thread per (slice, face); y = u_{j+1} (the u slots shifted by one), scale -sgn/dt
+            const int f = (int)(b % ks.ntile) * 256 + threadIdx.x;
+            if (f < g.nface) {
+                int a, i, j, k;
+                face_decode(g, f, a, i, j, k);
+                self_advect_T_source<T, D>(g, cfl, v + (long)slice * g.nface, u + (long)(slice + 1) * g.nface,
+                                           -sgn / dt, t1 + (long)slice * g.nface, a, i, j, k);
+            }
+            return;
+        }
         // tile, slice, axis; y = u_{j+1} (the u slots shifted by one), scale -sgn/dt
         const int tile = (int)(b % ks.ntile);
-        const int slice = (int)((b / ks.ntile) % (N - 1));
         const int a = (int)(b / ((long)ks.ntile * (N - 1)));
         self_advect_T_tile<T, D>(g, cfl, v, u + g.nface, -sgn / dt, t1, g.nface, tile, slice, a);
         return;

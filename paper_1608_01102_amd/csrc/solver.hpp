@@ -27,6 +27,7 @@ constexpr int BS = 256;
 constexpr int RED_BLOCKS = 512;
 constexpr int MAX_COARSE_CELLS = 4096;
 constexpr int MAX_PROJECT_CYCLES = 60;
+constexpr long DIRECT_T_SLOTS = 131072;   // face slots up to which the residual's transpose runs untiled
 
 struct HipError {
     hipError_t e;
@@ -578,6 +579,11 @@ inline void launch_self_advect_T(const Grid& g, T cfl, const T* v, const T* y, T
         const int t = ((ex + TS::X - 1) / TS::X) * ((ey + TS::Y - 1) / TS::Y) * (D == 3 ? (ez + TS::Z - 1) / TS::Z : 1);
         tiles = std::max(tiles, t);
     }
+    if ((long)batch * g.nface <= DIRECT_T_SLOTS) {
+        k_self_advect_T_direct<T, D><<<dim3(blocks_for(g.nface, 256), batch), 256, 0, st>>>(g, cfl, v, y, scale, out,
+                                                                                        g.nface);
+        return;
+    }
     // blocks whose tile lies beyond a smaller lattice exit after the (empty) flush
     k_self_advect_T_tiled<T, D><<<dim3(tiles, batch, D), 256, 0, st>>>(g, cfl, v, y, scale, out, g.nface);
 }
@@ -846,15 +852,22 @@ public:
         KktSplit ks{};
         ks.nbf = blocks_for(g.nface, 256);
         ks.nbc = blocks_for(g.ncell, 256);
+        // small levels: the transpose without tiles (no LDS window, no barriers), since there a launch is
+        // a chain of dependent memory steps and its few atomics are cheap
+        ks.direct = (long)N * g.nface <= DIRECT_T_SLOTS ? 1 : 0;
         ks.ntile = 0;
-        for (int a = 0; a < D; ++a) {
-            const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
-            const int t = ((ex + TS::X - 1) / TS::X) * ((ey + TS::Y - 1) / TS::Y) *
-                          (D == 3 ? (ez + TS::Z - 1) / TS::Z : 1);
-            ks.ntile = std::max(ks.ntile, t);
+        if (ks.direct) {
+            ks.ntile = blocks_for(g.nface, 256);
+        } else {
+            for (int a = 0; a < D; ++a) {
+                const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
+                const int t = ((ex + TS::X - 1) / TS::X) * ((ey + TS::Y - 1) / TS::Y) *
+                              (D == 3 ? (ez + TS::Z - 1) / TS::Z : 1);
+                ks.ntile = std::max(ks.ntile, t);
+            }
         }
         ks.nbz = std::min(blocks_for((long)N * g.nface, 256), 2048);
-        const long blocks = (long)(ks.nbf + ks.nbc) * N + (long)ks.ntile * (N - 1) * D + ks.nbz;
+        const long blocks = (long)(ks.nbf + ks.nbc) * N + (long)ks.ntile * (N - 1) * (ks.direct ? 1 : D) + ks.nbz;
         const double sz = sizeof(T);
         const double fslots = (double)g.nface * N, cslots = (double)g.ncell * N;
         // every sequence the launch reads or writes, once: v, u, w in and r1, r3, t1, t1z out per

@@ -84,6 +84,26 @@ def test_self_advect_and_transpose(n, N, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,B", [((96, 80), 20), ((40, 32, 24), 3), ((33, 17), 300)])
+def test_self_advect_T_tiled_sizes(n, B, prec):
+    """The tiled transpose (LDS window, merged corners, foot-point slots) at
+    sizes above the untiled threshold, with ragged tiles at the lattice
+    edges, and velocities up to 3 cells per step (backtraces past the halo
+    take the global-atomic path)."""
+    S, ctx, g, dt, K = _ctx(n, 2, prec, dt=1.0 / n[0])
+    rng = np.random.default_rng(24)
+    v = _q(np.stack([synthetic.curl_noise_velocity(n, rng, 2.0, 3.0, dt / g.h) for _ in range(B)]), prec)
+    y = _q(_faces(g, rng, B), prec)
+    base = _q(_faces(g, rng, B), prec)
+    acc = to_dev(base, prec)
+    flag(f"self_advect_T tiled n={n} B={B} {prec}")
+    S.stfas_op_self_advect_T(ctx, 0, B, to_dev(v, prec), to_dev(y, prec), 0.75, acc)
+    ref = base + 0.75 * advect.self_advect_T(g, v, y, dt)
+    assert rel(to_np(acc), ref) <= TOL[prec]
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,N", CASES)
 def test_projection_batched(n, N, prec):
     S, ctx, g, dt, K = _ctx(n, N, prec)
