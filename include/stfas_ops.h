@@ -106,8 +106,9 @@ stfas_status stfas_op_ao(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
  * bracketed by HIP events on the context's stream, and the algorithmic
  * bytes each launch must move (its inputs and outputs once) are summed.
  * kernel = 0 disables tracing.  Families: 1 SCGS recurrence, 2 SCGS
- * projection, 3 KKT face rows, 4 velocity-advection transpose, 5 Poisson
- * red-black sweep, 6 density advection, 7 KKT cell rows, 8 SCGS pressure
+ * projection, 3 KKT face and cell rows (one launch), 4 velocity-advection
+ * transpose, 5 Poisson red-black sweep, 6 density advection, 7 (no
+ * separate launch any more; records nothing), 8 SCGS pressure
  * (1, 2 and 8 run only for horizons too long for the fused kernel), 9 SCGS
  * whole-colour kernel (faces and pressure of one colour, time-parallel),
  * 10 the one-launch residual that precedes each fused colour pass (face

@@ -78,23 +78,6 @@ __device__ inline void kkt_cell(const Grid& g, T sgn, const T* __restrict__ v, c
     out4[e] = (res4 ? res4[e] : (T)0) + sgn * du * ih;
 }
 
-template <typename T, int D>
-__global__ void k_kkt_faces(Grid g, int N, T dt, T kr, T cfl, T sgn, const T* __restrict__ v,
-                            const T* __restrict__ pb, const T* __restrict__ u, const T* __restrict__ p,
-                            const T* __restrict__ w, const T* res1, const T* res3, T* out1, T* out3) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= g.nface) return;
-    kkt_face<T, D>(g, N, dt, kr, cfl, sgn, v, pb, u, p, w, res1, res3, out1, out3, f, blockIdx.y);
-}
-
-template <typename T, int D>
-__global__ void k_kkt_cells(Grid g, T sgn, const T* __restrict__ v, const T* __restrict__ u, const T* res2,
-                            const T* res4, T* out2, T* out4) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.ncell) return;
-    kkt_cell<T, D>(g, sgn, v, u, res2, res4, out2, out4, c, blockIdx.y);
-}
-
 // The whole residual of one level in one launch, for the SCGS colour passes:
 // blocks [0, nbf N) face rows, then [.., + nbc N) cell rows, then the tiles
 // of the velocity-advection transpose (slices 0..N-2, d axes), which add

@@ -828,14 +828,19 @@ public:
         const T dt = (T)P.dt;
         const double sz = sizeof(T);
         const double fslots = (double)g.nface * N, cslots = (double)g.ncell * N;
-        // faces: v (also read as v_{i-1} for S), u, w, out1, out3 (+ res1, res3) per face; pbar, p per cell
-        traced(tr, st, l == 0 ? TR_KKT_FACES : TR_NONE, sz * (fslots * (5 + (s1 ? 2 : 0)) + cslots * 2), [&] {
-            k_kkt_faces<T, D><<<dim3(blocks_for(g.nface, BS), N), BS, 0, st>>>(g, N, dt, (T)(P.K / P.r), cfl(l), sgn,
-                                                                              v, pb, u, p, w, s1, s3, o1, o3);
-        });
-        traced(tr, st, l == 0 ? TR_KKT_CELLS : TR_NONE, sz * (fslots * 2 + cslots * (2 + (s2 ? 2 : 0))), [&] {
-            k_kkt_cells<T, D><<<dim3(blocks_for(g.ncell, BS), N), BS, 0, st>>>(g, sgn, v, u, s2, s4, o2, o4);
-        });
+        // face and cell rows in one launch (the split residual kernel without its transpose part):
+        // v, u, w in and out1, out3 out per face slot (+ res1, res3); pbar, p in and out2, out4 out
+        // per cell slot (+ res2, res4)
+        KktSplit ks{};
+        ks.nbf = blocks_for(g.nface, 256);
+        ks.nbc = blocks_for(g.ncell, 256);
+        const long blocks = (long)(ks.nbf + ks.nbc) * N;
+        traced(tr, st, l == 0 ? TR_KKT_FACES : TR_NONE,
+               sz * (fslots * (5 + (s1 ? 2 : 0)) + cslots * (4 + (s2 ? 2 : 0))), [&] {
+                   k_kkt_split<T, D><<<(unsigned)blocks, 256, 0, st>>>(g, N, dt, (T)(P.K / P.r), cfl(l), sgn, ks, v,
+                                                                      pb, u, p, w, s1, s2, s3, s4, o1, o2, o3, o4,
+                                                                      nullptr, nullptr);
+               });
         if (N > 1) {
             // v, y read, out read-modify-write, per face
             traced(tr, st, l == 0 ? TR_SELF_ADVECT_T : TR_NONE, sz * (double)g.nface * (N - 1) * 4,
