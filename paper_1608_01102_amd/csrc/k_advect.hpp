@@ -242,8 +242,13 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
     // b-nodes next to the tile: the tile grown by one node on each side
     constexpr int BX = TS::X + 2, BY = TS::Y + 2, BZ = (D == 3) ? TS::Z + 2 : 1;
     constexpr int BN = BX * BY * BZ;
-    __shared__ T win[WN];
+    // the window accumulates in 64-bit fixed point (integer LDS atomics are
+    // much cheaper than float ones); the scale puts the tile's largest |y|
+    // at 2^52, so up to 1024 contributions per node fit and every value
+    // keeps 2^-52 of that maximum
+    __shared__ unsigned long long win[WN];
     __shared__ T slot[D][TN];
+    __shared__ T wmax[4];
     v += slice * vs;
     y += slice * vs;
     out += slice * vs;
@@ -258,7 +263,7 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
     const int ty0 = ((tile / ntx) % nty) * TS::Y;
     const int tz0 = (D == 3) ? (tile / (ntx * nty)) * TS::Z : 0;
     const int ox = tx0 - H, oy = ty0 - H, oz = (D == 3) ? tz0 - H : 0;
-    for (int e = threadIdx.x; e < WN; e += blockDim.x) win[e] = (T)0;
+    for (int e = threadIdx.x; e < WN; e += blockDim.x) win[e] = 0ull;
     __syncthreads();
     const int lx = threadIdx.x % TS::X, ly = (threadIdx.x / TS::X) % TS::Y, lz = threadIdx.x / (TS::X * TS::Y);
     const int i = tx0 + lx, j = ty0 + ly, k = tz0 + lz;
@@ -292,6 +297,17 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
             for (int q = 0; q < (1 << D); ++q) wq[q] = it.weight(q) * yv;
         }
     }
+    // fixed-point scale from the largest |y| of the tile
+    T my = 0;
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) my = fmax(my, fabs(wq[q]));
+    for (int o = 32; o > 0; o >>= 1) my = fmax(my, __shfl_xor(my, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = my;
+    __syncthreads();
+    my = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    int e2 = 0;
+    (void)frexp((double)my, &e2);
+    const double fx = ldexp(1.0, 52 - e2), ifx = ldexp(1.0, e2 - 52);
     // Weights.  Neighbouring lanes of a row usually backtrace into
     // neighbouring cells, so the +x corner of lane l is the 0 corner of lane
     // l+1: that lane adds both (one LDS atomic instead of two).  The match
@@ -314,7 +330,7 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
             if (ca == 0 || ca == g.n[a]) continue;          // wall node of the a-lattice
             const int wx = ci - ox, wy = cj - oy, wz = ck - oz;
             if (wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
-                atomicAdd(&win[(wz * WY + wy) * WX + wx], w);
+                atomicAdd(&win[(wz * WY + wy) * WX + wx], (unsigned long long)llrint((double)w * fx));
             else
                 atomic_add(out + face_index(g, a, ci, cj, ck), w);
         }
@@ -331,7 +347,7 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
     // flush the a-window: weights plus the foot-point term of the source at the node
     for (int e = threadIdx.x; e < WN; e += blockDim.x) {
         const int ci = ox + e % WX, cj = oy + (e / WX) % WY, ck = oz + e / (WX * WY);
-        T val = win[e] + src(a, ci, cj, ck);
+        T val = (T)((double)(long long)win[e] * ifx) + src(a, ci, cj, ck);
         if (val == (T)0) continue;
         if (ci < 0 || cj < 0 || ck < 0 || ci >= ex || cj >= ey || (D == 3 && ck >= ez)) continue;
         atomic_add(out + face_index(g, a, ci, cj, ck), val);
