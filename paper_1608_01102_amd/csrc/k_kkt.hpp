@@ -319,16 +319,22 @@ __global__ void k_scgs_thomas(Grid g, int N, ColourSet cs, const T* __restrict__
 // blocks.  Every load is unconditional (blocks past the end read a clamped
 // block of the same parity and are masked), so all of a lane's loads are in
 // flight together.
-template <typename T, int D, int G, int CH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
-k_scgs_colour(Grid g, int N, int L, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ t1,
-              const T* __restrict__ r2, const T* __restrict__ r3, const T* __restrict__ r4, T* v, T* pb, T* u, T* p,
-              const T* __restrict__ tdiag, const T* __restrict__ tsub, const T* __restrict__ tsup,
-              const T* __restrict__ tcp, const T* __restrict__ tinv, T omega) {
+// ROWS = false: the G lanes of a cell are adjacent in one wave (lane = chunk)
+// and the chunk maps are joined with shuffles.  ROWS = true: a workgroup
+// takes CPW consecutive cells of the colour and all G chunks, thread
+// g * CPW + c holding chunk g of cell c, so that each load of a wave reads
+// CPW neighbouring cells at one block (coalesced); the chunk maps are joined
+// through LDS (sc: G x (1 + 2d) x CPW values).
+template <typename T, int D, int G, int CH, bool ROWS, int CPW = 64>
+__device__ inline void scgs_colour_body(const Grid& g, int N, int L, const ColourSet& cs, int q, int lane, T* sc,
+                                        const T* __restrict__ r1, const T* __restrict__ t1,
+                                        const T* __restrict__ r2, const T* __restrict__ r3,
+                                        const T* __restrict__ r4, T* v, T* pb, T* u, T* p,
+                                        const T* __restrict__ tdiag, const T* __restrict__ tsub,
+                                        const T* __restrict__ tsup, const T* __restrict__ tcp,
+                                        const T* __restrict__ tinv, T omega) {
     constexpr int NF = 2 * D;
     const int M = 2 * N;
-    const int lane = threadIdx.x % G;
-    const int q = (blockIdx.x * blockDim.x + threadIdx.x) / G;
     const bool active = q < cs.total;
     // lanes past the last cell work on the last cell and write nothing
     int i, j, k;
@@ -399,25 +405,47 @@ k_scgs_colour(Grid g, int N, int L, ColourSet cs, const T* __restrict__ r1, cons
         prod = on ? a * prod : prod;
         pv[t] = prod;
     }
-    T A = prod;
+    if constexpr (ROWS) {
+        // chunk maps to LDS, then each chunk folds the maps of the chunks before it
+        const int l = threadIdx.x & (CPW - 1);
+        sc[(lane * (1 + NF)) * CPW + l] = prod;
 #pragma unroll
-    for (int off = 1; off < G; off <<= 1) {
-        const T Ap = __shfl_up(A, off, G);
-        T Bp[NF];
+        for (int e = 0; e < NF; ++e) sc[(lane * (1 + NF) + 1 + e) * CPW + l] = val[e];
+        __syncthreads();
+        T cin[NF];
 #pragma unroll
-        for (int e = 0; e < NF; ++e) Bp[e] = __shfl_up(val[e], off, G);
-        if (lane >= off) {
+        for (int e = 0; e < NF; ++e) cin[e] = 0;
+        for (int h = 0; h < lane; ++h) {
+            const T Ah = sc[(h * (1 + NF)) * CPW + l];
 #pragma unroll
-            for (int e = 0; e < NF; ++e) val[e] = A * Bp[e] + val[e];
-            A = A * Ap;
+            for (int e = 0; e < NF; ++e) cin[e] = Ah * cin[e] + sc[(h * (1 + NF) + 1 + e) * CPW + l];
         }
-    }
+        __syncthreads();
 #pragma unroll
-    for (int e = 0; e < NF; ++e) {
-        T cin = __shfl_up(val[e], 1, G);
-        cin = lane == 0 ? (T)0 : cin;
+        for (int e = 0; e < NF; ++e)
 #pragma unroll
-        for (int t = 0; t < CH; ++t) rv[t][e] += pv[t] * cin;
+            for (int t = 0; t < CH; ++t) rv[t][e] += pv[t] * cin[e];
+    } else {
+        T A = prod;
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            const T Ap = __shfl_up(A, off, G);
+            T Bp[NF];
+#pragma unroll
+            for (int e = 0; e < NF; ++e) Bp[e] = __shfl_up(val[e], off, G);
+            if (lane >= off) {
+#pragma unroll
+                for (int e = 0; e < NF; ++e) val[e] = A * Bp[e] + val[e];
+                A = A * Ap;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < NF; ++e) {
+            T cin = __shfl_up(val[e], 1, G);
+            cin = lane == 0 ? (T)0 : cin;
+#pragma unroll
+            for (int t = 0; t < CH; ++t) rv[t][e] += pv[t] * cin;
+        }
     }
     // ---- back substitution, chunk-local from a zero carry
     prod = 1;
@@ -435,25 +463,46 @@ k_scgs_colour(Grid g, int N, int L, ColourSet cs, const T* __restrict__ r1, cons
         prod = on ? cc * prod : prod;
         pv[t] = prod;
     }
-    A = prod;
+    if constexpr (ROWS) {
+        // each chunk folds the maps of the chunks after it, last first
+        const int l = threadIdx.x & (CPW - 1);
+        sc[(lane * (1 + NF)) * CPW + l] = prod;
 #pragma unroll
-    for (int off = 1; off < G; off <<= 1) {
-        const T An = __shfl_down(A, off, G);
-        T Bn[NF];
+        for (int e = 0; e < NF; ++e) sc[(lane * (1 + NF) + 1 + e) * CPW + l] = val[e];
+        __syncthreads();
+        T cin[NF];
 #pragma unroll
-        for (int e = 0; e < NF; ++e) Bn[e] = __shfl_down(val[e], off, G);
-        if (lane + off < G) {
+        for (int e = 0; e < NF; ++e) cin[e] = 0;
+        for (int h = G - 1; h > lane; --h) {
+            const T Ah = sc[(h * (1 + NF)) * CPW + l];
 #pragma unroll
-            for (int e = 0; e < NF; ++e) val[e] = A * Bn[e] + val[e];
-            A = A * An;
+            for (int e = 0; e < NF; ++e) cin[e] = Ah * cin[e] + sc[(h * (1 + NF) + 1 + e) * CPW + l];
         }
-    }
 #pragma unroll
-    for (int e = 0; e < NF; ++e) {
-        T cin = __shfl_down(val[e], 1, G);
-        cin = lane == G - 1 ? (T)0 : cin;
+        for (int e = 0; e < NF; ++e)
 #pragma unroll
-        for (int t = 0; t < CH; ++t) rv[t][e] += pv[t] * cin;
+            for (int t = 0; t < CH; ++t) rv[t][e] += pv[t] * cin[e];
+    } else {
+        T A = prod;
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            const T An = __shfl_down(A, off, G);
+            T Bn[NF];
+#pragma unroll
+            for (int e = 0; e < NF; ++e) Bn[e] = __shfl_down(val[e], off, G);
+            if (lane + off < G) {
+#pragma unroll
+                for (int e = 0; e < NF; ++e) val[e] = A * Bn[e] + val[e];
+                A = A * An;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < NF; ++e) {
+            T cin = __shfl_down(val[e], 1, G);
+            cin = lane == G - 1 ? (T)0 : cin;
+#pragma unroll
+            for (int t = 0; t < CH; ++t) rv[t][e] += pv[t] * cin;
+        }
     }
     // ---- apply the corrections of this chunk (relaxed by omega)
 #pragma unroll
@@ -471,6 +520,33 @@ k_scgs_colour(Grid g, int N, int L, ColourSet cs, const T* __restrict__ r1, cons
             ((t & 1) ? pb : p)[jj * C + c] = po[t] + omega * (acc * gn_inv - gr[t]) * gn_inv;
         }
     }
+}
+
+template <typename T, int D, int G, int CH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_scgs_colour(Grid g, int N, int L, ColourSet cs, const T* __restrict__ r1, const T* __restrict__ t1,
+              const T* __restrict__ r2, const T* __restrict__ r3, const T* __restrict__ r4, T* v, T* pb, T* u, T* p,
+              const T* __restrict__ tdiag, const T* __restrict__ tsub, const T* __restrict__ tsup,
+              const T* __restrict__ tcp, const T* __restrict__ tinv, T omega) {
+    scgs_colour_body<T, D, G, CH, false>(g, N, L, cs, (int)((blockIdx.x * blockDim.x + threadIdx.x) / G),
+                                         (int)(threadIdx.x % G), nullptr, r1, t1, r2, r3, r4, v, pb, u, p, tdiag,
+                                         tsub, tsup, tcp, tinv, omega);
+}
+
+template <typename T, int D, int G, int CH, int CPW>
+__global__ void __launch_bounds__(CPW * G) k_scgs_colour_rows(Grid g, int N, int L, ColourSet cs,
+                                                             const T* __restrict__ r1, const T* __restrict__ t1,
+                                                             const T* __restrict__ r2, const T* __restrict__ r3,
+                                                             const T* __restrict__ r4, T* v, T* pb, T* u, T* p,
+                                                             const T* __restrict__ tdiag,
+                                                             const T* __restrict__ tsub,
+                                                             const T* __restrict__ tsup,
+                                                             const T* __restrict__ tcp,
+                                                             const T* __restrict__ tinv, T omega) {
+    __shared__ T sc[G * (1 + 2 * D) * CPW];
+    scgs_colour_body<T, D, G, CH, true, CPW>(g, N, L, cs, (int)(blockIdx.x * CPW + (threadIdx.x & (CPW - 1))),
+                                             (int)(threadIdx.x / CPW), sc, r1, t1, r2, r3, r4, v, pb, u, p, tdiag,
+                                             tsub, tsup, tcp, tinv, omega);
 }
 
 // Pressure part: dpi_k = (sum_l T_kl xi_l - ghat^T r_k) / |g|, one thread per

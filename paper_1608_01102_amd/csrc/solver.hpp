@@ -534,6 +534,8 @@ inline bool colour_shape(int M, long cells, int& G, int& L, int& CH) {
     // registers allow; small ones are latency-bound: up to 64 lanes per cell
     if (cells < 4096)
         while (G < 64 && (M + 2 * G - 1) / (2 * G) >= 2) G <<= 1;
+    else    // row layout: chunks short enough for its register budget (see launch_scgs_colour)
+        while (G < 16 && (M + G - 1) / G > (sizeof(T) == 8 ? 4 : 8)) G <<= 1;
     L = (M + G - 1) / G;
     L += L & 1;
     while (G > 1 && (long)(G / 2) * L >= M) G >>= 1;
@@ -546,9 +548,32 @@ inline void launch_scgs_colour(int G, int L, int CH, const Grid& g, int N, const
                                const T* t1, const T* r2, const T* r3, const T* r4, T* v, T* pb, T* u, T* p,
                                const T* tdiag, const T* tsub, const T* tsup, const T* tcp, const T* tinv, T omega,
                                hipStream_t st) {
+    constexpr int CHMAX = (sizeof(T) == 4 && D == 2) ? 16 : 8;
+    // row-layout chunk lengths that fit the 256 registers of a 512-thread workgroup without spilling
+    constexpr int RMAX = sizeof(T) == 8 ? 4 : (D == 3 ? 8 : 12);
+    if (cs.total >= 4096 && G <= 16 && CH <= RMAX) {
+        // large colours: row layout, 512 threads = G chunks x (512 / G) neighbouring cells
+        constexpr int NT = 512;
+#define STFAS_ROWS_CASE(GG, CC)                                                                                  \
+    if constexpr (CC <= RMAX)                                                                                    \
+        if (G == GG && CH == CC) {                                                                               \
+            constexpr int CPW = NT / GG > 64 ? 64 : NT / GG;                                                     \
+            k_scgs_colour_rows<T, D, GG, CC, CPW><<<(cs.total + CPW - 1) / CPW, CPW * GG, 0, st>>>(             \
+                g, N, L, cs, r1, t1, r2, r3, r4, v, pb, u, p, tdiag, tsub, tsup, tcp, tinv, omega);              \
+            return;                                                                                              \
+        }
+#define STFAS_ROWS_G(GG)                                                                                         \
+    STFAS_ROWS_CASE(GG, 2) STFAS_ROWS_CASE(GG, 4) STFAS_ROWS_CASE(GG, 8) STFAS_ROWS_CASE(GG, 12)
+        STFAS_ROWS_G(1)
+        STFAS_ROWS_G(2)
+        STFAS_ROWS_G(4)
+        STFAS_ROWS_G(8)
+        STFAS_ROWS_G(16)
+#undef STFAS_ROWS_G
+#undef STFAS_ROWS_CASE
+    }
     const long threads = (long)cs.total * G;
     const int blocks = (int)((threads + 255) / 256);
-    constexpr int CHMAX = (sizeof(T) == 4 && D == 2) ? 16 : 8;
 #define STFAS_COLOUR_CASE(GG, CC)                                                                                \
     if constexpr (CC <= CHMAX)                                                                                   \
         if (G == GG && CH == CC)                                                                                 \

@@ -233,10 +233,12 @@ def test_scgs_sweep_long_horizon(n, N, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("n,N", [((128, 128), 40)])
+@pytest.mark.parametrize("n,N", [((128, 128), 40), ((128, 128), 20), ((32, 32, 32), 10)])
 def test_scgs_sweep_benchmark_shapes(n, N, prec):
-    """The 128x128 x 40 grid: the whole-colour kernel takes the launch shape
-    the benchmark times (8 lanes per cell, chunks of 10 blocks)."""
+    """Colours of at least 4096 cells take the row layout of the colour pass
+    (chunks across the waves of a workgroup, chunk maps joined in LDS):
+    128x128 x 40 is the shape the benchmark times (16 chunks of 6 blocks in
+    FP32), 128x128 x 20 and 32^3 x 10 reach it in FP64 and in 3D."""
     S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=0.7)
     kr = K / 1e-2
     rng = np.random.default_rng(19)
