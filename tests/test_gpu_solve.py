@@ -129,3 +129,44 @@ def test_step_forward_backward(n, prec):
     S.stfas_step_backward(prob, to_dev(rho, prec), to_dev(v, prec), to_dev(grn, prec), to_dev(gvn, prec), gr, gv, gu)
     a, b, c = step.step_backward(g, rho, v, grn, gvn, dt)
     assert rel(to_np(gr), a) <= tol and rel(to_np(gv), b) <= tol and rel(to_np(gu), c) <= tol
+
+
+def _edge_case(name):
+    """Degenerate and boundary instances of the full solve."""
+    rng = np.random.default_rng(31)
+    if name == "one_step":                     # N = 1: the keyframe is the first step
+        return synthetic.small_problem((8, 8), 1, seed=3, r=1e-2)
+    if name == "two_keys_3d":                  # keyframes in the middle and at the end
+        w = synthetic.small_problem((8, 8, 8), 4, seed=4, r=1e-2)
+        w["keys"] = {2: synthetic.smooth_noise_density((8, 8, 8), rng, 1.0), 4: w["keys"][4]}
+        return w
+    if name == "odd_coarse":                   # 12 x 10: the hierarchy stops at 6 x 5
+        return synthetic.small_problem((12, 10), 3, seed=5, r=1e-2)
+    if name == "zero":                         # no density anywhere: the control stays zero
+        w = synthetic.small_problem((8, 8), 3, seed=6, r=1e-2)
+        w["rho0"] = np.zeros_like(w["rho0"])
+        w["keys"] = {3: np.zeros_like(w["keys"][3])}
+        return w
+    raise ValueError(name)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["one_step", "two_keys_3d", "odd_coarse", "zero"])
+def test_solve_edge_cases(name, prec):
+    w = _edge_case(name)
+    u, st, ref = _solve_pair(w, prec, 2, 2, eps_admm=1.0)
+    tol = TOL[prec] if prec == "fp64" else 1e-3
+    scale = max(float(np.abs(ref.u).max()), 1e-30)
+    if name == "zero":
+        assert np.abs(u).max() == 0.0 and np.abs(ref.u).max() == 0.0
+        assert st["objective"] == 0.0
+    elif name == "one_step":
+        # with one step the control acts only after the last density: it stays zero,
+        # and the objective is the keyframe mismatch of the uncontrolled density
+        assert np.abs(u).max() == 0.0 and np.abs(ref.u).max() == 0.0
+        assert abs(st["objective"] - ref.objective) <= tol * ref.objective
+    else:
+        assert rel(u, ref.u) <= tol
+        assert abs(st["objective"] - ref.objective) <= tol * max(ref.objective, 1e-30)
+    assert np.isfinite(u).all() and np.abs(u).max() <= 10 * scale
+    assert st["admm_iters"] == ref.admm_iters and st["vcycles"] == ref.vcycles
