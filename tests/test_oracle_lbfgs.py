@@ -1,0 +1,68 @@
+"""Pins of the L-BFGS baseline oracle (the paper's comparison optimiser):
+the adjoint gradient against central finite differences, and the
+optimiser against problems whose minimiser is known."""
+import numpy as np
+import pytest
+from scipy.optimize import rosen, rosen_der
+
+import synthetic
+from oracle import lbfgs, metric
+from oracle.admm import objectives, resimulate
+from oracle.grid import Grid
+
+
+def _tiny(seed=0):
+    w = synthetic.small_problem((8, 8), 3, seed=seed, r=1e-2)
+    rng = np.random.default_rng(seed + 10)
+    w["keys"][2] = synthetic.smooth_noise_density((8, 8), rng, 1.0)
+    return w
+
+
+def test_gradient_matches_finite_differences():
+    w = _tiny()
+    g = Grid(w["n"])
+    N, dt, r = w["num_steps"], w["dt"], w["r"]
+    levels = metric.default_levels(w["n"])
+    rng = np.random.default_rng(1)
+    u = 0.05 * np.stack([synthetic.random_faces(w["n"], rng) for _ in range(N)])
+
+    def J(x):
+        rho, _ = resimulate(g, w["rho0"], x, dt)
+        return objectives(g, rho, w["keys"], x, r, levels)[0]
+
+    rho, v = resimulate(g, w["rho0"], u, dt)
+    gr = lbfgs.gradient(g, rho, v, u, w["keys"], r, dt, levels)
+    for k in range(3):
+        d = np.stack([synthetic.random_faces(w["n"], rng) for _ in range(N)])
+        eps = 1e-6
+        fd = (J(u + eps * d) - J(u - eps * d)) / (2 * eps)
+        assert abs(fd - np.sum(gr * d)) <= 1e-6 * max(abs(fd), 1e-12), k
+
+
+def test_minimize_quadratic_reaches_solution():
+    rng = np.random.default_rng(2)
+    n = 30
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(np.logspace(0, 2, n)) @ Q.T
+    b = rng.standard_normal(n)
+    x, hist, done = lbfgs.minimize(lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b), np.zeros(n), 200)
+    xs = np.linalg.solve(A, b)
+    # an Armijo search on f resolves x to about sqrt(machine epsilon) times the conditioning
+    assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs)
+    assert all(hist[i + 1] <= hist[i] for i in range(len(hist) - 1))
+
+
+def test_minimize_rosenbrock():
+    x, hist, done = lbfgs.minimize(lambda x: (rosen(x), rosen_der(x)), np.array([-1.2, 1.0]), 200)
+    assert np.allclose(x, [1.0, 1.0], atol=1e-6)
+    assert done < 200
+
+
+def test_solve_decreases_objective():
+    w = _tiny(3)
+    g = Grid(w["n"])
+    levels = metric.default_levels(w["n"])
+    u, hist, done = lbfgs.solve(g, w["rho0"], w["keys"], w["num_steps"], w["r"], w["dt"], levels, 6)
+    assert done == 6
+    assert all(hist[i + 1] <= hist[i] for i in range(len(hist) - 1))
+    assert hist[-1] < hist[0]
