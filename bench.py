@@ -29,6 +29,8 @@ def parse():
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--trace-kernel", default="kkt_split",
                     help="kernel family whose launches on the finest level are timed with HIP events")
+    ap.add_argument("--lbfgs-iters", type=int, default=200,
+                    help="iteration cap of the L-BFGS comparison (0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=16, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
@@ -109,6 +111,8 @@ def main():
         out["fp64_gpu"] = {"objective": s64["objective"], "admm_iters": s64["admm_iters"],
                            "seconds": s64["seconds"], "kf_err_mixed_vs_fp64": kf}
         c64.destroy()
+    if args.lbfgs_iters > 0:
+        out["lbfgs_baseline"] = lbfgs_run(S, ctx, rho0, ks, keys, args.lbfgs_iters, kw["eps_admm"], last)
     ctx.destroy()
     if args.serve_requests > 0:
         out["serving"] = serving_run(args)
@@ -132,6 +136,24 @@ def measured_traffic(kernel):
     if vals.get("kernel_source_hash") != kernel_source_hash():
         return None
     return float(vals["traffic_bytes_per_launch"])
+
+
+def lbfgs_run(S, ctx, rho0, ks, keys, iters, eps, admm_stats):
+    """The gradient-based baseline of the paper's comparison (outside the
+    step clock): L-BFGS from u = 0 on the same problem, precision and
+    objective, stopped by the same visual-difference rule as the ADMM loop
+    (or the iteration cap); reports its time, its objective and the first
+    iteration (if any) at which it reaches the ADMM solve's objective."""
+    import torch
+    u = torch.zeros(ctx.N * ctx.faces, dtype=torch.float32, device=rho0.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, done = S.stfas_lbfgs(ctx, rho0, ks, keys, u, iters, eps)
+    sec = time.perf_counter() - t0
+    target = admm_stats["objective"]
+    reach = next((i for i, j in enumerate(hist) if j <= target), None)
+    return {"iters": done, "iter_cap": iters, "eps_stop": eps, "stopped_before_cap": done < iters, "seconds": sec, "objective_start": hist[0], "objective": hist[-1],
+            "admm_objective": target, "admm_seconds": admm_stats["seconds"], "reaches_admm_at_iter": reach}
 
 
 def keyframe_error(S, p64, w, u_a, u_b):

@@ -120,6 +120,29 @@ stfas_status stfas_create_in(const stfas_problem* prob, void* hip_stream, void* 
 stfas_status stfas_solve(stfas_ctx* ctx, const void* rho0, int32_t num_key, const int32_t* key_steps,
                          const void* key_rho, void* u_out, stfas_stats* stats);
 
+/* Gradient-based baseline (Sec. 7, the comparison with LBFGS; Sec. 3.2 for
+ * the reduced problem): L-BFGS over the controls with the simulation
+ * eliminated, J(u) = 1/2 sum_k <e_k, C e_k> + r/2 |u|^2 (eq:opt), its
+ * gradient by the adjoint of the step chain (one forward and one backward
+ * simulation per evaluation, each projection to poisson_rtol).  History 8,
+ * initial Hessian scale s'y / y'y (1 / |g| at the first iteration), Armijo
+ * backtracking line search (c1 = 1e-4, first step 1, up to 20 halvings).
+ * Runs at most iters iterations; stops early when the line search finds no
+ * decrease, or, for eps_stop > 0, after an iterate whose density trajectory
+ * differs from the previous one by at most eps_stop (max over steps and
+ * cells: the ADMM stop of Alg:outter, which Sec. 7 applies to both
+ * optimisers).  eps_stop < 0 or NaN: STFAS_E_INVALID.
+ * Keys as for stfas_solve.  u_inout [N][faces] (device): the starting
+ * controls in, the last accepted iterate out.  J_hist (host, may be NULL):
+ * iters + 1 entries, J at the start and after each accepted iteration;
+ * *iters_done (may be NULL): the iterations done.  The first call on a
+ * context allocates the optimiser's buffers ((N+3)(cells+faces) + (N+1) cells + 23 N faces
+ * elements), freed by stfas_destroy; a context made by stfas_create_in makes
+ * no allocation, so there the call returns STFAS_E_INVALID.  Blocks. */
+stfas_status stfas_lbfgs(stfas_ctx* ctx, const void* rho0, int32_t num_key, const int32_t* key_steps,
+                         const void* key_rho, void* u_inout, int32_t iters, double eps_stop, int32_t* iters_done,
+                         double* J_hist);
+
 /* One simulation step (Sec. 3.1 eq:NSA-eq:Conv with semi-Lagrangian advection):
  *   rho_out = A(rho, v),  v_out = Q(S(v) + dt u),  p_out = phi/dt (may be NULL).
  * work: caller scratch of stfas_step_work_bytes(prob) bytes.  Asynchronous

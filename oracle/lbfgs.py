@@ -16,7 +16,10 @@ paper's), initial Hessian gamma I with gamma = s^T y / y^T y of the newest
 pair, and 1 / |g| on the first iteration; a backtracking line search on
 the Armijo condition (c1 = 1e-4, first trial step 1, halved up to 20
 times); a pair with y^T s <= 1e-12 |s| |y| is not stored.  The paper does
-not state its line search: this is the reading.
+not state its line search: this is the reading.  Stopping (Sec. 7 uses the
+same criterion for both optimisers, the ADMM one of Sec. 5): after an
+accepted iterate, stop when the largest change of the density over all
+steps between it and the previous iterate is at most eps_stop.
 """
 import numpy as np
 
@@ -40,10 +43,11 @@ def gradient(g: Grid, rho, v, u, keys, r, dt, levels):
     return gu + r * u
 
 
-def minimize(fg, x0, iters, m=8, c1=1e-4, max_halvings=20):
+def minimize(fg, x0, iters, m=8, c1=1e-4, max_halvings=20, stop=None):
     """Generic L-BFGS: fg(x) -> (f, grad).  Returns x, the f history (one
     entry per accepted iterate, starting with f(x0)) and the iterations done
-    (fewer than iters when the line search finds no decrease)."""
+    (fewer than iters when the line search finds no decrease, or when
+    stop(x_previous, x_accepted) is true after an accepted iterate)."""
     x = np.array(x0, dtype=np.float64)
     f, gr = fg(x)
     hist = [f]
@@ -89,14 +93,18 @@ def minimize(fg, x0, iters, m=8, c1=1e-4, max_halvings=20):
             if len(S) > m:
                 S.pop(0)
                 Y.pop(0)
+        x_prev = x
         x, f, gr = xt, ft, gt
         hist.append(f)
         done += 1
+        if stop is not None and stop(x_prev, x):
+            break
     return x, hist, done
 
 
-def solve(g: Grid, rho0, keys, N, r, dt, levels, iters, u0=None, m=8):
-    """L-BFGS on J(u) over N steps from u0 (zero by default).  Returns u,
+def solve(g: Grid, rho0, keys, N, r, dt, levels, iters, u0=None, m=8, eps_stop=0.0):
+    """L-BFGS on J(u) over N steps from u0 (zero by default), at most iters
+    iterations; eps_stop > 0 adds the visual-difference stop.  Returns u,
     the J history and the iterations done."""
     shape = (N, g.nface)
     u0 = np.zeros(shape) if u0 is None else np.asarray(u0, dtype=np.float64).reshape(shape)
@@ -107,5 +115,10 @@ def solve(g: Grid, rho0, keys, N, r, dt, levels, iters, u0=None, m=8):
         f = objectives(g, rho, keys, u, r, levels)[0]
         return f, gradient(g, rho, v, u, keys, r, dt, levels).ravel()
 
-    x, hist, done = minimize(fg, u0.ravel(), iters, m=m)
+    def visual_stop(xa, xb):
+        ra, _ = resimulate(g, rho0, xa.reshape(shape), dt)
+        rb, _ = resimulate(g, rho0, xb.reshape(shape), dt)
+        return float(np.max(np.abs(rb - ra))) <= eps_stop
+
+    x, hist, done = minimize(fg, u0.ravel(), iters, m=m, stop=visual_stop if eps_stop > 0 else None)
     return x.reshape(shape), hist, done

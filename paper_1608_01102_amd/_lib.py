@@ -47,6 +47,8 @@ _SIGS = {
                                   ctypes.POINTER(c_void_p)]),
     "stfas_solve": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.POINTER(c_int32), c_void_p, c_void_p,
                               ctypes.POINTER(StfasStats)]),
+    "stfas_lbfgs": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.POINTER(c_int32), c_void_p, c_void_p,
+                              c_int32, ctypes.c_double, ctypes.POINTER(c_int32), ctypes.POINTER(ctypes.c_double)]),
     "stfas_step_forward": (c_int32, [ctypes.POINTER(StfasProblem), c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p, c_void_p, c_void_p]),
     "stfas_step_backward": (c_int32, [ctypes.POINTER(StfasProblem), c_void_p, c_void_p, c_void_p, c_void_p,

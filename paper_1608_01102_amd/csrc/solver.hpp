@@ -493,6 +493,7 @@ public:
     virtual void op_prolong(int, stfas_state, double, stfas_state) = 0;
     virtual int op_nso(stfas_state, const void*, double*) = 0;
     virtual void op_ao(const void*, int, const int*, const void*, const void*, void*, void*, double*) = 0;
+    virtual int lbfgs(const void*, int, const int*, const void*, void*, int, double, double*) = 0;
     Tracer tr;
     void trace_enable(int kind, int cap) {
         tr.reset();
@@ -653,7 +654,9 @@ public:
         L = stfas_levels(g0);
         pois.init(g0, p.N, s);
     }
-    ~Solver() override {}
+    ~Solver() override {
+        if (lb) (void)hipFree(lb);
+    }
 
     int nlevels() const override { return (int)L.size(); }
     const Grid& level(int l) const override { return L[l]; }
@@ -1137,6 +1140,195 @@ public:
     }
 
     void blend(const T* x, const T* y, T alpha, T* out, long n);
+
+    // ------------------------------------------------------------ L-BFGS baseline
+    // The gradient-based optimiser the paper compares against: L-BFGS on the
+    // reduced objective J(u) = 1/2 sum_k <e_k, C e_k> + r/2 |u|^2 with the
+    // simulation eliminated, its gradient by the adjoint of the step chain.
+    // History 8, gamma = s'y / y'y (1/|g| on the first iteration), Armijo
+    // backtracking (c1 = 1e-4, first step 1, up to 20 halvings); pairs with
+    // y's <= 1e-12 |s||y| are not kept.  With eps_stop > 0 it stops after an
+    // accepted iterate whose density trajectory differs from the previous
+    // one by at most eps_stop (max over all steps and cells), the ADMM stop
+    // of Alg:outter, which the paper applies to both optimisers (Sec. 7).
+    // Buffers are allocated on the first
+    // call and freed with the context.  Returns the iterations done, -1 when
+    // the buffers cannot be allocated, -2 for a non-finite objective.
+    static constexpr int LB_M = 8;
+    T* lb = nullptr;
+    static constexpr int LB_R = LB_M + 1;   // ring slots: the newest pair is written into a free one
+    T *lb_rho, *lb_rho_prev, *lb_v, *lb_x, *lb_g, *lb_xt, *lb_gt, *lb_d, *lb_s[LB_R], *lb_y[LB_R];
+    T *lb_grho, *lb_grho2, *lb_gv, *lb_gw;
+    bool lb_alloc() {
+        if (lb) return true;
+        const long C = L[0].ncell, F = L[0].nface;
+        Arena A;
+        auto plan = [&](Arena& a) {
+            lb_rho = a.take<T>((N + 1) * C);
+            lb_rho_prev = a.take<T>((N + 1) * C);
+            lb_v = a.take<T>((N + 1) * F);
+            lb_x = a.take<T>(N * F);
+            lb_g = a.take<T>(N * F);
+            lb_xt = a.take<T>(N * F);
+            lb_gt = a.take<T>(N * F);
+            lb_d = a.take<T>(N * F);
+            for (int k = 0; k < LB_R; ++k) {
+                lb_s[k] = a.take<T>(N * F);
+                lb_y[k] = a.take<T>(N * F);
+            }
+            lb_grho = a.take<T>(C);
+            lb_grho2 = a.take<T>(C);
+            lb_gv = a.take<T>(F);
+            lb_gw = a.take<T>(F);
+        };
+        plan(A);
+        if (hipMalloc((void**)&lb, A.off) != hipSuccess) {
+            (void)hipGetLastError();
+            lb = nullptr;
+            return false;
+        }
+        Arena B;
+        B.base = (char*)lb;
+        plan(B);
+        return true;
+    }
+    double lb_dot(const T* a, const T* b) {
+        reduce(RED_DOT, (long)N * L[0].nface, a, b, 0, false);
+        readback(1);
+        return host_out[0];
+    }
+    // trajectory of u from (rho0, v = 0) into lb_rho, lb_v; returns J(u)
+    double lb_forward(const T* rho0, const T* u, int nk, const int* ks, const T* keys) {
+        const long C = L[0].ncell, F = L[0].nface;
+        copy(lb_rho, rho0, C);
+        fill(lb_v, F, (T)0);
+        for (int i = 0; i < N; ++i) {
+            advect(lb_rho + i * C, lb_v + i * F, lb_rho + (i + 1) * C, 1);
+            self_advect(0, lb_v + i * F, u + i * F, rs_w, 1);
+            project(rs_w, lb_v + (i + 1) * F, nullptr, 1);
+        }
+        zero_slots(2);
+        for (int q = 0; q < nk; ++q) {
+            axpby(C, (T)1, lb_rho + (long)ks[q] * C, (T)-1, keys + q * C, ce_e);
+            metric(ce_e, ce_acc);
+            reduce(RED_DOT, C, ce_e, ce_acc, 0, true);
+        }
+        reduce(RED_SUMSQ_DIFF, N * F, u, nullptr, 1, false);
+        readback(2);
+        return 0.5 * host_out[0] + 0.5 * P.r * host_out[1];
+    }
+    // gradient of J at the trajectory in lb_rho, lb_v into gout
+    void lb_gradient(const T* u, int nk, const int* ks, const T* keys, T* gout) {
+        const long C = L[0].ncell, F = L[0].nface;
+        fill(lb_grho, C, (T)0);
+        fill(lb_gv, F, (T)0);
+        for (int i = N; i >= 1; --i) {
+            for (int q = 0; q < nk; ++q)
+                if (ks[q] == i) {
+                    axpby(C, (T)1, lb_rho + (long)i * C, (T)-1, keys + q * C, ce_e);
+                    metric(ce_e, ce_acc);
+                    axpby(C, (T)1, lb_grho, (T)1, ce_acc, lb_grho);
+                }
+            const T* rho = lb_rho + (long)(i - 1) * C;
+            const T* v = lb_v + (long)(i - 1) * F;
+            project(lb_gv, lb_gw, nullptr, 1);                                   // g_w = Q g_v'
+            axpby(F, (T)P.dt, lb_gw, (T)0, nullptr, gout + (long)(i - 1) * F);   // g_u = dt g_w
+            advect_dv_T(lb_grho, rho, v, nullptr, (T)1, lb_gv, 1);               // (dA/dv)^T g_rho'
+            self_advect_T(0, v, lb_gw, (T)1, lb_gv, 1);                          // + J_S^T g_w
+            fill(lb_grho2, C, (T)0);
+            advect_T(lb_grho, v, lb_grho2, 1);                                   // W^T g_rho'
+            std::swap(lb_grho, lb_grho2);
+        }
+        axpby(N * F, (T)1, gout, (T)P.r, u, gout);                               // + r u
+    }
+    int lbfgs(const void* rho0v, int nk, const int* ks, const void* keysv, void* uv, int iters, double eps_stop,
+              double* hist) override {
+        const T* rho0 = (const T*)rho0v;
+        const T* keys = (const T*)keysv;
+        T* u = (T*)uv;
+        const long n = (long)N * L[0].nface;
+        if (!lb_alloc()) return -1;
+        copy(lb_x, u, n);
+        double f = lb_forward(rho0, lb_x, nk, ks, keys);
+        lb_gradient(lb_x, nk, ks, keys, lb_g);
+        if (hist) hist[0] = f;
+        int ns = 0, head = 0, done = 0;    // ns stored pairs; the newest at head - 1, slot head free
+        double rho_s[LB_R];
+        for (int it = 0; it < iters; ++it) {
+            // two-loop recursion: d = -H g
+            copy(lb_d, lb_g, n);
+            double al[LB_M];
+            for (int k = 0; k < ns; ++k) {
+                const int sl = (head - 1 - k + LB_R) % LB_R;
+                al[k] = rho_s[sl] * lb_dot(lb_s[sl], lb_d);
+                axpby(n, (T)1, lb_d, (T)(-al[k]), lb_y[sl], lb_d);
+            }
+            double gamma;
+            if (ns > 0) {
+                const int sl = (head - 1 + LB_R) % LB_R;
+                gamma = lb_dot(lb_s[sl], lb_y[sl]) / lb_dot(lb_y[sl], lb_y[sl]);
+            } else {
+                gamma = 1.0 / std::max(std::sqrt(lb_dot(lb_g, lb_g)), 1e-300);
+            }
+            axpby(n, (T)gamma, lb_d, (T)0, nullptr, lb_d);
+            for (int k = ns - 1; k >= 0; --k) {
+                const int sl = (head - 1 - k + LB_R) % LB_R;
+                const double b = rho_s[sl] * lb_dot(lb_y[sl], lb_d);
+                axpby(n, (T)1, lb_d, (T)(al[k] - b), lb_s[sl], lb_d);
+            }
+            axpby(n, (T)-1, lb_d, (T)0, nullptr, lb_d);
+            const double slope = lb_dot(lb_g, lb_d);
+            if (!(slope < 0)) break;
+            if (eps_stop > 0) copy(lb_rho_prev, lb_rho, (N + 1) * L[0].ncell);
+            // Armijo backtracking
+            double alpha = 1.0, ft = 0;
+            bool ok = false;
+            for (int h = 0; h <= 20; ++h) {
+                axpby(n, (T)1, lb_x, (T)alpha, lb_d, lb_xt);
+                ft = lb_forward(rho0, lb_xt, nk, ks, keys);
+                if (ft <= f + 1e-4 * alpha * slope) {
+                    ok = true;
+                    break;
+                }
+                alpha *= 0.5;
+            }
+            if (!ok) break;
+            bool stop = false;
+            if (eps_stop > 0) {                      // lb_rho holds the accepted trajectory
+                reduce(RED_MAXABS_DIFF, (N + 1) * L[0].ncell, lb_rho, lb_rho_prev, 0, false);
+                readback(1);
+                stop = host_out[0] <= eps_stop;
+            }
+            if (stop) {
+                std::swap(lb_x, lb_xt);
+                f = ft;
+                ++done;
+                if (hist) hist[done] = f;
+                break;
+            }
+            lb_gradient(lb_xt, nk, ks, keys, lb_gt);
+            // new pair s = xt - x, y = gt - g
+            T* sn = lb_s[head];
+            T* yn = lb_y[head];
+            axpby(n, (T)1, lb_xt, (T)-1, lb_x, sn);
+            axpby(n, (T)1, lb_gt, (T)-1, lb_g, yn);
+            const double ys = lb_dot(yn, sn);
+            const double nss = lb_dot(sn, sn), nyy = lb_dot(yn, yn);
+            if (ys > 1e-12 * std::sqrt(nss) * std::sqrt(nyy)) {
+                rho_s[head] = 1.0 / ys;
+                head = (head + 1) % LB_R;
+                ns = std::min(ns + 1, LB_M);
+            }
+            std::swap(lb_x, lb_xt);
+            std::swap(lb_g, lb_gt);
+            f = ft;
+            ++done;
+            if (hist) hist[done] = f;
+        }
+        copy(u, lb_x, n);
+        HCK(hipStreamSynchronize(st));
+        return std::isfinite(f) ? done : -2;
+    }
 
     // ------------------------------------------------------------ ADMM
     stfas_status solve(const void* rho0v, int nk, const int* ks, const void* keysv, void* u_out,

@@ -243,6 +243,22 @@ stfas_status stfas_solve(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
     });
 }
 
+stfas_status stfas_lbfgs(stfas_ctx* ctx, const void* rho0, int32_t num_key, const int32_t* key_steps,
+                         const void* key_rho, void* u_inout, int32_t iters, double eps_stop, int32_t* iters_done,
+                         double* J_hist) {
+    if (!ctx || !rho0 || !u_inout || iters < 0 || !(eps_stop >= 0)) return STFAS_E_INVALID;
+    if (!valid_keys(ctx, num_key, key_steps, key_rho)) return STFAS_E_INVALID;
+    if (!ctx->s->owns_mem) return STFAS_E_INVALID;
+    return guard([&]() -> stfas_status {
+        const int done = ctx->s->lbfgs(rho0, num_key, key_steps, key_rho, u_inout, iters, eps_stop, J_hist);
+        HCK(hipPeekAtLastError());
+        HCK(hipStreamSynchronize(ctx->s->st));
+        if (done == -1) return STFAS_E_NOMEM;
+        if (iters_done) *iters_done = done < 0 ? 0 : done;
+        return done == -2 ? STFAS_E_NONFINITE : STFAS_OK;
+    });
+}
+
 size_t stfas_step_work_bytes(const stfas_problem* prob) {
     Params p;
     if (!resolve(prob, p)) return 0;

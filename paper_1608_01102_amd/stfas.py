@@ -164,6 +164,22 @@ def stfas_solve(ctx, rho0, key_steps, key_rho, u_out):
     return {k: getattr(st, k) for k, _ in StfasStats._fields_}
 
 
+def stfas_lbfgs(ctx, rho0, key_steps, key_rho, u_inout, iters, eps_stop=0.0):
+    """L-BFGS baseline on the reduced objective; u_inout [N][faces] holds the
+    start and receives the result; eps_stop > 0 adds the visual-difference
+    stop.  Returns (J history, iterations done)."""
+    lib = _lib.load()
+    nk = len(key_steps)
+    ks = (ctypes.c_int32 * max(nk, 1))(*[int(k) for k in key_steps])
+    hist = (ctypes.c_double * (int(iters) + 1))()
+    done = ctypes.c_int32(0)
+    check(lib.stfas_lbfgs(ctx.handle, _ptr(rho0, ctx.dtype, ctx.cells, "rho0"), nk, ks,
+                          _ptr(key_rho, ctx.dtype, nk * ctx.cells, "key_rho", optional=nk == 0),
+                          _ptr(u_inout, ctx.dtype, ctx.N * ctx.faces, "u_inout"), int(iters), float(eps_stop), ctypes.byref(done),
+                          hist), "stfas_lbfgs")
+    return list(hist[:done.value + 1]), done.value
+
+
 def stfas_step_forward(prob, rho, v, u, rho_out, v_out, p_out=None, work=None, stream=None):
     dt = dtype_of(prob)
     c, f = counts(prob)

@@ -66,3 +66,29 @@ def test_solve_decreases_objective():
     assert done == 6
     assert all(hist[i + 1] <= hist[i] for i in range(len(hist) - 1))
     assert hist[-1] < hist[0]
+
+
+def test_visual_difference_stop_by_brute_force():
+    """The stop after an accepted iterate: brute force over the iterates of
+    unstopped runs (the method is deterministic, so k iterations give the
+    k-th iterate) finds the first k whose trajectory change is at most eps;
+    the stopped run must end exactly there, on that iterate."""
+    w = _tiny(2)
+    g = Grid(w["n"])
+    N, dt, r = w["num_steps"], w["dt"], w["r"]
+    levels = metric.default_levels(w["n"])
+    K = 6
+    xs = [lbfgs.solve(g, w["rho0"], w["keys"], N, r, dt, levels, k)[0] for k in range(K + 1)]
+    traj = [resimulate(g, w["rho0"], x, dt)[0] for x in xs]
+    diffs = [float(np.max(np.abs(traj[k] - traj[k - 1]))) for k in range(1, K + 1)]
+    # a threshold between the smallest and largest change so that the stop
+    # fires before K iterations
+    eps = 0.5 * (min(diffs) + max(diffs))
+    first = next(k + 1 for k, d in enumerate(diffs) if d <= eps)
+    assert first < K
+    x, hist, done = lbfgs.solve(g, w["rho0"], w["keys"], N, r, dt, levels, K, eps_stop=eps)
+    assert done == first and len(hist) == first + 1
+    assert np.array_equal(x, xs[first])
+    # eps = 0 never stops early, a huge eps stops after the first iterate
+    assert lbfgs.solve(g, w["rho0"], w["keys"], N, r, dt, levels, 3, eps_stop=0.0)[2] == 3
+    assert lbfgs.solve(g, w["rho0"], w["keys"], N, r, dt, levels, 3, eps_stop=1e30)[2] == 1
