@@ -48,6 +48,7 @@ class Problem:
     metric_levels: int = -1
     fixed_counts: bool = False
     scgs_omega: float = 0.7
+    density: str = "sl"               # density operator: "sl" or "upwind" (eq:Adv)
 
     def resolved(self, rho0):
         p = Problem(**self.__dict__)
@@ -78,13 +79,13 @@ class Result:
     history: dict = field(default_factory=dict)
 
 
-def resimulate(g: Grid, rho0, u, dt):
+def resimulate(g: Grid, rho0, u, dt, kind="sl"):
     N = u.shape[0]
     rho = np.zeros((N + 1, g.ncell))
     v = np.zeros((N + 1, g.nface))
     rho[0] = rho0
     for i in range(N):
-        rho[i + 1], v[i + 1], _ = step_forward(g, rho[i], v[i], u[i], dt)
+        rho[i + 1], v[i + 1], _ = step_forward(g, rho[i], v[i], u[i], dt, kind=kind)
     return rho, v
 
 
@@ -120,7 +121,7 @@ def solve(prob: Problem, rho0, keys):
     while it < p.max_admm:
         it += 1
         vt = v_all + lam / p.K
-        vstar, rho, phis = ao.solve(g, rho0, keys, vt, p.K, p.dt, p.metric_levels, p.ao_iters)
+        vstar, rho, phis = ao.solve(g, rho0, keys, vt, p.K, p.dt, p.metric_levels, p.ao_iters, kind=p.density)
         hist["ao_phi"].append(phis)
         w = vstar - lam / p.K
         nv, rh = stfas.nso(H, x, w, p.eps_stfas, p.max_vcycles, p.fixed_counts)
@@ -137,7 +138,7 @@ def solve(prob: Problem, rho0, keys):
         rho_last = rho.copy()
         lam = lam + p.K * p.beta * (v_all - vstar)
     u = x[2].copy()
-    rho_sim, _ = resimulate(g, rho0, u, p.dt)
+    rho_sim, _ = resimulate(g, rho0, u, p.dt, p.density)
     J, Jl2, reg = objectives(g, rho_sim, keys, u, p.r, p.metric_levels)
     return Result(u=u, v=x[0].copy(), vstar=vstar, rho_ao=rho, rho_sim=rho_sim, objective=J,
                   objective_l2=Jl2, reg_term=reg, admm_iters=it, vcycles=total_vc,

@@ -29,7 +29,7 @@ from .admm import objectives, resimulate
 from .step import step_backward
 
 
-def gradient(g: Grid, rho, v, u, keys, r, dt, levels):
+def gradient(g: Grid, rho, v, u, keys, r, dt, levels, kind="sl"):
     """dJ/du by the adjoint of the step chain; rho, v from resimulate."""
     N = u.shape[0]
     gu = np.zeros_like(u)
@@ -39,7 +39,7 @@ def gradient(g: Grid, rho, v, u, keys, r, dt, levels):
         if i in keys:
             e = rho[i] - keys[i]
             g_rho = g_rho + metric.apply_metric(g, e, levels)
-        g_rho, g_v, gu[i - 1] = step_backward(g, rho[i - 1], v[i - 1], g_rho, g_v, dt)
+        g_rho, g_v, gu[i - 1] = step_backward(g, rho[i - 1], v[i - 1], g_rho, g_v, dt, kind=kind)
     return gu + r * u
 
 
@@ -102,7 +102,7 @@ def minimize(fg, x0, iters, m=8, c1=1e-4, max_halvings=20, stop=None):
     return x, hist, done
 
 
-def solve(g: Grid, rho0, keys, N, r, dt, levels, iters, u0=None, m=8, eps_stop=0.0):
+def solve(g: Grid, rho0, keys, N, r, dt, levels, iters, u0=None, m=8, eps_stop=0.0, kind="sl"):
     """L-BFGS on J(u) over N steps from u0 (zero by default), at most iters
     iterations; eps_stop > 0 adds the visual-difference stop.  Returns u,
     the J history and the iterations done."""
@@ -111,13 +111,13 @@ def solve(g: Grid, rho0, keys, N, r, dt, levels, iters, u0=None, m=8, eps_stop=0
 
     def fg(x):
         u = x.reshape(shape)
-        rho, v = resimulate(g, rho0, u, dt)
+        rho, v = resimulate(g, rho0, u, dt, kind)
         f = objectives(g, rho, keys, u, r, levels)[0]
-        return f, gradient(g, rho, v, u, keys, r, dt, levels).ravel()
+        return f, gradient(g, rho, v, u, keys, r, dt, levels, kind).ravel()
 
     def visual_stop(xa, xb):
-        ra, _ = resimulate(g, rho0, xa.reshape(shape), dt)
-        rb, _ = resimulate(g, rho0, xb.reshape(shape), dt)
+        ra, _ = resimulate(g, rho0, xa.reshape(shape), dt, kind)
+        rb, _ = resimulate(g, rho0, xb.reshape(shape), dt, kind)
         return float(np.max(np.abs(rb - ra))) <= eps_stop
 
     x, hist, done = minimize(fg, u0.ravel(), iters, m=m, stop=visual_stop if eps_stop > 0 else None)

@@ -1,5 +1,6 @@
 """One simulation step (Sec. 3.1, eq:NSA-eq:Conv with the semi-Lagrangian
-operators) and its exact adjoint.
+velocity operator; the density operator is semi-Lagrangian or the upwind
+exponential of eq:Adv, `kind`) and its exact adjoint.
 
   rho' = A(rho, v)            (density is carried by the old velocity, eq:Conv)
   w    = S(v) + dt u          (advect, then add the control force)
@@ -9,24 +10,24 @@ operators) and its exact adjoint.
 import numpy as np
 
 from .grid import Grid
-from . import advect
+from . import advect, density
 from .poisson import project
 
 
-def step_forward(g: Grid, rho, v, u, dt, rtol=1e-14):
-    rho_n = advect.advect_scalar(g, rho, v, dt)
+def step_forward(g: Grid, rho, v, u, dt, rtol=1e-14, kind="sl"):
+    rho_n = density.fwd(g, rho, v, dt, kind)
     w = advect.self_advect(g, v, dt) + dt * u * g.interior_mask()
     v_n, phi = project(g, w, rtol=rtol)
     return rho_n, v_n, phi / dt
 
 
-def step_backward(g: Grid, rho, v, g_rho_n, g_v_n, dt, rtol=1e-14):
+def step_backward(g: Grid, rho, v, g_rho_n, g_v_n, dt, rtol=1e-14, kind="sl"):
     """Gradients (g_rho, g_v, g_u) of <g_rho_n, rho'> + <g_v_n, v'>.
     Q is symmetric, so the cotangent of w is Q g_v'."""
     mask = g.interior_mask()
     g_w, _ = project(g, g_v_n * mask, rtol=rtol)
     g_w = g_w * mask
     g_u = dt * g_w
-    g_v = advect.self_advect_T(g, v, g_w, dt) + advect.advect_scalar_dv_T(g, g_rho_n, rho, v, dt)
-    g_rho = advect.advect_scalar_T(g, g_rho_n, v, dt)
+    g_v = advect.self_advect_T(g, v, g_w, dt) + density.adj_v(g, g_rho_n, rho, v, dt, kind)
+    g_rho = density.adj_rho(g, g_rho_n, rho, v, dt, kind)
     return g_rho, g_v * mask, g_u
