@@ -60,6 +60,14 @@ typedef enum {
 
 typedef enum { STFAS_FP64 = 0, STFAS_MIXED = 1 } stfas_precision;
 
+/* Density operator A(rho, v) of Sec. 3.1 eq:Conv.  Semi-Lagrangian: one
+ * backtrace per cell and clamped multilinear interpolation.  Upwind
+ * exponential (eq:Adv): sum_{j<=k} (dt^j/j!) A(v)^j rho with a flux-form
+ * second-order upwind stencil A(v) and k the first j whose term has max norm
+ * below 1e-5 (at most 48); Sec. 4.1 allows either, as long as the partials
+ * in rho and v exist. */
+typedef enum { STFAS_DENSITY_SL = 0, STFAS_DENSITY_UPWIND = 1 } stfas_density;
+
 /* Problem description (Sec. 3.2 eq:opt and the parameter table of Sec. 5).
  * A field <= 0 selects the documented default. */
 typedef struct {
@@ -80,6 +88,7 @@ typedef struct {
     int32_t fixed_counts;   /* 1: ignore eps_*, run exactly max_admm and max_vcycles (parity mode) */
     int32_t precision;      /* stfas_precision */
     double scgs_omega;      /* relaxation weight of the SCGS smoother (Sec. 4.3), in (0, 2]; <= 0 selects 0.7 */
+    int32_t density_op;     /* stfas_density; 0 = semi-Lagrangian */
 } stfas_problem;
 
 typedef struct {

@@ -41,6 +41,19 @@ stfas_status stfas_op_advect_T(stfas_ctx* ctx, int32_t batch, const void* mu, co
 stfas_status stfas_op_advect_dv_T(stfas_ctx* ctx, int32_t batch, const void* mu, const void* rho, const void* v,
                                   const void* vt, double scale, void* gv);
 
+/* Upwind exponential density advection (Sec. 3.1 eq:Adv; the operator of
+ * STFAS_DENSITY_UPWIND), one slice on the level 0 grid, for a context whose
+ * problem selects it (otherwise STFAS_E_INVALID):
+ *   out = sum_{j<=k} (dt^j/j!) A(v)^j rho;  *k_out (host, may be NULL) = k.
+ * Synchronises (k is read back). */
+stfas_status stfas_op_upwind(stfas_ctx* ctx, const void* rho, const void* v, void* out, int32_t* k_out);
+
+/* Its partials at the same k (the series is linear in rho for fixed k):
+ *   g_rho = (dA(rho, v)/drho)^T mu,  g_v = (dA(rho, v)/dv)^T mu (0 on walls).
+ * Asynchronous. */
+stfas_status stfas_op_upwind_adj(stfas_ctx* ctx, const void* mu, const void* rho, const void* v, void* g_rho,
+                                 void* g_v);
+
 /* Velocity self-advection on level l: out[b] = S(v[b]) + dt u[b] (u may be NULL). */
 stfas_status stfas_op_self_advect(stfas_ctx* ctx, int32_t level, int32_t batch, const void* v, const void* u,
                                   void* out);

@@ -25,6 +25,7 @@ class StfasProblem(ctypes.Structure):
         ("poisson_rtol", c_double),
         ("fixed_counts", c_int32), ("precision", c_int32),
         ("scgs_omega", c_double),
+        ("density_op", c_int32),
     ]
 
 
@@ -65,6 +66,8 @@ _SIGS = {
     "stfas_op_advect_T": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "stfas_op_advect_dv_T": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                                        c_void_p]),
+    "stfas_op_upwind": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int32)]),
+    "stfas_op_upwind_adj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "stfas_op_self_advect": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "stfas_op_self_advect_T": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_double, c_void_p]),
     "stfas_op_project": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int32)]),

@@ -20,6 +20,7 @@
 #include "k_kkt.hpp"
 #include "k_misc.hpp"
 #include "k_poisson.hpp"
+#include "k_upwind.hpp"
 
 namespace stfas {
 
@@ -57,7 +58,7 @@ struct Arena {
 struct Params {
     int dim, n[3], N;
     double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol, omega;
-    int ao_iters, max_admm, max_vcycles, metric_levels, fixed_counts, precision;
+    int ao_iters, max_admm, max_vcycles, metric_levels, fixed_counts, precision, density;
 };
 
 inline int default_metric_levels(const int* n, int dim) {
@@ -96,6 +97,8 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     o.fixed_counts = p->fixed_counts ? 1 : 0;
     o.omega = p->scgs_omega > 0 ? p->scgs_omega : 0.7;
     if (!(o.omega <= 2.0)) return false;
+    if (p->density_op != STFAS_DENSITY_SL && p->density_op != STFAS_DENSITY_UPWIND) return false;
+    o.density = p->density_op;
     const double total = (double)o.n[0] * o.n[1] * o.n[2];
     if (total > 2.0e9 / (o.dim + 1)) return false;
     return true;
@@ -494,6 +497,9 @@ public:
     virtual int op_nso(stfas_state, const void*, double*) = 0;
     virtual void op_ao(const void*, int, const int*, const void*, const void*, void*, void*, double*) = 0;
     virtual int lbfgs(const void*, int, const int*, const void*, void*, int, double, double*) = 0;
+    virtual bool has_upwind() const = 0;
+    virtual int op_upwind(const void*, const void*, void*) = 0;
+    virtual void op_upwind_adj(const void*, const void*, const void*, void*, void*) = 0;
     Tracer tr;
     void trace_enable(int kind, int cap) {
         tr.reset();
@@ -641,6 +647,9 @@ public:
     T *lam, *rho_last, *wt;
     // re-simulation
     T *rs_rho[2], *rs_v[2], *rs_w;
+    // upwind exponential density operator (only when selected)
+    UpwindExp<T, D> up;
+    bool upwind() const { return P.density == STFAS_DENSITY_UPWIND; }
     // reductions
     double *red_part, *red_out;
     double* host_out = nullptr;   // pinned mirror of red_out
@@ -729,6 +738,7 @@ public:
         rs_w = A.take<T>(F0);
         red_part = A.take<double>(RED_BLOCKS);
         red_out = A.take<double>(64);
+        if (upwind()) up.layout(A, C0);
     }
 
     size_t plan() override {
@@ -821,6 +831,24 @@ public:
     void self_advect_T(int l, const T* v, const T* y, T scale, T* out, int batch) {
         if (batch <= 0) return;
         launch_self_advect_T<T, D>(L[l], cfl(l), v, y, scale, out, batch, st);
+    }
+
+    // Density operator of eq:Conv, semi-Lagrangian or upwind exponential.
+    void dens_fwd(const T* r, const T* v, T* out) {
+        if (upwind())
+            up.forward(L[0], P.dt, r, v, out, st);
+        else
+            advect(r, v, out, 1);
+    }
+    // grho += (dA/drho)^T m (grho may be null); gv = base + scale (dA/dv)^T m
+    // on interior faces, 0 on walls (base may be null)
+    void dens_adj(const T* m, const T* r, const T* v, T* grho, T* gv, const T* base, T scale) {
+        if (upwind()) {
+            up.adjoint(L[0], P.dt, m, r, v, grho, gv, base, scale, st);
+            return;
+        }
+        if (grho) advect_T(m, v, grho, 1);
+        advect_dv_T(m, r, v, base, scale, gv, 1);
     }
 
     // ------------------------------------------------------------ projection
@@ -1076,7 +1104,7 @@ public:
     void forward_sweep(const T* rho0, const T* vs, T* r) {
         const long C = L[0].ncell, F = L[0].nface;
         copy(r, rho0, C);
-        for (int i = 0; i < N; ++i) advect(r + i * C, vs + i * F, r + (i + 1) * C, 1);
+        for (int i = 0; i < N; ++i) dens_fwd(r + i * C, vs + i * F, r + (i + 1) * C);
     }
 
     // Phi = 1/2 sum_key <e, C e> + K/2 |vt - vs|^2 (reduced in double).
@@ -1093,8 +1121,12 @@ public:
         return 0.5 * host_out[0] + 0.5 * P.K * host_out[1];
     }
 
+    // mu_i for i = 0..N-1; with the upwind operator also the candidate
+    // directions cand_i = vt_i + (dA/dv)^T mu_i / K (the semi-Lagrangian
+    // form computes them afterwards in one batched launch)
     void ao_backward(const T* r, const T* vs, int nk, const int* ks, const T* keys) {
         const long C = L[0].ncell, F = L[0].nface;
+        const T ik = (T)(1.0 / P.K);
         for (int i = N; i >= 1; --i) {
             T* out = mu + (i - 1) * C;
             int kq = -1;
@@ -1107,8 +1139,14 @@ public:
             } else {
                 fill(out, C, (T)0);
             }
-            if (i < N) advect_T(mu + i * C, vs + i * F, out, 1);
+            if (i < N) {
+                if (upwind())
+                    dens_adj(mu + i * C, r + i * C, vs + i * F, out, cand + i * F, vt + i * F, ik);
+                else
+                    advect_T(mu + i * C, vs + i * F, out, 1);
+            }
         }
+        if (upwind()) dens_adj(mu, r, vs, nullptr, cand, vt, ik);
     }
 
     // Alg:Passive with blending; vt must hold v + lambda/K.  Result in vstar, rho.
@@ -1120,7 +1158,7 @@ public:
         if (hist) hist[0] = phi;
         for (int it = 0; it < P.ao_iters; ++it) {
             ao_backward(rho, vstar, nk, ks, keys);
-            advect_dv_T(mu, rho, vstar, vt, (T)(1.0 / P.K), cand, N);
+            if (!upwind()) advect_dv_T(mu, rho, vstar, vt, (T)(1.0 / P.K), cand, N);
             project(cand, cand, nullptr, N);
             double alpha = 1.0;
             for (int hv = 0; hv <= 10; ++hv) {
@@ -1203,7 +1241,7 @@ public:
         copy(lb_rho, rho0, C);
         fill(lb_v, F, (T)0);
         for (int i = 0; i < N; ++i) {
-            advect(lb_rho + i * C, lb_v + i * F, lb_rho + (i + 1) * C, 1);
+            dens_fwd(lb_rho + i * C, lb_v + i * F, lb_rho + (i + 1) * C);
             self_advect(0, lb_v + i * F, u + i * F, rs_w, 1);
             project(rs_w, lb_v + (i + 1) * F, nullptr, 1);
         }
@@ -1233,10 +1271,9 @@ public:
             const T* v = lb_v + (long)(i - 1) * F;
             project(lb_gv, lb_gw, nullptr, 1);                                   // g_w = Q g_v'
             axpby(F, (T)P.dt, lb_gw, (T)0, nullptr, gout + (long)(i - 1) * F);   // g_u = dt g_w
-            advect_dv_T(lb_grho, rho, v, nullptr, (T)1, lb_gv, 1);               // (dA/dv)^T g_rho'
-            self_advect_T(0, v, lb_gw, (T)1, lb_gv, 1);                          // + J_S^T g_w
             fill(lb_grho2, C, (T)0);
-            advect_T(lb_grho, v, lb_grho2, 1);                                   // W^T g_rho'
+            dens_adj(lb_grho, rho, v, lb_grho2, lb_gv, nullptr, (T)1);           // (dA/drho)^T, (dA/dv)^T g_rho'
+            self_advect_T(0, v, lb_gw, (T)1, lb_gv, 1);                          // + J_S^T g_w
             std::swap(lb_grho, lb_grho2);
         }
         axpby(N * F, (T)1, gout, (T)P.r, u, gout);                               // + r u
@@ -1381,7 +1418,7 @@ public:
         fill(rs_v[0], F, (T)0);
         int cur = 0;
         for (int i = 0; i < N; ++i) {
-            advect(rs_rho[cur], rs_v[cur], rs_rho[cur ^ 1], 1);
+            dens_fwd(rs_rho[cur], rs_v[cur], rs_rho[cur ^ 1]);
             self_advect(0, rs_v[cur], q.u + i * F, rs_w, 1);
             project(rs_w, rs_v[cur ^ 1], nullptr, 1);
             cur ^= 1;
@@ -1426,6 +1463,20 @@ public:
     void op_advect_dv_T(int batch, const void* m, const void* r, const void* v, const void* vtt, double scale,
                         void* gv) override {
         advect_dv_T((const T*)m, (const T*)r, (const T*)v, (const T*)vtt, (T)scale, (T*)gv, batch);
+    }
+    bool has_upwind() const override { return upwind(); }
+    // out = A(rho, v) with the upwind exponential; returns k (synchronises)
+    int op_upwind(const void* r, const void* v, void* out) override {
+        up.forward(L[0], P.dt, (const T*)r, (const T*)v, (T*)out, st);
+        int k = -1;
+        HCK(hipMemcpyAsync(&k, up.ctl.k, sizeof(int), hipMemcpyDeviceToHost, st));
+        HCK(hipStreamSynchronize(st));
+        return k;
+    }
+    // grho = (dA/drho)^T mu, gv = (dA/dv)^T mu (0 on walls)
+    void op_upwind_adj(const void* m, const void* r, const void* v, void* grho, void* gv) override {
+        fill((T*)grho, L[0].ncell, (T)0);
+        up.adjoint(L[0], P.dt, (const T*)m, (const T*)r, (const T*)v, (T*)grho, (T*)gv, nullptr, (T)1, st);
     }
     void op_self_advect(int l, int batch, const void* v, const void* u, void* out) override {
         self_advect(l, (const T*)v, (const T*)u, (T*)out, batch);

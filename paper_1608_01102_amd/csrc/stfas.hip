@@ -65,8 +65,10 @@ struct Step {
     Grid g;
     Poisson<T, D> pois;
     T *w, *gw;
+    UpwindExp<T, D> up;
+    bool upwind;
     hipStream_t st;
-    Step(const Params& p, hipStream_t s) : st(s) {
+    Step(const Params& p, hipStream_t s) : upwind(p.density == STFAS_DENSITY_UPWIND), st(s) {
         const int n[3] = {p.n[0], p.n[1], p.n[2]};
         g = make_grid(p.dim, n, 1.0 / p.n[0]);
         pois.init(g, 1, s);
@@ -75,6 +77,7 @@ struct Step {
         pois.layout(A, pinv);
         w = A.take<T>(g.nface);
         gw = A.take<T>(g.nface);
+        if (upwind) up.layout(A, g.ncell);
     }
     size_t bytes() {
         Arena A;
@@ -84,7 +87,10 @@ struct Step {
 
     void forward(const Params& p, const T* rho, const T* v, const T* u, T* rho_o, T* v_o, T* p_o) {
         const T cfl = (T)(p.dt / g.h);
-        k_advect<T, D><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g, cfl, rho, v, rho_o, g.ncell, g.nface);
+        if (upwind)
+            up.forward(g, p.dt, rho, v, rho_o, st);
+        else
+            k_advect<T, D><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g, cfl, rho, v, rho_o, g.ncell, g.nface);
         k_self_advect<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, (T)p.dt, v, u, w, g.nface);
         pois.project(w, v_o, p_o, 1, p.poisson_rtol, step_cycles(p), nullptr);
         if (p_o) k_axpby<T><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g.ncell, (T)(1.0 / p.dt), p_o, (T)0, nullptr, p_o);
@@ -95,12 +101,16 @@ struct Step {
         const T cfl = (T)(p.dt / g.h);
         pois.project(gv_o, gw, nullptr, 1, p.poisson_rtol, step_cycles(p), nullptr);       // g_w = Q g_v'
         k_axpby<T><<<blocks_for(g.nface, BS), BS, 0, st>>>(g.nface, (T)p.dt, gw, (T)0, nullptr, gu);
-        // g_v = (dA/dv)^T g_rho' + J_S^T g_w
-        k_advect_dv_T<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, grho_o, rho, v, nullptr, (T)1, gv,
-                                                                   g.ncell, g.nface);
-        launch_self_advect_T<T, D>(g, cfl, v, gw, (T)1, gv, 1, st);
+        // g_v = (dA/dv)^T g_rho' + J_S^T g_w,  g_rho = (dA/drho)^T g_rho'
         k_fill<T><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g.ncell, grho, (T)0);
-        k_advect_T<T, D><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g, cfl, grho_o, v, grho, g.ncell, g.nface);
+        if (upwind) {
+            up.adjoint(g, p.dt, grho_o, rho, v, grho, gv, nullptr, (T)1, st);
+        } else {
+            k_advect_dv_T<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, grho_o, rho, v, nullptr, (T)1, gv,
+                                                                       g.ncell, g.nface);
+            k_advect_T<T, D><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g, cfl, grho_o, v, grho, g.ncell, g.nface);
+        }
+        launch_self_advect_T<T, D>(g, cfl, v, gw, (T)1, gv, 1, st);
     }
 };
 
@@ -330,6 +340,22 @@ stfas_status stfas_op_advect_dv_T(stfas_ctx* ctx, int32_t batch, const void* mu,
                                   const void* vt, double scale, void* gv) {
     if (!ok_batch(ctx, batch) || !mu || !rho || !v || !gv) return STFAS_E_INVALID;
     OP_BODY(ctx->s->op_advect_dv_T(batch, mu, rho, v, vt, scale, gv));
+}
+
+stfas_status stfas_op_upwind(stfas_ctx* ctx, const void* rho, const void* v, void* out, int32_t* k_out) {
+    if (!ctx || !rho || !v || !out || !ctx->s->has_upwind()) return STFAS_E_INVALID;
+    return guard([&]() -> stfas_status {
+        const int k = ctx->s->op_upwind(rho, v, out);
+        HCK(hipPeekAtLastError());
+        if (k_out) *k_out = k;
+        return STFAS_OK;
+    });
+}
+
+stfas_status stfas_op_upwind_adj(stfas_ctx* ctx, const void* mu, const void* rho, const void* v, void* g_rho,
+                                 void* g_v) {
+    if (!ctx || !mu || !rho || !v || !g_rho || !g_v || !ctx->s->has_upwind()) return STFAS_E_INVALID;
+    OP_BODY(ctx->s->op_upwind_adj(mu, rho, v, g_rho, g_v));
 }
 
 stfas_status stfas_op_self_advect(stfas_ctx* ctx, int32_t level, int32_t batch, const void* v, const void* u,

@@ -13,11 +13,12 @@ from . import _lib
 from ._lib import StfasProblem, StfasState, StfasStats, check
 
 PRECISIONS = {"fp64": _lib.STFAS_FP64, "mixed": _lib.STFAS_MIXED}
+DENSITY_OPS = {"sl": 0, "upwind": 1}
 
 
 def make_problem(n, num_steps, r, dt=0.0, K=0.0, beta=0.0, ao_iters=0, eps_stfas=0.0, eps_admm=0.0, max_admm=0,
                  max_vcycles=0, metric_levels=-1, poisson_rtol=0.0, fixed_counts=False, precision="fp64",
-                 scgs_omega=0.0):
+                 scgs_omega=0.0, density="sl"):
     """stfas_problem with the C defaults for every field left at 0 (-1 for metric_levels)."""
     p = StfasProblem()
     n = tuple(int(x) for x in n)
@@ -33,6 +34,7 @@ def make_problem(n, num_steps, r, dt=0.0, K=0.0, beta=0.0, ao_iters=0, eps_stfas
     p.fixed_counts = 1 if fixed_counts else 0
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.scgs_omega = float(scgs_omega)
+    p.density_op = DENSITY_OPS[density] if isinstance(density, str) else int(density)
     return p
 
 
@@ -224,6 +226,22 @@ def stfas_op_advect_dv_T(ctx, batch, mu, rho, v, vt, scale, gv):
                                            _ptr(rho, ctx.dtype, batch * c, "rho"), _ptr(v, ctx.dtype, batch * f, "v"),
                                            _ptr(vt, ctx.dtype, batch * f, "vt", optional=True), float(scale),
                                            _ptr(gv, ctx.dtype, batch * f, "gv")), "stfas_op_advect_dv_T")
+
+
+def stfas_op_upwind(ctx, rho, v, out):
+    """Upwind exponential advection of one slice; returns k."""
+    c, f = ctx.cells, ctx.faces
+    k = ctypes.c_int32(-1)
+    check(_lib.load().stfas_op_upwind(ctx.handle, _ptr(rho, ctx.dtype, c, "rho"), _ptr(v, ctx.dtype, f, "v"),
+                                      _ptr(out, ctx.dtype, c, "out"), ctypes.byref(k)), "stfas_op_upwind")
+    return k.value
+
+
+def stfas_op_upwind_adj(ctx, mu, rho, v, g_rho, g_v):
+    c, f = ctx.cells, ctx.faces
+    check(_lib.load().stfas_op_upwind_adj(ctx.handle, _ptr(mu, ctx.dtype, c, "mu"), _ptr(rho, ctx.dtype, c, "rho"),
+                                          _ptr(v, ctx.dtype, f, "v"), _ptr(g_rho, ctx.dtype, c, "g_rho"),
+                                          _ptr(g_v, ctx.dtype, f, "g_v")), "stfas_op_upwind_adj")
 
 
 def stfas_op_self_advect(ctx, level, batch, v, u, out):

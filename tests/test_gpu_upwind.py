@@ -1,0 +1,188 @@
+"""Parity of the upwind Taylor-exponential density operator (Sec. 3.1
+eq:Adv) with the FP64 oracle through the C interface: the operator, its
+truncation index k and both adjoints, then the step, the density
+subproblem, the full solve and the L-BFGS baseline with this operator."""
+import numpy as np
+import pytest
+
+import synthetic
+from gpu_common import TOL, empty, flag, rel, to_dev, to_np
+from oracle import admm, ao, lbfgs, metric, step, upwind
+from oracle.grid import Grid
+
+pytestmark = pytest.mark.gpu
+
+
+def _q(x, prec):
+    return np.asarray(x, dtype=np.float32).astype(np.float64) if prec == "mixed" else np.asarray(x)
+
+
+def _ctx(n, N, prec, dt=None):
+    from paper_1608_01102_amd import stfas as S
+    g = Grid(n)
+    prob = S.make_problem(n, N, 1e-2, dt=dt or g.h, precision=prec, density="upwind")
+    return S, S.stfas_create(prob), g
+
+
+def _fields(n, rng, cfl, prec):
+    rho = _q(synthetic.smooth_noise_density(n, rng, 1.5), prec)
+    v = _q(synthetic.curl_noise_velocity(n, rng, 1.5, cfl, 1.0), prec)
+    return rho, v
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,cfl", [((16, 12), 1.0), ((33, 17), 2.5), ((8, 6, 10), 1.5), ((4, 4), 0.8),
+                                   ((24, 20, 16), 2.0)])
+def test_upwind_operator_and_adjoints(n, cfl, prec):
+    S, ctx, g = _ctx(n, 1, prec)
+    rng = np.random.default_rng(51)
+    rho, v = _fields(n, rng, cfl, prec)
+    mu = _q(rng.standard_normal(g.ncell), prec)
+    out = empty(g.ncell, prec)
+    flag(f"upwind n={n} cfl={cfl} {prec}")
+    k = S.stfas_op_upwind(ctx, to_dev(rho, prec), to_dev(v, prec), out)
+    ref = upwind.advect_up(g, rho, v, g.h)
+    k_ref = upwind.advect_up_k(g, rho, v, g.h)
+    tol = TOL[prec] if prec == "fp64" else 1e-5
+    assert rel(to_np(out), ref) <= tol
+    if prec == "fp64":
+        assert k == k_ref
+    else:
+        assert abs(k - k_ref) <= 1
+    gr, gv = empty(g.ncell, prec), empty(g.nface, prec)
+    S.stfas_op_upwind_adj(ctx, to_dev(mu, prec), to_dev(rho, prec), to_dev(v, prec), gr, gv)
+    if prec == "fp64" or k == k_ref:
+        atol = TOL[prec] if prec == "fp64" else 1e-4
+        assert rel(to_np(gr), upwind.advect_up_T(g, mu, rho, v, g.h)) <= atol
+        assert rel(to_np(gv), upwind.advect_up_dv_T(g, mu, rho, v, g.h)) <= atol
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_upwind_degenerate_inputs(prec):
+    """Zero velocity: k = 1 and the density is unchanged, both adjoints
+    trivial; zero density: k = 0."""
+    n = (12, 10)
+    S, ctx, g = _ctx(n, 1, prec)
+    rng = np.random.default_rng(52)
+    rho = _q(rng.random(g.ncell), prec)
+    out = empty(g.ncell, prec)
+    flag(f"upwind degenerate {prec}")
+    k = S.stfas_op_upwind(ctx, to_dev(rho, prec), to_dev(np.zeros(g.nface), prec), out)
+    assert k == 1 and np.array_equal(to_np(out), rho)
+    mu = _q(rng.standard_normal(g.ncell), prec)
+    gr, gv = empty(g.ncell, prec), empty(g.nface, prec)
+    S.stfas_op_upwind_adj(ctx, to_dev(mu, prec), to_dev(rho, prec), to_dev(np.zeros(g.nface), prec), gr, gv)
+    assert np.array_equal(to_np(gr), mu)
+    v = _q(synthetic.curl_noise_velocity(n, rng, 1.5, 1.0, 1.0), prec)
+    dv = to_np(gv)
+    assert np.all(dv[g.interior_mask() == 0] == 0)
+    k = S.stfas_op_upwind(ctx, to_dev(np.zeros(g.ncell), prec), to_dev(v, prec), out)
+    assert k == 0 and not np.any(to_np(out))
+    ctx.destroy()
+
+
+def test_upwind_rejected_without_the_operator():
+    from paper_1608_01102_amd import stfas as S
+    prob = S.make_problem((8, 8), 1, 1e-2, precision="fp64")
+    ctx = S.stfas_create(prob)
+    g = Grid((8, 8))
+    with pytest.raises(RuntimeError):
+        S.stfas_op_upwind(ctx, to_dev(np.zeros(g.ncell), "fp64"), to_dev(np.zeros(g.nface), "fp64"),
+                          empty(g.ncell, "fp64"))
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [(16, 12), (8, 8, 8)])
+def test_step_forward_backward_upwind(n, prec):
+    from paper_1608_01102_amd import stfas as S
+    g = Grid(n)
+    dt = 0.9 * g.h
+    prob = S.make_problem(n, 1, 1.0, dt=dt, precision=prec, density="upwind")
+    rng = np.random.default_rng(53)
+    rho = _q(synthetic.smooth_noise_density(n, rng, 1.0), prec)
+    v = _q(synthetic.curl_noise_velocity(n, rng, 1.0, 1.5, dt / g.h), prec)
+    u = _q(synthetic.random_faces(n, rng, 2.0), prec)
+    ro, vo, po = empty(g.ncell, prec), empty(g.nface, prec), empty(g.ncell, prec)
+    flag(f"step upwind n={n} {prec}")
+    S.stfas_step_forward(prob, to_dev(rho, prec), to_dev(v, prec), to_dev(u, prec), ro, vo, po)
+    rr, vr, pr = step.step_forward(g, rho, v, u, dt, kind="upwind")
+    tol = TOL[prec] if prec == "fp64" else 2e-5
+    assert rel(to_np(ro), rr) <= tol and rel(to_np(vo), vr) <= tol and rel(to_np(po), pr) <= 10 * tol
+    grn = _q(rng.standard_normal(g.ncell), prec)
+    gvn = _q(synthetic.random_faces(n, rng), prec)
+    gr, gv, gu = empty(g.ncell, prec), empty(g.nface, prec), empty(g.nface, prec)
+    S.stfas_step_backward(prob, to_dev(rho, prec), to_dev(v, prec), to_dev(grn, prec), to_dev(gvn, prec), gr, gv, gu)
+    a, b, c = step.step_backward(g, rho, v, grn, gvn, dt, kind="upwind")
+    tol = TOL[prec] if prec == "fp64" else 1e-4
+    assert rel(to_np(gr), a) <= tol and rel(to_np(gv), b) <= tol and rel(to_np(gu), c) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_density_subproblem_upwind(prec):
+    from paper_1608_01102_amd import stfas as S
+    w = synthetic.small_problem((16, 16), 4, seed=5, r=1e-2)
+    g = Grid(w["n"])
+    N, dt, r = w["num_steps"], w["dt"], w["r"]
+    K = r / dt ** 2
+    prob = S.make_problem(w["n"], N, r, dt=dt, K=K, ao_iters=2, metric_levels=2, precision=prec, density="upwind")
+    ctx = S.stfas_create(prob)
+    rng = np.random.default_rng(54)
+    vt = _q(np.stack([synthetic.curl_noise_velocity(w["n"], rng, 2.0, 1.0) for _ in range(N)]), prec)
+    rho0 = _q(w["rho0"], prec)
+    keys = {t: _q(v, prec) for t, v in w["keys"].items()}
+    ks = sorted(keys)
+    vs = empty(N * g.nface, prec)
+    rho = empty((N + 1) * g.ncell, prec)
+    flag(f"ao upwind {prec}")
+    hist = S.stfas_op_ao(ctx, to_dev(rho0, prec), ks, to_dev(np.stack([keys[k] for k in ks]), prec),
+                         to_dev(vt, prec), vs, rho)
+    vs_ref, rho_ref, hist_ref = ao.solve(g, rho0, keys, vt, K, dt, 2, iters=2, kind="upwind")
+    tol = TOL[prec] if prec == "fp64" else 1e-3
+    assert rel(to_np(vs), vs_ref) <= tol
+    assert rel(to_np(rho), rho_ref) <= tol
+    assert np.allclose(hist, hist_ref, rtol=1e-9 if prec == "fp64" else 1e-4)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_small_upwind(prec):
+    from paper_1608_01102_amd import stfas as S
+    w = synthetic.small_problem((8, 8), 4, seed=0, r=1e-2)
+    g = Grid(w["n"])
+    N = w["num_steps"]
+    args = dict(n=w["n"], num_steps=N, r=w["r"], dt=w["dt"], max_admm=3, max_vcycles=3, fixed_counts=True)
+    prob = S.make_problem(precision=prec, density="upwind", **args)
+    ctx = S.stfas_create(prob)
+    rho0 = _q(w["rho0"], prec)
+    keys = {t: _q(v, prec) for t, v in w["keys"].items()}
+    ks = sorted(keys)
+    u = empty(N * g.nface, prec)
+    flag(f"solve upwind {prec}")
+    st = S.stfas_solve(ctx, to_dev(rho0, prec), ks, to_dev(np.stack([keys[k] for k in ks]), prec), u)
+    ref = admm.solve(admm.Problem(density="upwind", **args), rho0, keys)
+    ctx.destroy()
+    tol = TOL[prec] if prec == "fp64" else 1e-3
+    assert rel(to_np(u).reshape(N, -1), ref.u) <= tol
+    assert abs(st["objective"] - ref.objective) <= tol * ref.objective
+
+
+def test_lbfgs_upwind_fp64():
+    from paper_1608_01102_amd import stfas as S
+    w = synthetic.small_problem((8, 8), 4, seed=7, r=1e-2)
+    g = Grid(w["n"])
+    N, dt, r = w["num_steps"], w["dt"], w["r"]
+    prob = S.make_problem(w["n"], N, r, dt=dt, precision="fp64", density="upwind")
+    ctx = S.stfas_create(prob)
+    ks = sorted(w["keys"])
+    u = to_dev(np.zeros((N, g.nface)), "fp64")
+    flag("lbfgs upwind fp64")
+    hist, done = S.stfas_lbfgs(ctx, to_dev(w["rho0"], "fp64"), ks,
+                               to_dev(np.stack([w["keys"][k] for k in ks]), "fp64"), u, 5)
+    ctx.destroy()
+    u_ref, hist_ref, done_ref = lbfgs.solve(g, w["rho0"], w["keys"], N, r, dt, metric.default_levels(w["n"]), 5,
+                                            kind="upwind")
+    assert done == done_ref
+    assert np.allclose(hist, hist_ref, rtol=1e-9, atol=0)
+    assert rel(to_np(u).reshape(N, -1), u_ref) <= 1e-9
