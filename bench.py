@@ -31,6 +31,8 @@ def parse():
                     help="kernel family whose launches on the finest level are timed with HIP events")
     ap.add_argument("--lbfgs-iters", type=int, default=200,
                     help="iteration cap of the L-BFGS comparison (0 skips it)")
+    ap.add_argument("--upwind-admm", type=int, default=10,
+                    help="ADMM cap of the solve with the upwind exponential density operator (0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=16, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
@@ -114,6 +116,8 @@ def main():
     if args.lbfgs_iters > 0:
         out["lbfgs_baseline"] = lbfgs_run(S, ctx, rho0, ks, keys, args.lbfgs_iters, kw["eps_admm"], last)
     ctx.destroy()
+    if args.upwind_admm > 0:
+        out["upwind_solve"] = upwind_run(S, w, kw, rho0, ks, keys, args.upwind_admm, last)
     if args.serve_requests > 0:
         out["serving"] = serving_run(args)
     if not args.no_cpu_baseline:
@@ -154,6 +158,26 @@ def lbfgs_run(S, ctx, rho0, ks, keys, iters, eps, admm_stats):
     reach = next((i for i, j in enumerate(hist) if j <= target), None)
     return {"iters": done, "iter_cap": iters, "eps_stop": eps, "stopped_before_cap": done < iters, "seconds": sec, "objective_start": hist[0], "objective": hist[-1],
             "admm_objective": target, "admm_seconds": admm_stats["seconds"], "reaches_admm_at_iter": reach}
+
+
+def upwind_run(S, w, kw, rho0, ks, keys, max_admm, sl_stats):
+    """The same workload with the paper's upwind exponential density operator
+    (outside the step clock): seconds per ADMM iteration beside the
+    semi-Lagrangian solve's."""
+    import torch
+    n, N = w["n"], w["num_steps"]
+    kwu = dict(kw, max_admm=max_admm)
+    prob = S.make_problem(n, N, w["r"], precision="mixed", density="upwind", **kwu)
+    ctx = S.stfas_create(prob)
+    u = torch.zeros(N * ctx.faces, dtype=torch.float32, device=rho0.device)
+    S.stfas_solve(ctx, rho0, ks, keys, u)          # warm-up
+    torch.cuda.synchronize()
+    st = S.stfas_solve(ctx, rho0, ks, keys, u)
+    ctx.destroy()
+    return {"admm_cap": max_admm, "admm_iters": st["admm_iters"], "vcycles": st["vcycles"],
+            "seconds": st["seconds"], "objective": st["objective"], "visual_diff": st["visual_diff"],
+            "s_per_admm_iter": st["seconds"] / max(st["admm_iters"], 1),
+            "sl_s_per_admm_iter": sl_stats["seconds"] / max(sl_stats["admm_iters"], 1)}
 
 
 def keyframe_error(S, p64, w, u_a, u_b):
