@@ -195,6 +195,16 @@ __global__ void __launch_bounds__(256) k_up_adj(Grid g, T dtb, T inv_h, int b, c
     }
 }
 
+// The series after launches 0..nl: its k, and whether it stopped (the last
+// launched term passed the test, or the cap was reached).
+template <typename T>
+__global__ void k_up_record(UpCtl<T> ctl, int nl, typename UpBits<T>::U tolb, int* __restrict__ k_out,
+                            int* __restrict__ ok_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    *k_out = *ctl.k;
+    *ok_out = (nl >= UP_KMAX || ctl.maxb[nl] < tolb) ? 1 : 0;
+}
+
 // gv = base (or 0) on interior faces, 0 on walls.
 template <typename T>
 __global__ void k_up_gv_init(Grid g, const T* __restrict__ base, T* __restrict__ gv) {
@@ -223,30 +233,41 @@ struct UpwindExp {
     }
     const T* term(const T* rho, int j, long C) const { return j == 0 ? rho : terms + (long)(j - 1) * C; }
 
-    // terms T_1..T_k of rho (and their sum into out, unless null); k on the device
-    void series(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st) {
+    // terms T_1..T_k of rho (and their sum into out, unless null); k on the
+    // device.  Launches terms 0..nl only: when the series has not stopped by
+    // then (record() tells), the result is truncated and the caller runs it
+    // again with a larger nl.
+    void series(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st, int nl = UP_KMAX) {
         const long C = g.ncell;
         k_fill<U><<<1, 64, 0, st>>>(UP_KMAX + 1, ctl.maxb, (U)0);
         const U tolb = UpBits<T>::of((T)UP_TOL);
         const int nb = blocks_for(C, 256);
-        for (int j = 0; j <= UP_KMAX; ++j)
+        nl = nl < 0 ? 0 : (nl > UP_KMAX ? UP_KMAX : nl);
+        for (int j = 0; j <= nl; ++j)
             k_up_term<T, D><<<nb, 256, 0, st>>>(g, j ? (T)(dt / (j * g.h)) : (T)0, j,
                                                  j ? term(rho, j - 1, C) : rho, v,
                                                  j ? terms + (long)(j - 1) * C : nullptr, out, ctl, tolb);
     }
-    void forward(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st) {
-        series(g, dt, rho, v, out, st);
+    void forward(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st, int nl = UP_KMAX) {
+        series(g, dt, rho, v, out, st, nl);
+    }
+    // k and the stopped flag of the last series (launched to nl) into device ints
+    void record(int nl, int* k_out, int* ok_out, hipStream_t st) {
+        k_up_record<T><<<1, 64, 0, st>>>(ctl, nl, UpBits<T>::of((T)UP_TOL), k_out, ok_out);
     }
     // grho += (dA/drho)^T mu (grho may be null); gv = base + scale (dA/dv)^T mu
-    // on interior faces, 0 on walls (base may be null)
+    // on interior faces, 0 on walls (base may be null).  k_known >= 0: the
+    // series of (rho, v) is known to stop at that k (the forward sweep of the
+    // same trajectory measured it), so exactly the needed launches are made.
     void adjoint(const Grid& g, double dt, const T* mu, const T* rho, const T* v, T* grho, T* gv, const T* base,
-                 T scale, hipStream_t st) {
+                 T scale, hipStream_t st, int k_known = -1) {
         const long C = g.ncell;
-        series(g, dt, rho, v, nullptr, st);
+        const int nl = k_known >= 0 ? k_known : UP_KMAX;
+        series(g, dt, rho, v, nullptr, st, nl);
         k_up_gv_init<T><<<blocks_for(g.nface, 256), 256, 0, st>>>(g, base, gv);
         const int nb = blocks_for(C, 256);
         const T inv_h = (T)(1.0 / g.h);
-        for (int b = UP_KMAX - 1; b >= -1; --b)
+        for (int b = (nl < UP_KMAX ? nl : UP_KMAX) - 1; b >= -1; --b)
             k_up_adj<T, D><<<nb, 256, 0, st>>>(g, (T)(dt / (b + 1 > 0 ? b + 1 : 1)), inv_h, b, mu, z[(b + 1) & 1],
                                                 b >= 0 ? z[b & 1] : nullptr, term(rho, b + 1, C), v, grho, gv,
                                                 scale, ctl.k);

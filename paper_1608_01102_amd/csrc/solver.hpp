@@ -650,6 +650,9 @@ public:
     // upwind exponential density operator (only when selected)
     UpwindExp<T, D> up;
     bool upwind() const { return P.density == STFAS_DENSITY_UPWIND; }
+    int *up_kd = nullptr, *up_okd = nullptr;      // per step: k and "stopped" of the last sweep (device)
+    std::vector<int> up_pred;                     // launches per step predicted from the previous sweep
+    std::vector<int> k_rho, k_rho_t, lb_k;        // k per step of the trajectories in rho, rho_t, lb_rho
     // reductions
     double *red_part, *red_out;
     double* host_out = nullptr;   // pinned mirror of red_out
@@ -738,7 +741,11 @@ public:
         rs_w = A.take<T>(F0);
         red_part = A.take<double>(RED_BLOCKS);
         red_out = A.take<double>(64);
-        if (upwind()) up.layout(A, C0);
+        if (upwind()) {
+            up.layout(A, C0);
+            up_kd = A.template take<int>(N);
+            up_okd = A.template take<int>(N);
+        }
     }
 
     size_t plan() override {
@@ -841,10 +848,11 @@ public:
             advect(r, v, out, 1);
     }
     // grho += (dA/drho)^T m (grho may be null); gv = base + scale (dA/dv)^T m
-    // on interior faces, 0 on walls (base may be null)
-    void dens_adj(const T* m, const T* r, const T* v, T* grho, T* gv, const T* base, T scale) {
+    // on interior faces, 0 on walls (base may be null); k_known: the upwind
+    // series' k for (r, v) when the forward sweep measured it
+    void dens_adj(const T* m, const T* r, const T* v, T* grho, T* gv, const T* base, T scale, int k_known = -1) {
         if (upwind()) {
-            up.adjoint(L[0], P.dt, m, r, v, grho, gv, base, scale, st);
+            up.adjoint(L[0], P.dt, m, r, v, grho, gv, base, scale, st, k_known);
             return;
         }
         if (grho) advect_T(m, v, grho, 1);
@@ -1101,10 +1109,47 @@ public:
     }
 
     // ------------------------------------------------------------ density subproblem
-    void forward_sweep(const T* rho0, const T* vs, T* r) {
+    void forward_sweep(const T* rho0, const T* vs, T* r, std::vector<int>* kout = nullptr) {
         const long C = L[0].ncell, F = L[0].nface;
         copy(r, rho0, C);
+        if (upwind()) {
+            up_sweep(r, vs, kout);
+            return;
+        }
         for (int i = 0; i < N; ++i) dens_fwd(r + i * C, vs + i * F, r + (i + 1) * C);
+    }
+
+    // Density sweep r_{i+1} = A(r_i, v_i), i = 0..N-1, with the upwind
+    // exponential (r_0 already set).  Each step's series is launched only to
+    // the k of the previous sweep plus 3; one readback after the sweep shows
+    // which steps had not stopped by then, and the sweep is run again from
+    // the first of them with the full 48 launches for that step.  k per step
+    // goes to kout.
+    void up_sweep(T* r, const T* vs, std::vector<int>* kout) {
+        const long C = L[0].ncell, F = L[0].nface;
+        if ((int)up_pred.size() != N) up_pred.assign(N, UP_KMAX);
+        std::vector<int> nl(up_pred), kh(N), okh(N);
+        int from = 0;
+        while (from < N) {
+            for (int i = from; i < N; ++i) {
+                up.forward(L[0], P.dt, r + i * C, vs + i * F, r + (i + 1) * C, st, nl[i]);
+                up.record(nl[i], up_kd + i, up_okd + i, st);
+            }
+            HCK(hipMemcpyAsync(kh.data() + from, up_kd + from, (N - from) * sizeof(int), hipMemcpyDeviceToHost, st));
+            HCK(hipMemcpyAsync(okh.data() + from, up_okd + from, (N - from) * sizeof(int), hipMemcpyDeviceToHost,
+                               st));
+            HCK(hipStreamSynchronize(st));
+            int bad = N;
+            for (int i = from; i < N; ++i)
+                if (!okh[i]) {
+                    bad = i;
+                    break;
+                }
+            from = bad;
+            if (from < N) nl[from] = UP_KMAX;   // the steps after it are re-run with their predictions
+        }
+        for (int i = 0; i < N; ++i) up_pred[i] = std::min(UP_KMAX, kh[i] + 3);
+        if (kout) *kout = kh;
     }
 
     // Phi = 1/2 sum_key <e, C e> + K/2 |vt - vs|^2 (reduced in double).
@@ -1141,19 +1186,21 @@ public:
             }
             if (i < N) {
                 if (upwind())
-                    dens_adj(mu + i * C, r + i * C, vs + i * F, out, cand + i * F, vt + i * F, ik);
+                    dens_adj(mu + i * C, r + i * C, vs + i * F, out, cand + i * F, vt + i * F, ik, kr_of(i));
                 else
                     advect_T(mu + i * C, vs + i * F, out, 1);
             }
         }
-        if (upwind()) dens_adj(mu, r, vs, nullptr, cand, vt, ik);
+        if (upwind()) dens_adj(mu, r, vs, nullptr, cand, vt, ik, kr_of(0));
     }
+    // k of step i of the accepted AO trajectory (-1: unknown)
+    int kr_of(int i) const { return (int)k_rho.size() == N ? k_rho[i] : -1; }
 
     // Alg:Passive with blending; vt must hold v + lambda/K.  Result in vstar, rho.
     void ao(const T* rho0, int nk, const int* ks, const T* keys, double* hist) {
         const long C = L[0].ncell, F = L[0].nface;
         copy(vstar, vt, N * F);
-        forward_sweep(rho0, vstar, rho);
+        forward_sweep(rho0, vstar, rho, &k_rho);
         double phi = ao_objective(rho, vstar, nk, ks, keys);
         if (hist) hist[0] = phi;
         for (int it = 0; it < P.ao_iters; ++it) {
@@ -1163,11 +1210,12 @@ public:
             double alpha = 1.0;
             for (int hv = 0; hv <= 10; ++hv) {
                 blend(vstar, cand, (T)alpha, trial, N * F);
-                forward_sweep(rho0, trial, rho_t);
+                forward_sweep(rho0, trial, rho_t, &k_rho_t);
                 const double pt = ao_objective(rho_t, trial, nk, ks, keys);
                 if (pt <= phi) {
                     std::swap(vstar, trial);
                     std::swap(rho, rho_t);
+                    std::swap(k_rho, k_rho_t);
                     phi = pt;
                     break;
                 }
@@ -1238,13 +1286,12 @@ public:
     // trajectory of u from (rho0, v = 0) into lb_rho, lb_v; returns J(u)
     double lb_forward(const T* rho0, const T* u, int nk, const int* ks, const T* keys) {
         const long C = L[0].ncell, F = L[0].nface;
-        copy(lb_rho, rho0, C);
         fill(lb_v, F, (T)0);
         for (int i = 0; i < N; ++i) {
-            dens_fwd(lb_rho + i * C, lb_v + i * F, lb_rho + (i + 1) * C);
             self_advect(0, lb_v + i * F, u + i * F, rs_w, 1);
             project(rs_w, lb_v + (i + 1) * F, nullptr, 1);
         }
+        forward_sweep(rho0, lb_v, lb_rho, &lb_k);        // the densities follow the velocities
         zero_slots(2);
         for (int q = 0; q < nk; ++q) {
             axpby(C, (T)1, lb_rho + (long)ks[q] * C, (T)-1, keys + q * C, ce_e);
@@ -1272,7 +1319,8 @@ public:
             project(lb_gv, lb_gw, nullptr, 1);                                   // g_w = Q g_v'
             axpby(F, (T)P.dt, lb_gw, (T)0, nullptr, gout + (long)(i - 1) * F);   // g_u = dt g_w
             fill(lb_grho2, C, (T)0);
-            dens_adj(lb_grho, rho, v, lb_grho2, lb_gv, nullptr, (T)1);           // (dA/drho)^T, (dA/dv)^T g_rho'
+            dens_adj(lb_grho, rho, v, lb_grho2, lb_gv, nullptr, (T)1,
+                     (int)lb_k.size() == N ? lb_k[i - 1] : -1);                 // (dA/drho)^T, (dA/dv)^T g_rho'
             self_advect_T(0, v, lb_gw, (T)1, lb_gv, 1);                          // + J_S^T g_w
             std::swap(lb_grho, lb_grho2);
         }

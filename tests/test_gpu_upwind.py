@@ -186,3 +186,39 @@ def test_lbfgs_upwind_fp64():
     assert done == done_ref
     assert np.allclose(hist, hist_ref, rtol=1e-9, atol=0)
     assert rel(to_np(u).reshape(N, -1), u_ref) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_density_subproblem_upwind_mispredicted_terms(prec):
+    """A slow flow first (its sweeps leave small per-step term counts as the
+    next prediction), then a fast one on the same context: the steps whose
+    series run past the prediction are re-run, and the result still matches
+    the oracle."""
+    from paper_1608_01102_amd import stfas as S
+    w = synthetic.small_problem((16, 16), 4, seed=6, r=1e-2)
+    g = Grid(w["n"])
+    N, dt, r = w["num_steps"], w["dt"], w["r"]
+    K = r / dt ** 2
+    prob = S.make_problem(w["n"], N, r, dt=dt, K=K, ao_iters=2, metric_levels=2, precision=prec, density="upwind")
+    ctx = S.stfas_create(prob)
+    rng = np.random.default_rng(55)
+    rho0 = _q(w["rho0"], prec)
+    keys = {t: _q(v, prec) for t, v in w["keys"].items()}
+    ks = sorted(keys)
+    kd = to_dev(np.stack([keys[k] for k in ks]), prec)
+    vs = empty(N * g.nface, prec)
+    rho = empty((N + 1) * g.ncell, prec)
+    slow = _q(np.stack([synthetic.curl_noise_velocity(w["n"], rng, 2.0, 0.2) for _ in range(N)]), prec)
+    fast = _q(np.stack([synthetic.curl_noise_velocity(w["n"], rng, 2.0, 2.5) for _ in range(N)]), prec)
+    flag(f"ao upwind mispredicted {prec}")
+    S.stfas_op_ao(ctx, to_dev(rho0, prec), ks, kd, to_dev(slow, prec), vs, rho)
+    k_slow = [upwind.advect_up_k(g, rho0, slow[0], dt)]
+    k_fast = [upwind.advect_up_k(g, rho0, fast[0], dt)]
+    assert k_fast[0] > k_slow[0] + 3            # the fast flow needs more terms than predicted
+    hist = S.stfas_op_ao(ctx, to_dev(rho0, prec), ks, kd, to_dev(fast, prec), vs, rho)
+    vs_ref, rho_ref, hist_ref = ao.solve(g, rho0, keys, fast, K, dt, 2, iters=2, kind="upwind")
+    tol = TOL[prec] if prec == "fp64" else 1e-3
+    assert rel(to_np(vs), vs_ref) <= tol
+    assert rel(to_np(rho), rho_ref) <= tol
+    assert np.allclose(hist, hist_ref, rtol=1e-9 if prec == "fp64" else 1e-4)
+    ctx.destroy()
