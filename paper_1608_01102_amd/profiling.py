@@ -11,6 +11,14 @@
   python -m paper_1608_01102_amd.profiling pmc DIR COUNTER KERNEL GRID_X
       mean counter value per dispatch (KiB) of KERNEL at GRID_X and of the
       copy kernel, from a rocprofv3 --pmc CSV directory.
+  python -m paper_1608_01102_amd.profiling ops
+      the per-operator workload: the calibration copy, then every operator
+      of the path once per repetition on the 64^3 grid, batched over the 60
+      time slices of the 3D precision workload (mixed precision).
+  python -m paper_1608_01102_amd.profiling opstable RESULTS.db [FETCH_DIR WRITE_DIR]
+      achieved GB/s of each operator kernel of that workload: algorithmic
+      bytes per launch / average launch time, and, with the two counter
+      directories, the measured HBM bytes per launch.
 """
 import csv
 import glob
@@ -105,6 +113,115 @@ def pmc(directory, counter, kernel, grid_x):
     return out
 
 
+# ---------------------------------------------------------------- per-operator roofline
+OPS_N = (64, 64, 64)
+OPS_SLICES = 60
+
+
+def ops_workload(reps=5):
+    import torch
+    sys.path.insert(0, os.path.dirname(HERE))
+    import synthetic
+    from paper_1608_01102_amd import stfas as S
+    dev = torch.device("cuda:0")
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    del a, b
+    n, N = OPS_N, OPS_SLICES
+    prob = S.make_problem(n, N, 1e-3, precision="mixed")
+    ctx = S.stfas_create(prob)
+    C, F = ctx.cells, ctx.faces
+    import numpy as np
+    rng = np.random.default_rng(0)
+    v1 = torch.tensor(synthetic.curl_noise_velocity(n, rng, 4.0, 2.0, 1.0), dtype=torch.float32, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    v = v1.repeat(N)
+    rho = torch.rand(N * C, generator=g, device=dev)
+    mu = torch.randn(N * C, generator=g, device=dev)
+    y = torch.randn(N * F, generator=g, device=dev) * (v != 0)
+    out_c = torch.empty(N * C, device=dev)
+    out_f = torch.empty(N * F, device=dev)
+    st = tuple(torch.randn(N * m, generator=g, device=dev) * 1e-3 for m in (F, C, F, C))
+    res = tuple(torch.zeros(N * m, device=dev) for m in (F, C, F, C))
+    rout = tuple(torch.empty(N * m, device=dev) for m in (F, C, F, C))
+    w = v.clone()
+    lc, lf = ctx.level_counts(1)
+    coarse = tuple(torch.empty(N * m, device=dev) for m in (lf, lc, lf, lc))
+    for _ in range(reps):
+        S.stfas_op_advect(ctx, N, rho, v, out_c)
+        S.stfas_op_advect_T(ctx, N, mu, v, None, out_c)
+        S.stfas_op_advect_dv_T(ctx, N, mu, rho, v, None, 1.0, out_f)
+        S.stfas_op_self_advect(ctx, 0, N, v, y, out_f)
+        S.stfas_op_self_advect_T(ctx, 0, N, v, y, 1.0, out_f)
+        S.stfas_op_project(ctx, N, y, out_f)
+        S.stfas_op_metric(ctx, rho[:C], out_c[:C])
+        S.stfas_op_kkt_residual(ctx, 0, st, w, res, rout)
+        S.stfas_op_scgs_sweep(ctx, 0, st, w)
+        S.stfas_op_restrict(ctx, 0, st, coarse)
+        S.stfas_op_prolong(ctx, 0, coarse, 1.0, st)
+    torch.cuda.synchronize()
+    ctx.destroy()
+    print("ops workload done", flush=True)
+
+
+def _ceil256(x):
+    return -(-x // 256) * 256
+
+
+def ops_expectations():
+    """(label, kernel name part, grid x, grid y, algorithmic bytes per launch,
+    what they are) of the operator kernels of the ops workload, FP32."""
+    n0, n1, n2 = OPS_N
+    N = OPS_SLICES
+    C = n0 * n1 * n2
+    F = (n0 + 1) * n1 * n2 + n0 * (n1 + 1) * n2 + n0 * n1 * (n2 + 1)
+    half = (n0 + 1) // 2 * n1 * n2
+    return [
+        ("SL density advection", "k_advect<", _ceil256(C), N, N * C * 20, "rho, 3 face velocities, rho' per cell"),
+        ("its rho adjoint", "k_advect_T<", _ceil256(C), N, N * C * 24, "mu, 3 face velocities, out read+write"),
+        ("its v adjoint", "k_advect_dv_T<", _ceil256(F), N, N * F * 16, "mu, rho, v, out per face"),
+        ("SL self-advection", "k_self_advect<", _ceil256(F), N, N * F * 12, "v, u, out per face"),
+        ("its adjoint (tiled)", "k_self_advect_T_tiled<", None, N, N * F * 16, "v, y, out read+write per face"),
+        ("divergence", "k_divergence<", _ceil256(C), N, N * C * 16, "3 faces, b per cell"),
+        ("red-black GS, one colour, finest", "k_rbgs<", _ceil256(half), N, N * C * 6,
+         "phi of the other colour, b and phi of this one"),
+        ("projection apply", "k_project_apply<", _ceil256(F), N, N * (F * 12 + C * 4), "w, v per face; phi"),
+        ("Gaussian, one axis", "k_blur_axis<", _ceil256(C), 1, C * 8, "in, out per cell"),
+    ]
+
+
+def ops_table(db, fetch_dir=None, write_dir=None):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, grid_x, grid_y, grid_z, duration from kernels").fetchall()
+    lines = ["| Operator | Kernel | Launches | Avg µs | Alg. MB/launch | Alg. GB/s | % of 8000 |"
+             + (" HBM MB/launch | HBM GB/s |" if fetch_dir else ""),
+             "|---|---|---|---|---|---|---|" + ("---|---|" if fetch_dir else "")]
+    for label, part, gx, gy, nbytes, what in ops_expectations():
+        ds = [r[4] for r in rows if part in r[0] and (gx is None or int(r[1]) == gx) and int(r[2]) == gy]
+        if not ds:
+            lines.append(f"| {label} | `{part[:-1]}` | 0 | | | | |")
+            continue
+        avg = sum(ds) / len(ds)       # ns
+        gbs = nbytes / avg
+        line = (f"| {label} | `{part[:-1]}` | {len(ds)} | {avg / 1e3:.1f} | {nbytes / 1e6:.1f} | {gbs:.0f} | "
+                f"{100 * gbs / 8000:.0f}% |")
+        if fetch_dir:
+            gsz = None
+            m = [r for r in rows if part in r[0] and (gx is None or int(r[1]) == gx) and int(r[2]) == gy]
+            gsz = int(m[0][1]) * int(m[0][2]) * int(m[0][3])
+            fb = pmc(fetch_dir, "FETCH_SIZE", part, gsz).get("bytes_per_dispatch")
+            wb = pmc(write_dir, "WRITE_SIZE", part, gsz).get("bytes_per_dispatch")
+            if fb is not None and wb is not None:
+                line += f" {(fb + wb) / 1e6:.1f} | {(fb + wb) / avg:.0f} |"
+            else:
+                line += " | |"
+        lines.append(line)
+    return "\n".join(lines)
+
+
 def main(argv):
     if argv[0] == "stats":
         print(stats(argv[1], *(argv[2:4] if len(argv) >= 4 else [])))
@@ -113,6 +230,10 @@ def main(argv):
     elif argv[0] == "pmc":
         import json
         print(json.dumps(pmc(argv[1], argv[2], argv[3], argv[4])))
+    elif argv[0] == "ops":
+        ops_workload()
+    elif argv[0] == "opstable":
+        print(ops_table(*argv[1:4]))
     elif argv[0] == "hash":
         print(kernel_source_hash())
 
