@@ -7,7 +7,10 @@ reductions), regularisation 1e-4, ADMM stopped at 1e-4 * max(rho_0)
 visual difference or 50 iterations.  Inputs are synthetic and seeded
 (a blurred disk to a union of strokes), already resident on the device.
 
-Prints one JSON line (see the design doc for every field)."""
+Prints one JSON line: the solve rate with its roofline (the finest residual
+launch, timed with HIP events on the solver's stream, and its counter-
+measured HBM bytes), the FP64 solve beside the mixed one, the L-BFGS and
+upwind-operator comparisons, the serving run and the oracle's CPU rate."""
 import argparse
 import json
 import os
@@ -42,7 +45,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only (the solve is not sharded across GPUs); "
+        print("bench.py: measures one GPU only (the solve is not sharded across GPUs); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
