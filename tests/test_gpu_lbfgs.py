@@ -104,3 +104,23 @@ def test_lbfgs_rejects_caller_workspace():
     with pytest.raises(RuntimeError):
         S.stfas_lbfgs(ctx, to_dev(w["rho0"], "fp64"), [2], to_dev(w["keys"][2][None], "fp64"), u, 2)
     ctx.destroy()
+
+
+def test_lbfgs_invalid_arguments():
+    """Rejected before anything runs: negative iterations, a negative or NaN
+    stop threshold, keyframe steps outside 1..N."""
+    from paper_1608_01102_amd import stfas as S
+    w = synthetic.small_problem((8, 8), 2, seed=12, r=1e-2)
+    g = Grid(w["n"])
+    prob = S.make_problem(w["n"], 2, w["r"], dt=w["dt"], precision="fp64")
+    ctx = S.stfas_create(prob)
+    rho0 = to_dev(w["rho0"], "fp64")
+    key = to_dev(w["keys"][2][None], "fp64")
+    u = to_dev(np.zeros((2, g.nface)), "fp64")
+    flag("lbfgs invalid arguments")
+    for args in ([2], key, -1, 0.0), ([2], key, 2, -1.0), ([2], key, 2, float("nan")), ([3], key, 2, 0.0), \
+            ([0], key, 2, 0.0):
+        with pytest.raises(RuntimeError):
+            S.stfas_lbfgs(ctx, rho0, args[0], args[1], u, args[2], args[3])
+    assert not np.any(to_np(u))                  # nothing ran
+    ctx.destroy()
