@@ -78,16 +78,44 @@ __device__ inline void kkt_cell(const Grid& g, T sgn, const T* __restrict__ v, c
     out4[e] = (res4 ? res4[e] : (T)0) + sgn * du * ih;
 }
 
-// The whole residual of one level in one launch, for the SCGS colour passes:
+// The residual of one level in one launch, for the SCGS colour passes:
 // blocks [0, nbf N) face rows, then [.., + nbc N) cell rows, then the tiles
 // of the velocity-advection transpose (slices 0..N-2, d axes), which add
 // their J_S^T term into t1 (zero on entry) instead of F1, then blocks that
 // clear t1z (the other t1 buffer, for the next pass).  All four parts read
 // only the state, so they run side by side; the SCGS pass reads F1 + t1.
+// With `rows` set the face and cell rows are those of one colour only: the
+// faces of its cells and the cells themselves, all that its pass reads (the
+// rows elsewhere are computed again before the pass that reads them).  The
+// transpose always covers every source: any of them can land on a face of
+// the colour.
 struct KktSplit {
     int nbf, nbc, ntile, nbz;
     int direct;     // 1: the transpose part runs one thread per source (ntile = blocks per slice)
+    int rows;       // 1: face and cell rows of the colour (par, cnt) only
+    int par[3];     // coordinate parities of the colour's cells
+    int cnt[3];     // cells of the colour along each axis
+    int nfc;        // faces of the colour's cells (per slice), with rows set
 };
+
+// Face e (0 <= e < nfc) of the colour's cells: a-faces whose coordinates
+// across a have the colour's parities, a-faces first, then b, then c.
+__device__ inline int colour_face(const Grid& g, const KktSplit& ks, int e) {
+    const int m0 = (g.n[0] + 1) * ks.cnt[1] * ks.cnt[2];
+    if (e < m0) {
+        const int i = e % (g.n[0] + 1), r = e / (g.n[0] + 1);
+        return face_index(g, 0, i, 2 * (r % ks.cnt[1]) + ks.par[1], 2 * (r / ks.cnt[1]) + ks.par[2]);
+    }
+    e -= m0;
+    const int m1 = ks.cnt[0] * (g.n[1] + 1) * ks.cnt[2];
+    if (e < m1) {
+        const int ii = e % ks.cnt[0], r = e / ks.cnt[0];
+        return face_index(g, 1, 2 * ii + ks.par[0], r % (g.n[1] + 1), 2 * (r / (g.n[1] + 1)) + ks.par[2]);
+    }
+    e -= m1;
+    const int ii = e % ks.cnt[0], r = e / ks.cnt[0];
+    return face_index(g, 2, 2 * ii + ks.par[0], 2 * (r % ks.cnt[1]) + ks.par[1], r / ks.cnt[1]);
+}
 
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T cfl, T sgn, KktSplit ks,
@@ -100,14 +128,21 @@ __global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T 
     const long bf = (long)ks.nbf * N, bc = (long)ks.nbc * N;
     const long bt = (long)ks.ntile * (N - 1) * (ks.direct ? 1 : D);
     if (b < bf) {
-        const int f = (int)(b % ks.nbf) * 256 + threadIdx.x;
-        if (f < g.nface) kkt_face<T, D>(g, N, dt, kr, cfl, sgn, v, pb, u, p, w, res1, res3, out1, out3, f, (int)(b / ks.nbf));
+        const int e = (int)(b % ks.nbf) * 256 + threadIdx.x;
+        if (e >= (ks.rows ? ks.nfc : g.nface)) return;
+        const int f = ks.rows ? colour_face(g, ks, e) : e;
+        kkt_face<T, D>(g, N, dt, kr, cfl, sgn, v, pb, u, p, w, res1, res3, out1, out3, f, (int)(b / ks.nbf));
         return;
     }
     b -= bf;
     if (b < bc) {
-        const int c = (int)(b % ks.nbc) * 256 + threadIdx.x;
-        if (c < g.ncell) kkt_cell<T, D>(g, sgn, v, u, res2, res4, out2, out4, c, (int)(b / ks.nbc));
+        const int e = (int)(b % ks.nbc) * 256 + threadIdx.x;
+        if (e >= (ks.rows ? ks.cnt[0] * ks.cnt[1] * ks.cnt[2] : g.ncell)) return;
+        const int c = ks.rows ? cell_index(g, 2 * (e % ks.cnt[0]) + ks.par[0],
+                                           2 * ((e / ks.cnt[0]) % ks.cnt[1]) + ks.par[1],
+                                           2 * (e / (ks.cnt[0] * ks.cnt[1])) + ks.par[2])
+                              : e;
+        kkt_cell<T, D>(g, sgn, v, u, res2, res4, out2, out4, c, (int)(b / ks.nbc));
         return;
     }
     b -= bc;

@@ -914,13 +914,32 @@ public:
     // The residual r = res - f(x) of level l for an SCGS colour pass in one
     // launch: F1 without its J_S^T term in r1, that term in t1 (zero on
     // entry), and t1z cleared for the next pass.
-    void kkt_split(int l, T* t1, T* t1z) {
+    // colour >= 0: the face and cell rows of that colour only (see KktSplit)
+    void kkt_split(int l, T* t1, T* t1z, int colour = -1) {
         const Grid& g = L[l];
         Lev& q = lev[l];
         using TS = TileShape<D>;
         KktSplit ks{};
-        ks.nbf = blocks_for(g.nface, 256);
-        ks.nbc = blocks_for(g.ncell, 256);
+        long nfr = g.nface, ncr = g.ncell;     // face and cell rows per slice
+        if (colour >= 0) {
+            const ColourSet cs = colour_set(g, colour);
+            ks.rows = 1;
+            for (int a = 0; a < 3; ++a) {
+                ks.par[a] = cs.p[a];
+                ks.cnt[a] = cs.cnt[a];
+            }
+            ks.nfc = 0;
+            for (int a = 0; a < D; ++a) {
+                long m = g.n[a] + 1;
+                for (int b2 = 0; b2 < 3; ++b2)
+                    if (b2 != a) m *= cs.cnt[b2];
+                ks.nfc += (int)m;
+            }
+            nfr = ks.nfc;
+            ncr = cs.total;
+        }
+        ks.nbf = blocks_for(nfr, 256);
+        ks.nbc = blocks_for(ncr, 256);
         // small levels: the transpose without tiles (no LDS window, no barriers), since there a launch is
         // a chain of dependent memory steps and its few atomics are cheap
         ks.direct = (long)N * g.nface <= DIRECT_T_SLOTS ? 1 : 0;
@@ -938,10 +957,11 @@ public:
         ks.nbz = std::min(blocks_for((long)N * g.nface, 256), 2048);
         const long blocks = (long)(ks.nbf + ks.nbc) * N + (long)ks.ntile * (N - 1) * (ks.direct ? 1 : D) + ks.nbz;
         const double sz = sizeof(T);
-        const double fslots = (double)g.nface * N, cslots = (double)g.ncell * N;
-        // every sequence the launch reads or writes, once: v, u, w in and r1, r3, t1, t1z out per
-        // face slot (+ s1, s3 on coarse levels); pbar, p in and r2, r4 out per cell slot (+ s2, s4)
-        const double bytes = sz * (fslots * (7 + (q.s1 ? 2 : 0)) + cslots * (4 + (q.s2 ? 2 : 0)));
+        const double fslots = (double)g.nface * N, rslots = (double)nfr * N, cslots = (double)ncr * N;
+        // every sequence the launch reads or writes, once: v and u in (the transpose reads them at
+        // every face) and t1, t1z out per face slot; w in and r1, r3 out per face-row slot (+ s1, s3
+        // on coarse levels); pbar, p in and r2, r4 out per cell-row slot (+ s2, s4)
+        const double bytes = sz * (fslots * 4 + rslots * (3 + (q.s1 ? 2 : 0)) + cslots * (4 + (q.s2 ? 2 : 0)));
         traced(tr, st, l == 0 ? TR_KKT_SPLIT : TR_NONE, bytes, [&] {
             k_kkt_split<T, D><<<(unsigned)blocks, 256, 0, st>>>(g, N, (T)P.dt, (T)(P.K / P.r), cfl(l), (T)-1, ks,
                                                                q.v, q.pb, q.u, q.p, q.w, q.s1, q.s2, q.s3, q.s4,
@@ -987,7 +1007,7 @@ public:
             if (t1c && colour_shape<T, D>(2 * N, cs.total, G, Lc, CH)) {
                 // two launches per colour: the residual (faces, cells and the J_S^T term side by side),
                 // then one kernel that reads r1 + t1, r2..r4 once and updates u/v and p/pbar
-                kkt_split(l, t1c, t1n);
+                kkt_split(l, t1c, t1n, colour);
                 // per block pair: r1, t1, r3 read, u and v read + written at each interior face;
                 // per block: the divergence residual read, p or pbar read + written at each cell
                 traced(tr, st, l == 0 ? TR_SCGS_COLOUR : TR_NONE, sz * M2 * (inner * 3.5 + cs.total * 3), [&] {
