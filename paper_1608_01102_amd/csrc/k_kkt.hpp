@@ -87,8 +87,8 @@ __device__ inline void kkt_cell(const Grid& g, T sgn, const T* __restrict__ v, c
 // With `rows` set the face and cell rows are those of one colour only: the
 // faces of its cells and the cells themselves, all that its pass reads (the
 // rows elsewhere are computed again before the pass that reads them).  The
-// transpose always covers every source: any of them can land on a face of
-// the colour.
+// transpose then still runs every source (any of them can land on a face of
+// the colour) but, in 3D, adds into t1 only at the colour's faces.
 struct KktSplit {
     int nbf, nbc, ntile, nbz;
     int direct;     // 1: the transpose part runs one thread per source (ntile = blocks per slice)
@@ -147,6 +147,10 @@ __global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T 
     }
     b -= bc;
     if (b < bt) {
+        // with colour rows in 3D, J_S^T only where the colour pass reads t1: its faces (a quarter of
+        // them; in 2D, where half would go, the tiles are bound by instruction issue and the extra
+        // tests cost more than the skipped flush, so there every face is written)
+        const int cpar = (D == 3 && ks.rows) ? (ks.par[0] | (ks.par[1] << 1) | (ks.par[2] << 2)) : -1;
         const int slice = (int)((b / ks.ntile) % (N - 1));
         if (ks.direct) {
             // one thread per (slice, face); y = u_{j+1} (the u slots shifted by one), scale -sgn/dt
@@ -155,14 +159,14 @@ __global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T 
                 int a, i, j, k;
                 face_decode(g, f, a, i, j, k);
                 self_advect_T_source<T, D>(g, cfl, v + (long)slice * g.nface, u + (long)(slice + 1) * g.nface,
-                                           -sgn / dt, t1 + (long)slice * g.nface, a, i, j, k);
+                                           -sgn / dt, t1 + (long)slice * g.nface, a, i, j, k, cpar);
             }
             return;
         }
         // tile, slice, axis; y = u_{j+1} (the u slots shifted by one), scale -sgn/dt
         const int tile = (int)(b % ks.ntile);
         const int a = (int)(b / ((long)ks.ntile * (N - 1)));
-        self_advect_T_tile<T, D>(g, cfl, v, u + g.nface, -sgn / dt, t1, g.nface, tile, slice, a);
+        self_advect_T_tile<T, D>(g, cfl, v, u + g.nface, -sgn / dt, t1, g.nface, tile, slice, a, cpar);
         return;
     }
     b -= bt;
