@@ -36,6 +36,7 @@ def parse():
                     help="iteration cap of the L-BFGS comparison (0 skips it)")
     ap.add_argument("--upwind-admm", type=int, default=10,
                     help="ADMM cap of the solve with the upwind exponential density operator (0 skips it)")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 64^3 x 60 precision-form comparison")
     ap.add_argument("--serve-requests", type=int, default=16, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
@@ -121,6 +122,8 @@ def main():
     ctx.destroy()
     if args.upwind_admm > 0:
         out["upwind_solve"] = upwind_run(S, w, kw, rho0, ks, keys, args.upwind_admm, last)
+    if not args.no_3d:
+        out["precision_3d"] = precision_3d_run(S)
     if args.serve_requests > 0:
         out["serving"] = serving_run(args)
     if not args.no_cpu_baseline:
@@ -181,6 +184,38 @@ def upwind_run(S, w, kw, rho0, ks, keys, max_admm, sl_stats):
             "seconds": st["seconds"], "objective": st["objective"], "visual_diff": st["visual_diff"],
             "s_per_admm_iter": st["seconds"] / max(st["admm_iters"], 1),
             "sl_s_per_admm_iter": sl_stats["seconds"] / max(sl_stats["admm_iters"], 1)}
+
+
+def precision_3d_run(S):
+    """The 3D precision form (outside the step clock): the 64^3, 60-step
+    workload (sphere to ellipsoid unions at t = 30 and 60), 2 ADMM iterations
+    of 4 V-cycles each (fixed counts), mixed and FP64 on the GPU; seconds,
+    seconds per V-cycle, and the mixed form's keyframe error against the
+    FP64 run after re-simulating both controls with the FP64 step."""
+    import numpy as np
+    import torch
+    import synthetic
+    w = synthetic.c3_precision_3d(0)
+    n, N = w["n"], w["num_steps"]
+    ks = sorted(w["keys"])
+    res, us = {}, {}
+    for prec, dt in (("mixed", torch.float32), ("fp64", torch.float64)):
+        p = S.make_problem(n, N, w["r"], dt=w["dt"], precision=prec, max_admm=2, max_vcycles=4, fixed_counts=True)
+        ctx = S.stfas_create(p)
+        rho0 = torch.tensor(w["rho0"], dtype=dt, device="cuda")
+        keys = torch.tensor(np.stack([w["keys"][k] for k in ks]), dtype=dt, device="cuda")
+        u = torch.zeros(N * ctx.faces, dtype=dt, device="cuda")
+        st = S.stfas_solve(ctx, rho0, ks, keys, u)
+        ctx.destroy()
+        us[prec] = u.double().cpu().numpy()
+        res[prec] = {"seconds": st["seconds"], "vcycles": st["vcycles"],
+                     "ms_per_vcycle_incl_ao": st["seconds"] * 1e3 / max(st["vcycles"], 1),
+                     "objective": st["objective"]}
+        torch.cuda.empty_cache()
+    p64 = S.make_problem(n, N, w["r"], dt=w["dt"], precision="fp64")
+    res["kf_err_mixed_vs_fp64"] = keyframe_error(S, p64, w, us["mixed"], us["fp64"])
+    res["workload"] = "3D 64^3 MAC grid, 60 steps, r=1e-3, 2 ADMM x 4 V-cycles (fixed counts)"
+    return res
 
 
 def keyframe_error(S, p64, w, u_a, u_b):
