@@ -118,24 +118,32 @@ __global__ void k_slice_sum(int n, const T* __restrict__ x, double* __restrict__
 // Per-slice Poisson residual ratios |r|/|b| from block partials; the max over
 // slices goes to out[slot].
 __global__ void k_poisson_ratio(int nslice, int nblk, const double* __restrict__ part, double* out, int slot) {
-    __shared__ double sm[256];
+    // one wavefront per slice: its lanes stride over the slice's block
+    // partials and fold them with shuffles; then the largest ratio of all
+    // slices (one launch of 256 threads)
+    __shared__ double sm[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     double worst = 0;
-    for (int s = threadIdx.x; s < nslice; s += blockDim.x) {
+    for (int s = wave; s < nslice; s += nw) {
         double r2 = 0, b2 = 0;
-        for (int q = 0; q < nblk; ++q) {
+        for (int q = lane; q < nblk; q += 64) {
             r2 += part[((long)s * nblk + q) * 2];
             b2 += part[((long)s * nblk + q) * 2 + 1];
         }
-        const double ratio = b2 > 0 ? sqrt(r2 / b2) : 0.0;
-        worst = fmax(worst, ratio);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            r2 += __shfl_xor(r2, o);
+            b2 += __shfl_xor(b2, o);
+        }
+        worst = fmax(worst, b2 > 0 ? sqrt(r2 / b2) : 0.0);
     }
-    sm[threadIdx.x] = worst;
+    if (lane == 0) sm[wave] = worst;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0;
+        for (int w = 0; w < nw; ++w) m = fmax(m, sm[w]);
+        out[slot] = m;
     }
-    if (threadIdx.x == 0) out[slot] = sm[0];
 }
 
 }  // namespace stfas
