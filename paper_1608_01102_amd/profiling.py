@@ -190,6 +190,37 @@ def ops_expectations():
          "phi of the other colour, b and phi of this one"),
         ("projection apply", "k_project_apply<", _ceil256(F), N, N * (F * 12 + C * 4), "w, v per face; phi"),
         ("Gaussian, one axis", "k_blur_axis<", _ceil256(C), 1, C * 8, "in, out per cell"),
+    ] + _stfas_expectations(n0, n1, n2, N, C, F)
+
+
+def _stfas_expectations(n0, n1, n2, N, C, F):
+    """The velocity-subproblem kernels of the ops workload (level 0 and the
+    transfers to level 1): the KKT residual, one colour pass's residual, the
+    SCGS colour pass and the four FAS transfers."""
+    nb = lambda x: -(-x // 256)
+    # colour 0 of the SCGS sweep (every colour of an even grid has the same counts)
+    cnt = [(m + 1) // 2 for m in (n0, n1, n2)]
+    cc = cnt[0] * cnt[1] * cnt[2]
+    fc = sum((m + 1) * (cnt[0] * cnt[1] * cnt[2] // cnt[a]) for a, m in enumerate((n0, n1, n2)))
+    inner = 3 * (2 * cnt[0] - 1) * cnt[1] * cnt[2]          # interior faces of colour 0's cells
+    Cc = (n0 // 2) * (n1 // 2) * (n2 // 2)
+    Fc = 3 * (n0 // 2) * (n0 // 2) * (n0 // 2 + 1)
+    full = (nb(F) + nb(C)) * N * 256
+    tiles = (-(-(n0 + 1) // 8)) * (-(-n1 // 8)) * (-(-n2 // 4))
+    colour = ((nb(fc) + nb(cc)) * N + tiles * (N - 1) * 3 + min(nb(N * F), 2048)) * 256
+    return [
+        ("KKT residual rows (whole level)", "k_kkt_split<", full, 1, N * (F * 5 + C * 4) * 4,
+         "v, u, w in, r1, r3 out per face; p-bar, p in, r2, r4 out per cell"),
+        ("colour-pass residual with the transpose", "k_kkt_split<", colour, 1, N * (F * 16 + fc * 12 + cc * 16),
+         "v, u in, t1, t1z out per face; w, r1, r3 at the colour's faces; 4 per colour cell"),
+        ("SCGS colour pass", "k_scgs_colour_rows<", None, 1, 4 * 2 * N * (inner * 3.5 + cc * 3),
+         "r1, t1, r3 read and u/v read+written per face block pair; 3 per cell block"),
+        ("FAS restriction, faces", "k_restrict_faces<", _ceil256(Fc), N, N * (F + Fc) * 4, "fine in, coarse out"),
+        ("FAS restriction, cells", "k_restrict_cells<", _ceil256(Cc), N, N * (C + Cc) * 4, "fine in, coarse out"),
+        ("FAS prolongation, faces", "k_prolong_faces<", _ceil256(F), N, N * (2 * F + Fc) * 4,
+         "fine read+written, coarse in"),
+        ("FAS prolongation, cells", "k_prolong_cells<", _ceil256(C), N, N * (2 * C + Cc) * 4,
+         "fine read+written, coarse in"),
     ]
 
 
