@@ -246,6 +246,99 @@ struct TileShape<3> {
     static constexpr int X = 8, Y = 8, Z = 4, H = 2;
 };
 
+// out += W(v)^T mu with an LDS window per tile of cells (the shape and halo
+// of TileShape): each cell scatters its eight (2D: four) weights into the
+// window in 64-bit fixed point (scale from the tile's largest weight, so the
+// window sums are exact and independent of order; a node takes at most one
+// weight per cell of the tile), a weight beyond the halo goes straight to
+// global memory, and the window is flushed with one global atomic per
+// nonzero node.  blockIdx.x = tile, blockIdx.y = slice.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_advect_T_tiled(Grid g, T cfl, const T* __restrict__ mu,
+                                                        const T* __restrict__ v, T* out, long rs, long vs) {
+    using TS = TileShape<D>;
+    constexpr int H = TS::H;
+    constexpr int HZ = D == 3 ? H : 0;
+    constexpr int WX = TS::X + 2 * H, WY = TS::Y + 2 * H, WZ = TS::Z + 2 * HZ;
+    constexpr int WN = WX * WY * WZ;
+    __shared__ unsigned long long win[WN];
+    __shared__ T wmax[4];
+    mu += blockIdx.y * rs;
+    v += blockIdx.y * vs;
+    out += blockIdx.y * rs;
+    const int ntx = (g.n[0] + TS::X - 1) / TS::X, nty = (g.n[1] + TS::Y - 1) / TS::Y;
+    const int tile = blockIdx.x;
+    const int tx0 = (tile % ntx) * TS::X, ty0 = ((tile / ntx) % nty) * TS::Y, tz0 = (tile / (ntx * nty)) * TS::Z;
+    const int ox = tx0 - H, oy = ty0 - H, oz = tz0 - HZ;
+    for (int e = threadIdx.x; e < WN; e += blockDim.x) win[e] = 0ull;
+    __syncthreads();
+    const int i = tx0 + (int)threadIdx.x % TS::X, j = ty0 + ((int)threadIdx.x / TS::X) % TS::Y;
+    const int k = tz0 + (int)threadIdx.x / (TS::X * TS::Y);
+    T wq[1 << D];
+    int c0[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) wq[q] = 0;
+    if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+        const T m = mu[cell_index(g, i, j, k)];
+        if (m != (T)0) {
+            const int idx[3] = {i, j, k};
+            T y[3];
+            for (int a = 0; a < D; ++a) y[a] = -cfl * vbar(g, v, a, i, j, k);
+            Interp<T, D> it;
+            it.setup_disp(idx, y, g.n[0], g.n[1], g.n[2]);
+            c0[0] = it.ax[0].i0;
+            c0[1] = it.ax[1].i0;
+            c0[2] = D == 3 ? it.ax[D - 1].i0 : 0;
+#pragma unroll
+            for (int q = 0; q < (1 << D); ++q) wq[q] = it.weight(q) * m;
+        }
+    }
+    T my = 0;
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) my = fmax(my, fabs(wq[q]));
+    for (int o = 32; o > 0; o >>= 1) my = fmax(my, __shfl_xor(my, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = my;
+    __syncthreads();
+    my = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    int e2 = 0;
+    (void)frexp((double)my, &e2);
+    const double fx = ldexp(1.0, 52 - e2), ifx = ldexp(1.0, e2 - 52);
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) {
+        const T w = wq[q];
+        if (w == (T)0) continue;
+        const int ci = c0[0] + (q & 1), cj = c0[1] + ((q >> 1) & 1), ck = D == 3 ? c0[2] + ((q >> 2) & 1) : 0;
+        const int wx = ci - ox, wy = cj - oy, wz = ck - oz;
+        if (wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
+            atomicAdd(&win[(wz * WY + wy) * WX + wx], (unsigned long long)llrint((double)w * fx));
+        else
+            atomic_add(out + cell_index(g, ci, cj, ck), w);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < WN; e += blockDim.x) {
+        const int ci = ox + e % WX, cj = oy + (e / WX) % WY, ck = oz + e / (WX * WY);
+        if (ci < 0 || cj < 0 || ck < 0 || ci >= g.n[0] || cj >= g.n[1] || ck >= g.n[2]) continue;
+        const long long s = (long long)win[e];
+        if (s != 0) atomic_add(out + cell_index(g, ci, cj, ck), (T)((double)s * ifx));
+    }
+}
+
+// Tiled from 131072 cells per launch (at 64^3 x 60: 1506 -> 271 us); below,
+// a launch is a short chain of dependent steps and the window's clear and
+// flush cost more than the global atomics it saves (128^2, one slice: 2.9
+// against 4.2 us), so each cell adds its weights straight into out.
+template <typename T, int D>
+inline void launch_advect_T(const Grid& g, T cfl, const T* mu, const T* v, T* out, int batch, hipStream_t st) {
+    if ((long)g.ncell * batch < 131072) {
+        k_advect_T<T, D><<<dim3((g.ncell + 255) / 256, batch), 256, 0, st>>>(g, cfl, mu, v, out, g.ncell, g.nface);
+        return;
+    }
+    using TS = TileShape<D>;
+    const int tiles = ((g.n[0] + TS::X - 1) / TS::X) * ((g.n[1] + TS::Y - 1) / TS::Y) *
+                      ((g.n[2] + TS::Z - 1) / TS::Z);
+    k_advect_T_tiled<T, D><<<dim3(tiles, batch), 256, 0, st>>>(g, cfl, mu, v, out, g.ncell, g.nface);
+}
+
 template <typename T, int D>
 __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restrict__ v, const T* __restrict__ y,
                                           T scale, T* out, long vs, int tile, int slice, int a, int cpar = -1) {

@@ -820,11 +820,7 @@ public:
         const Grid& g = L[0];
         k_advect<T, D><<<dim3(blocks_for(g.ncell, BS), batch), BS, 0, st>>>(g, cfl(0), r, v, out, g.ncell, g.nface);
     }
-    void advect_T(const T* m, const T* v, T* out, int batch) {
-        const Grid& g = L[0];
-        k_advect_T<T, D><<<dim3(blocks_for(g.ncell, BS), batch), BS, 0, st>>>(g, cfl(0), m, v, out, g.ncell,
-                                                                             g.nface);
-    }
+    void advect_T(const T* m, const T* v, T* out, int batch) { launch_advect_T<T, D>(L[0], cfl(0), m, v, out, batch, st); }
     void advect_dv_T(const T* m, const T* r, const T* v, const T* vtt, T scale, T* gv, int batch) {
         const Grid& g = L[0];
         k_advect_dv_T<T, D><<<dim3(blocks_for(g.nface, BS), batch), BS, 0, st>>>(g, cfl(0), m, r, v, vtt, scale,

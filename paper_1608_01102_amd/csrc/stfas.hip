@@ -108,7 +108,7 @@ struct Step {
         } else {
             k_advect_dv_T<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, grho_o, rho, v, nullptr, (T)1, gv,
                                                                        g.ncell, g.nface);
-            k_advect_T<T, D><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g, cfl, grho_o, v, grho, g.ncell, g.nface);
+            launch_advect_T<T, D>(g, cfl, grho_o, v, grho, 1, st);
         }
         launch_self_advect_T<T, D>(g, cfl, v, gw, (T)1, gv, 1, st);
     }

@@ -181,7 +181,8 @@ def ops_expectations():
     half = (n0 + 1) // 2 * n1 * n2
     return [
         ("SL density advection", "k_advect<", _ceil256(C), N, N * C * 20, "rho, 3 face velocities, rho' per cell"),
-        ("its rho adjoint", "k_advect_T<", _ceil256(C), N, N * C * 24, "mu, 3 face velocities, out read+write"),
+        ("its rho adjoint", "k_advect_T_tiled<", ((n0 + 7) // 8) * ((n1 + 7) // 8) * ((n2 + 3) // 4) * 256, N,
+         N * C * 24, "mu, 3 face velocities, out read+write"),
         ("its v adjoint", "k_advect_dv_T<", _ceil256(F), N, N * F * 16, "mu, rho, v, out per face"),
         ("SL self-advection", "k_self_advect<", _ceil256(F), N, N * F * 12, "v, u, out per face"),
         ("its adjoint (tiled)", "k_self_advect_T_tiled<", None, N, N * F * 16, "v, y, out read+write per face"),

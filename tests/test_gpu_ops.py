@@ -104,6 +104,27 @@ def test_self_advect_T_tiled_sizes(n, B, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,B", [((96, 80), 20), ((40, 32, 24), 6), ((33, 17), 300)])
+def test_advect_T_tiled_sizes(n, B, prec):
+    """The tiled density adjoint (LDS window in fixed point, one flush per
+    node) at launch sizes above its threshold, with ragged tiles at the grid
+    edges and backtraces of up to 3 cells (beyond the halo: the global-atomic
+    path)."""
+    S, ctx, g, dt, K = _ctx(n, 2, prec, dt=1.0 / n[0])
+    rng = np.random.default_rng(25)
+    assert g.ncell * B >= 131072
+    v = _q(np.stack([synthetic.curl_noise_velocity(n, rng, 2.0, 3.0, dt / g.h) for _ in range(B)]), prec)
+    mu = _q(rng.standard_normal((B, g.ncell)), prec)
+    add = _q(rng.standard_normal((B, g.ncell)), prec)
+    out = empty(B * g.ncell, prec)
+    flag(f"advect_T tiled n={n} B={B} {prec}")
+    S.stfas_op_advect_T(ctx, B, to_dev(mu, prec), to_dev(v, prec), to_dev(add, prec), out)
+    ref = advect.advect_scalar_T(g, mu, v, dt) + add
+    assert rel(to_np(out), ref) <= TOL[prec]
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,N", CASES)
 def test_projection_batched(n, N, prec):
     S, ctx, g, dt, K = _ctx(n, N, prec)
