@@ -101,11 +101,15 @@ def main():
     if nlaunch:
         avg_us = tms * 1e3 / nlaunch
         achieved = tbytes / (tms * 1e-3) / 1e9
+        traffic, valu_us = measured_counters(args.trace_kernel)
         out["roofline"] = {"bound": "hbm", "kernel": args.trace_kernel, "achieved": achieved, "peak": 8000.0,
                            "unit": "GB/s", "frac": achieved / 8000.0,
-                           "traffic": measured_traffic(args.trace_kernel),
+                           "traffic": traffic,
                            "avg_launch_us": avg_us, "launches_timed": nlaunch,
-                           "alg_bytes_per_launch": tbytes / nlaunch}
+                           "alg_bytes_per_launch": tbytes / nlaunch,
+                           # VALU-busy share of the launch from the committed counters (instruction issue,
+                           # not HBM, is what limits this launch; see the counter summary)
+                           "valu_busy_frac": (valu_us / avg_us) if valu_us else None}
     u_mixed = u.double().cpu().numpy()
     if not args.no_fp64_check:
         # same solve in FP64 on the GPU (untimed): the mixed form's keyframe error against it
@@ -131,21 +135,24 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed counter summary of this kernel,
-    or None when there is none or the kernel sources changed since."""
+def measured_counters(kernel):
+    """HBM bytes per launch and the VALU-busy time per launch from the
+    committed counter summary of this kernel, or None for each when there is
+    none or the kernel sources changed since."""
     from paper_1608_01102_amd.profiling import kernel_source_hash
     path = os.path.join(ROOT, "profiles", f"{kernel}_128x128x40_pmc.md")
     if not os.path.exists(path):
-        return None
+        return None, None
     vals = {}
     for line in open(path):
-        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_hash"):
-            k, v = line.split(":", 1)
-            vals[k] = v.strip()
+        key = line.split(":")[0]
+        if ":" in line and key in ("traffic_bytes_per_launch", "valu_busy_us_per_launch", "kernel_source_hash"):
+            vals[key] = line.split(":", 1)[1].strip()
     if vals.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    return float(vals["traffic_bytes_per_launch"])
+        return None, None
+    t = float(vals["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in vals else None
+    u = float(vals["valu_busy_us_per_launch"]) if "valu_busy_us_per_launch" in vals else None
+    return t, u
 
 
 def lbfgs_run(S, ctx, rho0, ks, keys, iters, eps, admm_stats):

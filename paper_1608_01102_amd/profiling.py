@@ -254,6 +254,24 @@ def ops_table(db, fetch_dir=None, write_dir=None):
     return "\n".join(lines)
 
 
+def sq_valu(directory, kernel, grid_x, simds=1024, clock_hz=2.4e9):
+    """Mean SQ_ACTIVE_INST_VALU per dispatch of KERNEL at GRID_X and the
+    VALU-busy time it stands for (4 cycles per wavefront instruction over all
+    SIMDs), from a rocprofv3 --pmc CSV directory."""
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    vals = []
+    for f in files:
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") == "SQ_ACTIVE_INST_VALU" and kernel in row.get("Kernel_Name", "") and \
+                        int(row.get("Grid_Size", row.get("Grid_Size_X", "0"))) == int(grid_x):
+                    vals.append(float(row["Counter_Value"]))
+    if not vals:
+        return {"dispatches": 0}
+    mean = sum(vals) / len(vals)
+    return {"dispatches": len(vals), "sq_active_inst_valu": mean, "valu_busy_us": mean * 4 / simds / clock_hz * 1e6}
+
+
 def main(argv):
     if argv[0] == "stats":
         print(stats(argv[1], *(argv[2:4] if len(argv) >= 4 else [])))
@@ -266,6 +284,9 @@ def main(argv):
         ops_workload()
     elif argv[0] == "opstable":
         print(ops_table(*argv[1:4]))
+    elif argv[0] == "valu":
+        import json
+        print(json.dumps(sq_valu(argv[1], argv[2], argv[3])))
     elif argv[0] == "hash":
         print(kernel_source_hash())
 
