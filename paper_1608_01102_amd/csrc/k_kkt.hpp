@@ -675,25 +675,41 @@ __device__ inline void restrict_face_at(const Grid& gf, const Grid& gc, const T*
         return;
     }
     const int I[3] = {I0, I1, I2};
-    int lo[3], hi[3];
+    // the 1D weights of each axis once (3 along a, 4 across; 0 outside the
+    // fine lattice), then the tensor-product sum in k, j, i order
+    int lo[3];
+    T wt[3][4];
+#pragma unroll
     for (int b = 0; b < 3; ++b) {
-        if (b >= D) { lo[b] = hi[b] = 0; continue; }
-        if (b == a) { lo[b] = 2 * I[b] - 1; hi[b] = 2 * I[b] + 1; }
-        else { lo[b] = 2 * I[b] - 1; hi[b] = 2 * I[b] + 2; }
+        lo[b] = b < D ? 2 * I[b] - 1 : 0;
+        const int cnt = b >= D ? 1 : (b == a ? 3 : 4);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int x = lo[b] + t;
+            wt[b][t] = (T)0;
+            if (t >= cnt) continue;
+            if (b >= D) {
+                wt[b][t] = (T)1;
+                continue;
+            }
+            if (x < 0 || x >= face_ext(gf, a, b)) continue;
+            wt[b][t] = axis_weight<T>(fine_pos<T>(x, a == b), face_ext(gc, a, b), I[b]);
+        }
     }
     T s = 0;
-    for (int k = lo[2]; k <= hi[2]; ++k) {
-        if (D == 3 && (k < 0 || k >= face_ext(gf, a, 2))) continue;
-        const T wk = D == 3 ? axis_weight<T>(fine_pos<T>(k, a == 2), face_ext(gc, a, 2), I[2]) : (T)1;
+#pragma unroll
+    for (int tk = 0; tk < 4; ++tk) {
+        const T wk = wt[2][tk];
         if (wk == (T)0) continue;
-        for (int j = lo[1]; j <= hi[1]; ++j) {
-            if (j < 0 || j >= face_ext(gf, a, 1)) continue;
-            const T wj = axis_weight<T>(fine_pos<T>(j, a == 1), face_ext(gc, a, 1), I[1]);
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) {
+            const T wj = wt[1][tj];
             if (wj == (T)0) continue;
-            for (int i = lo[0]; i <= hi[0]; ++i) {
-                if (i < 0 || i >= face_ext(gf, a, 0)) continue;
-                const T wi = axis_weight<T>(fine_pos<T>(i, a == 0), face_ext(gc, a, 0), I[0]);
-                s += wi * wj * wk * fine[face_index(gf, a, i, j, k)];
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti) {
+                const T wi = wt[0][ti];
+                if (wi == (T)0) continue;
+                s += wi * wj * wk * fine[face_index(gf, a, lo[0] + ti, lo[1] + tj, lo[2] + tk)];
             }
         }
     }
