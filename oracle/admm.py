@@ -19,6 +19,14 @@ omega = 0.7 (with omega = 1 the velocity subproblem diverges once the flow
 moves about 0.7 cells per step, because the smoother's local matrix leaves
 out the advection derivative).
 
+Augmented-Lagrangian fallback (Sec. 5, convergence analysis: ADMM falls
+back to a standard augmented Lagrangian method by leaving out the multiplier
+update until the decrease in function value drops below a threshold).
+Reading: the function value is the density subproblem's objective Phi at
+the end of the iteration's AO; with al_tol > 0 the multiplier update of
+iteration t > 1 is made only when (Phi_{t-1} - Phi_t) / |Phi_{t-1}| <= al_tol
+(the first iteration always updates); al_tol = 0 is plain ADMM.
+
 Outputs: u from the NSO; a re-simulation from (rho_0, 0) with u; the
 objective J = 1/2 sum_k <e_k, C e_k> + r/2 sum|u_i|^2, its plain-L2 variant
 and the regularisation term.
@@ -49,6 +57,7 @@ class Problem:
     fixed_counts: bool = False
     scgs_omega: float = 0.7
     density: str = "sl"               # density operator: "sl" or "upwind" (eq:Adv)
+    al_tol: float = 0.0               # augmented-Lagrangian fallback threshold (0: plain ADMM)
 
     def resolved(self, rho0):
         p = Problem(**self.__dict__)
@@ -112,7 +121,8 @@ def solve(prob: Problem, rho0, keys):
     lam = np.zeros((N, F))
     x = [np.zeros((N, F)), np.zeros((N, g.ncell)), np.zeros((N, F)), np.zeros((N, g.ncell))]
     rho_last = np.tile(rho0, (N + 1, 1))
-    hist = {"visual_diff": [], "ao_phi": [], "nso_res": []}
+    hist = {"visual_diff": [], "ao_phi": [], "nso_res": [], "updates": 0}
+    phi_prev = None
     total_vc = 0
     converged = False
     it = 0
@@ -136,7 +146,14 @@ def solve(prob: Problem, rho0, keys):
             converged = True
             break
         rho_last = rho.copy()
-        lam = lam + p.K * p.beta * (v_all - vstar)
+        phi = phis[-1]
+        update = True
+        if p.al_tol > 0 and phi_prev is not None:
+            update = (phi_prev - phi) / max(abs(phi_prev), 1e-300) <= p.al_tol
+        phi_prev = phi
+        if update:
+            lam = lam + p.K * p.beta * (v_all - vstar)
+            hist["updates"] += 1
     u = x[2].copy()
     rho_sim, _ = resimulate(g, rho0, u, p.dt, p.density)
     J, Jl2, reg = objectives(g, rho_sim, keys, u, p.r, p.metric_levels)

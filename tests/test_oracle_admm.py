@@ -70,3 +70,22 @@ def test_admm_close_to_brute_force_optimum():
     assert Ja < 0.7 * J0
     assert bf.fun <= Ja <= 1.02 * bf.fun
     assert np.linalg.norm(ga) < 0.2 * np.linalg.norm(g0)
+
+
+def test_al_fallback_gating():
+    """The augmented-Lagrangian fallback (Sec. 5): a threshold of 1 or more
+    admits every multiplier update (Phi >= 0, so no relative decrease exceeds
+    1) and reproduces plain ADMM bit for bit; a tiny threshold updates only
+    in the first iteration and where Phi did not decrease, as the recorded
+    Phi history shows."""
+    w = synthetic.small_problem((8, 8), 3, seed=4, r=1e-2)
+    base = dict(n=w["n"], num_steps=3, r=w["r"], dt=w["dt"], max_admm=4, max_vcycles=3, fixed_counts=True)
+    plain = admm.solve(admm.Problem(**base), w["rho0"], w["keys"])
+    loose = admm.solve(admm.Problem(al_tol=1.0, **base), w["rho0"], w["keys"])
+    assert np.array_equal(plain.u, loose.u) and loose.history["updates"] == 4
+    tight = admm.solve(admm.Problem(al_tol=1e-300, **base), w["rho0"], w["keys"])
+    phis = [h[-1] for h in tight.history["ao_phi"]]
+    expected = 1 + sum(1 for t in range(1, len(phis)) if phis[t] >= phis[t - 1])
+    assert tight.history["updates"] == expected
+    assert tight.history["updates"] < 4          # this case decreases Phi, so updates are skipped
+    assert not np.array_equal(tight.u, plain.u)
