@@ -89,6 +89,10 @@ typedef struct {
     int32_t precision;      /* stfas_precision */
     double scgs_omega;      /* relaxation weight of the SCGS smoother (Sec. 4.3), in (0, 2]; <= 0 selects 0.7 */
     int32_t density_op;     /* stfas_density; 0 = semi-Lagrangian */
+    double al_tol;          /* augmented-Lagrangian fallback of the ADMM loop (Sec. 5, convergence
+                             * analysis): > 0 makes the multiplier update of an iteration t > 1 only
+                             * when the density subproblem's objective fell by at most al_tol
+                             * (relative) since iteration t - 1; 0 = plain ADMM; < 0 invalid */
 } stfas_problem;
 
 typedef struct {
@@ -101,6 +105,8 @@ typedef struct {
     double kkt_res_inf;     /* |f|_inf of the last velocity subproblem */
     double visual_diff;     /* last max_i |rho_i - rho_i^last|_inf */
     double seconds;         /* wall time of the solve */
+    int32_t multiplier_updates; /* ADMM multiplier updates made (all iterations but a converged last
+                                 * one, unless al_tol > 0 held some back) */
 } stfas_stats;
 
 /* Device bytes stfas_create allocates for this problem (exact); used for

@@ -26,6 +26,7 @@ class StfasProblem(ctypes.Structure):
         ("fixed_counts", c_int32), ("precision", c_int32),
         ("scgs_omega", c_double),
         ("density_op", c_int32),
+        ("al_tol", c_double),
     ]
 
 
@@ -34,6 +35,7 @@ class StfasStats(ctypes.Structure):
         ("admm_iters", c_int32), ("vcycles", c_int32), ("converged", c_int32),
         ("objective", c_double), ("objective_l2", c_double), ("reg_term", c_double),
         ("kkt_res_inf", c_double), ("visual_diff", c_double), ("seconds", c_double),
+        ("multiplier_updates", c_int32),
     ]
 
 

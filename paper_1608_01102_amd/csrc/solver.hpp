@@ -57,7 +57,7 @@ struct Arena {
 // Resolved problem constants (defaults of stfas.h applied).
 struct Params {
     int dim, n[3], N;
-    double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol, omega;
+    double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol, omega, al_tol;
     int ao_iters, max_admm, max_vcycles, metric_levels, fixed_counts, precision, density;
 };
 
@@ -99,6 +99,8 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     if (!(o.omega <= 2.0)) return false;
     if (p->density_op != STFAS_DENSITY_SL && p->density_op != STFAS_DENSITY_UPWIND) return false;
     o.density = p->density_op;
+    if (!(p->al_tol >= 0) || !std::isfinite(p->al_tol)) return false;
+    o.al_tol = p->al_tol;
     const double total = (double)o.n[0] * o.n[1] * o.n[2];
     if (total > 2.0e9 / (o.dim + 1)) return false;
     return true;
@@ -1452,13 +1454,14 @@ public:
             eps_admm = host_out[0] / 100.0;
         }
         const T invK = (T)(1.0 / P.K);
-        int it = 0, conv = 0, vcs = 0;
-        double last_res = 0, diff = 0;
+        int it = 0, conv = 0, vcs = 0, updates = 0;
+        double last_res = 0, diff = 0, phi_prev = 0;
+        std::vector<double> phis((size_t)P.ao_iters + 1);
         while (it < P.max_admm) {
             ++it;
             // vt = v + lambda/K (v_0 = 0)
             k_shift_combine<T><<<blocks_for(N * F, BS), BS, 0, st>>>(F, N, (T)1, q.v, invK, lam, (T)0, nullptr, vt);
-            ao(rho0, nk, ks, keys, nullptr);
+            ao(rho0, nk, ks, keys, phis.data());
             // w = v* - lambda/K
             axpby(N * F, (T)1, vstar, -invK, lam, q.w);
             vcs += nso(nullptr, &last_res);
@@ -1472,8 +1475,18 @@ public:
                 break;
             }
             copy(rho_last, rho, (N + 1) * C);
-            const T kb = (T)(P.K * P.beta);
-            k_shift_combine<T><<<blocks_for(N * F, BS), BS, 0, st>>>(F, N, kb, q.v, (T)1, lam, -kb, vstar, lam);
+            // augmented-Lagrangian fallback: hold the multipliers while the density subproblem's
+            // objective still falls by more than al_tol (relative) per iteration
+            const double phi = phis[P.ao_iters];
+            const bool update =
+                !(P.al_tol > 0 && it > 1) || (phi_prev - phi) / std::max(std::fabs(phi_prev), 1e-300) <= P.al_tol;
+            phi_prev = phi;
+            if (update) {
+                const T kb = (T)(P.K * P.beta);
+                k_shift_combine<T><<<blocks_for(N * F, BS), BS, 0, st>>>(F, N, kb, q.v, (T)1, lam, -kb, vstar,
+                                                                        lam);
+                ++updates;
+            }
         }
         copy((T*)u_out, q.u, N * F);
         // re-simulate and evaluate the objective
@@ -1507,6 +1520,7 @@ public:
             stats->kkt_res_inf = last_res;
             stats->visual_diff = diff;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            stats->multiplier_updates = updates;
         }
         if (!std::isfinite(0.5 * host_out[0] + reg)) return STFAS_E_NONFINITE;
         return STFAS_OK;

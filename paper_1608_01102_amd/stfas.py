@@ -18,7 +18,7 @@ DENSITY_OPS = {"sl": 0, "upwind": 1}
 
 def make_problem(n, num_steps, r, dt=0.0, K=0.0, beta=0.0, ao_iters=0, eps_stfas=0.0, eps_admm=0.0, max_admm=0,
                  max_vcycles=0, metric_levels=-1, poisson_rtol=0.0, fixed_counts=False, precision="fp64",
-                 scgs_omega=0.0, density="sl"):
+                 scgs_omega=0.0, density="sl", al_tol=0.0):
     """stfas_problem with the C defaults for every field left at 0 (-1 for metric_levels)."""
     p = StfasProblem()
     n = tuple(int(x) for x in n)
@@ -35,6 +35,7 @@ def make_problem(n, num_steps, r, dt=0.0, K=0.0, beta=0.0, ao_iters=0, eps_stfas
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.scgs_omega = float(scgs_omega)
     p.density_op = DENSITY_OPS[density] if isinstance(density, str) else int(density)
+    p.al_tol = float(al_tol)
     return p
 
 

@@ -170,3 +170,16 @@ def test_solve_edge_cases(name, prec):
         assert abs(st["objective"] - ref.objective) <= tol * max(ref.objective, 1e-30)
     assert np.isfinite(u).all() and np.abs(u).max() <= 10 * scale
     assert st["admm_iters"] == ref.admm_iters and st["vcycles"] == ref.vcycles
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("al_tol", [1e-300, 0.05])
+def test_solve_al_fallback(al_tol, prec):
+    """The augmented-Lagrangian fallback of the ADMM loop: same controls,
+    objective and number of multiplier updates as the oracle."""
+    w = synthetic.small_problem((8, 8), 3, seed=4, r=1e-2)
+    u, st, ref = _solve_pair(w, prec, 4, 3, al_tol=al_tol)
+    tol = TOL[prec] if prec == "fp64" else 1e-3
+    assert st["multiplier_updates"] == ref.history["updates"]
+    assert rel(u, ref.u) <= tol
+    assert abs(st["objective"] - ref.objective) <= tol * ref.objective
