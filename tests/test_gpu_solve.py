@@ -183,3 +183,31 @@ def test_solve_al_fallback(al_tol, prec):
     assert st["multiplier_updates"] == ref.history["updates"]
     assert rel(u, ref.u) <= tol
     assert abs(st["objective"] - ref.objective) <= tol * ref.objective
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_repeatable(prec):
+    """Two solves of the 32x32x10 workload on fresh contexts.  The
+    transposes add their tile windows into the output with floating-point
+    atomics, so the order of those additions varies between runs: FP64 agrees
+    to rounding, the mixed form within its parity tolerance."""
+    from paper_1608_01102_amd import stfas as S
+    w = synthetic.c1_plain_2d_32(0)
+    g = Grid(w["n"])
+    N = w["num_steps"]
+    ks = sorted(w["keys"])
+    out = []
+    for rep in range(2):
+        prob = S.make_problem(w["n"], N, w["r"], dt=w["dt"], max_admm=2, max_vcycles=4, fixed_counts=True,
+                              precision=prec)
+        ctx = S.stfas_create(prob)
+        u = zeros(N * g.nface, prec)
+        flag(f"repeatable solve {prec} run {rep}")
+        st = S.stfas_solve(ctx, to_dev(_q(w["rho0"], prec), prec), ks,
+                           to_dev(np.stack([_q(w["keys"][k], prec) for k in ks]), prec), u)
+        ctx.destroy()
+        out.append((to_np(u), st["objective"]))
+    (u0, j0), (u1, j1) = out
+    tol = 1e-12 if prec == "fp64" else 1e-3
+    assert rel(u1, u0) <= tol
+    assert abs(j1 - j0) <= tol * abs(j0)
