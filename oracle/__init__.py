@@ -28,6 +28,8 @@ Module map
 
 Parity-unpinned parts (no worked example in the paper; pinned only through
 invariants, special cases and brute force on tiny grids): the full ADMM
-trajectory (admm.solve) and the FAS V-cycle iterates on nonlinear problems
-(stfas.vcycle with advection switched on).
+trajectory (admm.solve).  The FAS V-cycle on nonlinear problems (stfas.vcycle
+with advection switched on) is pinned by two exact properties rather than
+printed values: a cycle started at an exact solution of f(x) = res returns
+it unchanged, and a cycle contracts the residual near such a solution.
 """
