@@ -97,3 +97,26 @@ def test_serving_footprint_is_exact_and_monotone():
 def synthetic_requests():
     import synthetic
     return synthetic.c5_requests(0, 12, rate=1.0)
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library every entry point raises: there is no
+    CPU fallback.  Run in a fresh interpreter with the library path pointed
+    at a file that does not exist."""
+    import subprocess
+    import sys
+    code = (
+        "import paper_1608_01102_amd._lib as L\n"
+        "L.LIB_PATH = '/nonexistent/libstfas.so'\n"
+        "from paper_1608_01102_amd import stfas as S\n"
+        "try:\n"
+        "    S.stfas_workspace_bytes(S.make_problem((8, 8), 2, 1e-2))\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "    raise SystemExit(0)\n"
+        "raise SystemExit(3)\n"
+    )
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "no CPU fallback" in out.stdout
