@@ -36,6 +36,10 @@ def parse():
                     help="iteration cap of the L-BFGS comparison (0 skips it)")
     ap.add_argument("--upwind-admm", type=int, default=10,
                     help="ADMM cap of the solve with the upwind exponential density operator (0 skips it)")
+    ap.add_argument("--al-admm", type=int, default=10,
+                    help="ADMM cap of the solves with and without the augmented-Lagrangian fallback (0 skips them)")
+    ap.add_argument("--al-tol", type=float, default=0.05,
+                    help="relative objective decrease below which the fallback updates the multipliers")
     ap.add_argument("--no-3d", action="store_true", help="skip the 64^3 x 60 precision-form comparison")
     ap.add_argument("--serve-requests", type=int, default=16, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -126,6 +130,8 @@ def main():
     ctx.destroy()
     if args.upwind_admm > 0:
         out["upwind_solve"] = upwind_run(S, w, kw, rho0, ks, keys, args.upwind_admm, last)
+    if args.al_admm > 0:
+        out["al_fallback"] = al_run(S, w, kw, rho0, ks, keys, args.al_admm, args.al_tol)
     if not args.no_3d:
         out["precision_3d"] = precision_3d_run(S)
     if args.serve_requests > 0:
@@ -191,6 +197,29 @@ def upwind_run(S, w, kw, rho0, ks, keys, max_admm, sl_stats):
             "seconds": st["seconds"], "objective": st["objective"], "visual_diff": st["visual_diff"],
             "s_per_admm_iter": st["seconds"] / max(st["admm_iters"], 1),
             "sl_s_per_admm_iter": sl_stats["seconds"] / max(sl_stats["admm_iters"], 1)}
+
+
+def al_run(S, w, kw, rho0, ks, keys, max_admm, al_tol):
+    """The augmented-Lagrangian fallback of the ADMM loop (outside the step
+    clock): the same workload and ADMM cap solved with plain ADMM and with
+    the multiplier update held while the density subproblem's objective still
+    falls by more than al_tol; ADMM iterations, multiplier updates, objective,
+    visual difference and seconds of each (one warm-up solve first)."""
+    import torch
+    n, N = w["n"], w["num_steps"]
+    res = {"admm_cap": max_admm, "al_tol": al_tol}
+    for name, tol in (("plain", 0.0), ("fallback", al_tol)):
+        prob = S.make_problem(n, N, w["r"], precision="mixed", al_tol=tol, **dict(kw, max_admm=max_admm))
+        ctx = S.stfas_create(prob)
+        u = torch.zeros(N * ctx.faces, dtype=torch.float32, device=rho0.device)
+        S.stfas_solve(ctx, rho0, ks, keys, u)          # warm-up
+        torch.cuda.synchronize()
+        st = S.stfas_solve(ctx, rho0, ks, keys, u)
+        ctx.destroy()
+        res[name] = {"admm_iters": st["admm_iters"], "multiplier_updates": st["multiplier_updates"],
+                     "vcycles": st["vcycles"], "objective": st["objective"], "visual_diff": st["visual_diff"],
+                     "seconds": st["seconds"]}
+    return res
 
 
 def precision_3d_run(S):
