@@ -9,8 +9,9 @@ visual difference or 50 iterations.  Inputs are synthetic and seeded
 
 Prints one JSON line: the solve rate with its roofline (the finest residual
 launch, timed with HIP events on the solver's stream, and its counter-
-measured HBM bytes), the FP64 solve beside the mixed one, the L-BFGS and
-upwind-operator comparisons, the serving run and the oracle's CPU rate."""
+measured HBM bytes), the FP64 solve beside the mixed one, the L-BFGS,
+upwind-operator and augmented-Lagrangian-fallback comparisons, the 3D
+precision form, the serving run and the oracle's CPU rate."""
 import argparse
 import json
 import os
