@@ -80,7 +80,10 @@ __device__ inline T up_face(const T* __restrict__ x, T vf, int cR, int s, int I,
 }
 
 // Block maximum of a non-negative value (256 threads, four waves) folded
-// into *out by its bit pattern.
+// into *out by its bit pattern.  Atomics on one word serialise, so a block
+// first reads the word (at device scope) and folds only when it would raise
+// it: the word only grows after its reset, so a value at or below what was
+// read can never be the maximum's last word, and the result is unchanged.
 template <typename T>
 __device__ inline void block_max_fold(T m, typename UpBits<T>::U* out) {
     __shared__ T wm[4];
@@ -90,7 +93,8 @@ __device__ inline void block_max_fold(T m, typename UpBits<T>::U* out) {
     __syncthreads();
     if (threadIdx.x == 0) {
         const T b = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
-        atomicMax(out, UpBits<T>::of(b));
+        const typename UpBits<T>::U bb = UpBits<T>::of(b);
+        if (bb > __hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(out, bb);
     }
 }
 

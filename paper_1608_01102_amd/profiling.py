@@ -164,6 +164,14 @@ def ops_workload(reps=5):
         S.stfas_op_prolong(ctx, 0, coarse, 1.0, st)
     torch.cuda.synchronize()
     ctx.destroy()
+    # the upwind exponential density operator on one field of the same grid
+    # (its series is launched term by term; the table needs its k)
+    pu = S.make_problem(n, 1, 1e-3, precision="mixed", density="upwind")
+    cu = S.stfas_create(pu)
+    ks = [S.stfas_op_upwind(cu, rho[:C], v1, out_c[:C]) for _ in range(reps)]
+    torch.cuda.synchronize()
+    cu.destroy()
+    print(f"upwind series k = {ks[0]} (all calls: {ks})", flush=True)
     print("ops workload done", flush=True)
 
 
@@ -225,9 +233,27 @@ def _stfas_expectations(n0, n1, n2, N, C, F):
     ]
 
 
-def ops_table(db, fetch_dir=None, write_dir=None):
+def upwind_term_row(rows, k, C, F):
+    """Table row of the upwind series' working terms: the k_up_term
+    launches of each series in launch order (terms 0 .. UP_KMAX), of which
+    terms 1..k compute a term (0 copies rho into the sum, terms after k
+    return at once).  Algorithmic bytes per term: prev, next and the sum's
+    read and write per cell, the velocity once per face."""
+    per = 49                                  # terms 0..48 launched per call of the operator
+    ds = [r[4] for r in rows if "k_up_term<" in r[0]]
+    if not ds or len(ds) % per:
+        return None
+    work = [d for s0 in range(0, len(ds), per) for d in ds[s0 + 1:s0 + 1 + k]]
+    avg = sum(work) / len(work)
+    nbytes = C * 16 + F * 4
+    gbs = nbytes / avg
+    return (f"| upwind exponential, one term (k = {k}) | `k_up_term` | {len(work)} | {avg / 1e3:.1f} | "
+            f"{nbytes / 1e6:.1f} | {gbs:.0f} | {100 * gbs / 8000:.0f}% |")
+
+
+def ops_table(db, fetch_dir=None, write_dir=None, upwind_k=None):
     con = sqlite3.connect(db)
-    rows = con.execute("select name, grid_x, grid_y, grid_z, duration from kernels").fetchall()
+    rows = con.execute("select name, grid_x, grid_y, grid_z, duration from kernels order by start").fetchall()
     lines = ["| Operator | Kernel | Launches | Avg µs | Alg. MB/launch | Alg. GB/s | % of 8000 |"
              + (" HBM MB/launch | HBM GB/s |" if fetch_dir else ""),
              "|---|---|---|---|---|---|---|" + ("---|---|" if fetch_dir else "")]
@@ -251,6 +277,13 @@ def ops_table(db, fetch_dir=None, write_dir=None):
             else:
                 line += " | |"
         lines.append(line)
+    if upwind_k is not None:
+        n0, n1, n2 = OPS_N
+        C = n0 * n1 * n2
+        F = (n0 + 1) * n1 * n2 + n0 * (n1 + 1) * n2 + n0 * n1 * (n2 + 1)
+        row = upwind_term_row(rows, int(upwind_k), C, F)
+        if row:
+            lines.append(row + (" | |" if fetch_dir else ""))
     return "\n".join(lines)
 
 
@@ -283,7 +316,7 @@ def main(argv):
     elif argv[0] == "ops":
         ops_workload()
     elif argv[0] == "opstable":
-        print(ops_table(*argv[1:4]))
+        print(ops_table(*argv[1:5]))
     elif argv[0] == "valu":
         import json
         print(json.dumps(sq_valu(argv[1], argv[2], argv[3])))
