@@ -17,16 +17,20 @@ from . import stfas as S
 
 
 class _Work:
-    """Step scratch per (problem shape, device), allocated once."""
+    """Step scratch per (byte count, device), allocated once.  The key is the
+    library's own byte count for the problem, so problems that need more
+    scratch (a larger grid, FP64, the upwind density operator's series terms)
+    never share a smaller buffer."""
 
     _cache = {}
 
     @classmethod
     def get(cls, prob, device):
-        key = (prob.dim, tuple(prob.n), prob.precision, str(device))
+        nbytes = S.stfas_step_work_bytes(prob)
+        key = (nbytes, str(device))
         buf = cls._cache.get(key)
         if buf is None:
-            buf = torch.empty(S.stfas_step_work_bytes(prob), dtype=torch.uint8, device=device)
+            buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
             cls._cache[key] = buf
         return buf
 

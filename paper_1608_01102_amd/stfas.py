@@ -183,11 +183,24 @@ def stfas_lbfgs(ctx, rho0, key_steps, key_rho, u_inout, iters, eps_stop=0.0):
     return list(hist[:done.value + 1]), done.value
 
 
+def _step_work(prob, work, device):
+    """The step's scratch: allocated here when not given; a given buffer must
+    hold at least the library's byte count for this problem (the C calls take
+    no size, so a short buffer would be overrun)."""
+    need = stfas_step_work_bytes(prob)
+    if work is None:
+        return torch.empty(need, dtype=torch.uint8, device=device)
+    have = work.numel() * work.element_size()
+    if not work.is_contiguous() or have < need:
+        raise ValueError(f"step work buffer holds {have} bytes (contiguous: {work.is_contiguous()}); "
+                         f"this problem needs {need}")
+    return work
+
+
 def stfas_step_forward(prob, rho, v, u, rho_out, v_out, p_out=None, work=None, stream=None):
     dt = dtype_of(prob)
     c, f = counts(prob)
-    if work is None:
-        work = torch.empty(stfas_step_work_bytes(prob), dtype=torch.uint8, device=rho.device)
+    work = _step_work(prob, work, rho.device)
     check(_lib.load().stfas_step_forward(
         ctypes.byref(prob), _stream(stream), _ptr(rho, dt, c, "rho"), _ptr(v, dt, f, "v"), _ptr(u, dt, f, "u"),
         _ptr(rho_out, dt, c, "rho_out"), _ptr(v_out, dt, f, "v_out"), _ptr(p_out, dt, c, "p_out", optional=True),
@@ -197,8 +210,7 @@ def stfas_step_forward(prob, rho, v, u, rho_out, v_out, p_out=None, work=None, s
 def stfas_step_backward(prob, rho, v, g_rho_out, g_v_out, g_rho, g_v, g_u, work=None, stream=None):
     dt = dtype_of(prob)
     c, f = counts(prob)
-    if work is None:
-        work = torch.empty(stfas_step_work_bytes(prob), dtype=torch.uint8, device=rho.device)
+    work = _step_work(prob, work, rho.device)
     check(_lib.load().stfas_step_backward(
         ctypes.byref(prob), _stream(stream), _ptr(rho, dt, c, "rho"), _ptr(v, dt, f, "v"),
         _ptr(g_rho_out, dt, c, "g_rho_out"), _ptr(g_v_out, dt, f, "g_v_out"), _ptr(g_rho, dt, c, "g_rho"),

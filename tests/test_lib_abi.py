@@ -120,3 +120,33 @@ def test_missing_library_fails_loudly():
     out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "no CPU fallback" in out.stdout
+
+
+def test_step_work_cache_keyed_on_byte_count(monkeypatch):
+    """The differentiation form's cached step scratch is keyed on the
+    library's byte count for the problem, so an upwind step (series terms in
+    its scratch) after a semi-Lagrangian one of the same grid never reuses
+    the smaller buffer; a given buffer shorter than that count is refused
+    before any C call."""
+    import torch
+    from paper_1608_01102_amd import autograd as AG
+    from paper_1608_01102_amd import stfas as S
+    sl = S.make_problem((32, 32), 1, 1e-3)
+    up = S.make_problem((32, 32), 1, 1e-3, density="upwind")
+    assert S.stfas_step_work_bytes(up) > S.stfas_step_work_bytes(sl)
+    made = []
+
+    def fake_empty(n, dtype=None, device=None):
+        made.append(n)
+        return torch.zeros(n, dtype=dtype)
+    monkeypatch.setattr(AG.torch, "empty", fake_empty)
+    monkeypatch.setattr(AG._Work, "_cache", {})
+    a = AG._Work.get(sl, "cpu")
+    b = AG._Work.get(up, "cpu")
+    assert a is not b and b.numel() == S.stfas_step_work_bytes(up)
+    assert AG._Work.get(sl, "cpu") is a and made == [S.stfas_step_work_bytes(sl), S.stfas_step_work_bytes(up)]
+    monkeypatch.undo()
+    short = torch.zeros(S.stfas_step_work_bytes(up) - 1, dtype=torch.uint8)
+    with pytest.raises(ValueError):
+        S._step_work(up, short, "cpu")
+    assert S._step_work(sl, short, "cpu") is short
