@@ -135,7 +135,7 @@ stfas_status stfas_create_in(const stfas_problem* prob, void* hip_stream, void* 
 stfas_status stfas_solve(stfas_ctx* ctx, const void* rho0, int32_t num_key, const int32_t* key_steps,
                          const void* key_rho, void* u_out, stfas_stats* stats);
 
-/* Gradient-based baseline (Sec. 7, the comparison with LBFGS; Sec. 3.2 for
+/* Gradient-based baseline (Sec. 5, the comparison with LBFGS; Sec. 3.2 for
  * the reduced problem): L-BFGS over the controls with the simulation
  * eliminated, J(u) = 1/2 sum_k <e_k, C e_k> + r/2 |u|^2 (eq:opt), its
  * gradient by the adjoint of the step chain (one forward and one backward
@@ -145,7 +145,7 @@ stfas_status stfas_solve(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
  * Runs at most iters iterations; stops early when the line search finds no
  * decrease, or, for eps_stop > 0, after an iterate whose density trajectory
  * differs from the previous one by at most eps_stop (max over steps and
- * cells: the ADMM stop of Alg:outter, which Sec. 7 applies to both
+ * cells: the ADMM stop of Alg:outter, which Sec. 5 applies to both
  * optimisers).  eps_stop < 0 or NaN: STFAS_E_INVALID.
  * Keys as for stfas_solve.  u_inout [N][faces] (device): the starting
  * controls in, the last accepted iterate out.  J_hist (host, may be NULL):

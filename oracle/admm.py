@@ -121,7 +121,7 @@ def solve(prob: Problem, rho0, keys):
     lam = np.zeros((N, F))
     x = [np.zeros((N, F)), np.zeros((N, g.ncell)), np.zeros((N, F)), np.zeros((N, g.ncell))]
     rho_last = np.tile(rho0, (N + 1, 1))
-    hist = {"visual_diff": [], "ao_phi": [], "nso_res": [], "updates": 0}
+    hist = {"visual_diff": [], "ao_phi": [], "nso_res": [], "nso_f0": [], "updates": 0}
     phi_prev = None
     total_vc = 0
     converged = False
@@ -134,9 +134,11 @@ def solve(prob: Problem, rho0, keys):
         vstar, rho, phis = ao.solve(g, rho0, keys, vt, p.K, p.dt, p.metric_levels, p.ao_iters, kind=p.density)
         hist["ao_phi"].append(phis)
         w = vstar - lam / p.K
-        nv, rh = stfas.nso(H, x, w, p.eps_stfas, p.max_vcycles, p.fixed_counts)
+        info = {}
+        nv, rh = stfas.nso(H, x, w, p.eps_stfas, p.max_vcycles, p.fixed_counts, info)
         total_vc += nv
         hist["nso_res"].append(rh)
+        hist["nso_f0"].append(info["f0"])
         # v_i for i = 1..N-1 lives in slots 0..N-2 of x[0]
         v_all = np.zeros((N, F))
         v_all[1:] = x[0][:N - 1]

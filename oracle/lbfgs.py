@@ -1,5 +1,5 @@
 """L-BFGS on the reduced objective: the gradient-based baseline the paper
-compares against (Sec. 7, "Comparison with LBFGS"; Sec. 3.2 for the approach
+compares against (Sec. 5, "Comparison with LBFGS"; Sec. 3.2 for the approach
 it stands for: eliminate the simulation and minimise over u directly).
 
 Test infrastructure: only the tests, the smoke check and the benchmark's CPU
@@ -16,7 +16,7 @@ paper's), initial Hessian gamma I with gamma = s^T y / y^T y of the newest
 pair, and 1 / |g| on the first iteration; a backtracking line search on
 the Armijo condition (c1 = 1e-4, first trial step 1, halved up to 20
 times); a pair with y^T s <= 1e-12 |s| |y| is not stored.  The paper does
-not state its line search: this is the reading.  Stopping (Sec. 7 uses the
+not state its line search: this is the reading.  Stopping (Sec. 5 uses the
 same criterion for both optimisers, the ADMM one of Sec. 5): after an
 accepted iterate, stop when the largest change of the density over all
 steps between it and the previous iterate is at most eps_stop.

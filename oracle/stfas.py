@@ -72,12 +72,15 @@ def vcycle(H: Hierarchy, l, x, ws, res, pre=2, post=2, coarse_sweeps=10):
         sweep(L, x, ws[l], res)
 
 
-def nso(H: Hierarchy, x, w, eps=1e-5, max_vcycles=30, fixed_counts=False):
-    """Returns (vcycles run, |f|_inf history)."""
+def nso(H: Hierarchy, x, w, eps=1e-5, max_vcycles=30, fixed_counts=False, info=None):
+    """Returns (vcycles run, |f|_inf history); info (a dict), if given,
+    receives f0 = |f(0)|_inf, the scale of the relative stop."""
     L = H.levels[0]
     ws = H.targets(w)
     zero = [np.zeros_like(a) for a in x]
     f0 = inf_norm(residual_f(L, zero, w))
+    if info is not None:
+        info["f0"] = f0
     res = [np.zeros_like(a) for a in x]
     hist = [inf_norm(residual_f(L, x, w))]
     n = 0

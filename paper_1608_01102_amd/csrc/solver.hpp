@@ -1254,7 +1254,7 @@ public:
     // y's <= 1e-12 |s||y| are not kept.  With eps_stop > 0 it stops after an
     // accepted iterate whose density trajectory differs from the previous
     // one by at most eps_stop (max over all steps and cells), the ADMM stop
-    // of Alg:outter, which the paper applies to both optimisers (Sec. 7).
+    // of Alg:outter, which the paper applies to both optimisers (Sec. 5).
     // Buffers are allocated on the first
     // call and freed with the context.  Returns the iterations done, -1 when
     // the buffers cannot be allocated, -2 for a non-finite objective.

@@ -1,5 +1,5 @@
 """Parity of the L-BFGS baseline (the gradient-based optimiser the paper
-compares against in Sec. 7) with the FP64 oracle, through the C interface:
+compares against in Sec. 5) with the FP64 oracle, through the C interface:
 same objective history, same iteration count, same controls."""
 import numpy as np
 import pytest
