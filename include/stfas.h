@@ -176,6 +176,29 @@ stfas_status stfas_step_backward(const stfas_problem* prob, void* hip_stream, co
 
 size_t stfas_step_work_bytes(const stfas_problem* prob);
 
+/* Size of the library's static device scratch used by
+ * stfas_step_forward_noalloc (one array per device, held until the process
+ * ends). */
+#define STFAS_NOALLOC_SCRATCH_BYTES (80u << 20)
+
+/* stfas_step_forward without the work argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The step's scratch (the coarsest
+ * Poisson level's pseudo-inverse followed by stfas_step_work_bytes(prob)
+ * bytes of projection buffers) lives in a static device array of
+ * STFAS_NOALLOC_SCRATCH_BYTES per device, which the call never allocates or
+ * frees.  A problem whose scratch exceeds that size returns STFAS_E_INVALID
+ * before any launch (SL steps fit up to 128^3 in FP32 and 96^3 in FP64).
+ * The first call on a device looks the array up (hipGetSymbolAddress); a
+ * call whose coarse grid differs from the previous call's uploads that
+ * grid's pseudo-inverse (computed and cached on the host) to the array on
+ * the stream.  Inputs, outputs, results and asynchrony are those of
+ * stfas_step_forward.  Every call on one device shares the one array and it
+ * keeps the last call's contents: calls that overlap on a device (other
+ * streams, other host threads) race and must be serialised by the caller. */
+stfas_status stfas_step_forward_noalloc(const stfas_problem* prob, void* hip_stream, const void* rho, const void* v,
+                                        const void* u, void* rho_out, void* v_out, void* p_out);
+
 /* Number of projection V-cycles the step functions run (depends on the
  * precision only; chosen so that the relative residual reaches
  * poisson_rtol on smooth data). */

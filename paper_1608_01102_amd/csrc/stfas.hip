@@ -114,14 +114,75 @@ struct Step {
     }
 };
 
+// Scratch of the allocation-free forward step: the coarsest level's
+// pseudo-inverse (m x m doubles) followed by the step's own buffers.  The
+// array lives once per device for the life of the process; host code only
+// ever uses its device address from hipGetSymbolAddress (the array's name is
+// a host-side stand-in there).
+__device__ __align__(256) char scratch[STFAS_NOALLOC_SCRATCH_BYTES];
+
+struct NoallocDevice {
+    char* ptr = nullptr;      // device address of `scratch` on this device
+    Grid pinv_grid{};         // coarse grid whose pseudo-inverse the scratch holds
+    bool pinv_valid = false;
+};
+std::mutex g_noalloc_mu;
+std::map<int, NoallocDevice> g_noalloc;
+// host copies of the coarse pseudo-inverses, kept for the life of the process
+// (an asynchronous upload reads them after the call returns)
+std::map<std::tuple<int, int, int, int>, std::vector<double>> g_pinv_host;
+
+size_t pinv_bytes(const Grid& coarse) {
+    const size_t b = (size_t)coarse.ncell * coarse.ncell * sizeof(double);
+    return (b + 255) & ~(size_t)255;
+}
+
+bool same_grid(const Grid& a, const Grid& b) {
+    return a.dim == b.dim && a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2];
+}
+
+// The device address of `scratch` on the current device, fetched once per
+// device; with `coarse` set, also makes sure its head holds that grid's
+// pseudo-inverse (uploaded on `st` when another grid's is there).
+char* noalloc_scratch(const Grid& coarse, hipStream_t st) {
+    int dev = 0;
+    HCK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    NoallocDevice& nd = g_noalloc[dev];
+    if (!nd.ptr) {
+        void* ptr = nullptr;
+        HCK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        nd.ptr = (char*)ptr;
+    }
+    if (!nd.pinv_valid || !same_grid(nd.pinv_grid, coarse)) {
+        auto& pv = g_pinv_host[std::make_tuple(coarse.dim, coarse.n[0], coarse.n[1], coarse.n[2])];
+        if (pv.empty()) coarse_pinv(coarse, pv);
+        HCK(hipMemcpyAsync(nd.ptr, pv.data(), pv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        nd.pinv_grid = coarse;
+        nd.pinv_valid = true;
+    }
+    return nd.ptr;
+}
+
 template <typename T, int D>
 stfas_status run_step(const Params& p, hipStream_t st, void* work, bool fwd, const void* a0, const void* a1,
-                      const void* a2, const void* a3, void* o0, void* o1, void* o2) {
+                      const void* a2, const void* a3, void* o0, void* o1, void* o2, bool noalloc = false) {
     Step<T, D> s(p, st);
     if (!s.pois.coarse_ok()) return STFAS_E_INVALID;
     Arena A;
-    A.base = (char*)work;
-    s.layout(A, cached_pinv(s.pois.PG.back(), st));
+    double* pinv = nullptr;
+    if (noalloc) {
+        const Grid& coarse = s.pois.PG.back();
+        const size_t head = pinv_bytes(coarse);
+        if (head + s.bytes() > (size_t)STFAS_NOALLOC_SCRATCH_BYTES) return STFAS_E_INVALID;
+        char* base = noalloc_scratch(coarse, st);
+        pinv = (double*)base;
+        A.base = base + head;
+    } else {
+        A.base = (char*)work;
+        pinv = cached_pinv(s.pois.PG.back(), st);
+    }
+    s.layout(A, pinv);
     if (fwd)
         s.forward(p, (const T*)a0, (const T*)a1, (const T*)a2, (T*)o0, (T*)o1, (T*)o2);
     else
@@ -131,13 +192,13 @@ stfas_status run_step(const Params& p, hipStream_t st, void* work, bool fwd, con
 }
 
 stfas_status dispatch_step(const Params& p, hipStream_t st, void* work, bool fwd, const void* a0, const void* a1,
-                           const void* a2, const void* a3, void* o0, void* o1, void* o2) {
+                           const void* a2, const void* a3, void* o0, void* o1, void* o2, bool noalloc = false) {
     if (p.precision == STFAS_FP64) {
-        if (p.dim == 2) return run_step<double, 2>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2);
-        return run_step<double, 3>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2);
+        if (p.dim == 2) return run_step<double, 2>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc);
+        return run_step<double, 3>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc);
     }
-    if (p.dim == 2) return run_step<float, 2>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2);
-    return run_step<float, 3>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2);
+    if (p.dim == 2) return run_step<float, 2>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc);
+    return run_step<float, 3>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc);
 }
 
 size_t step_bytes(const Params& p) {
@@ -288,6 +349,17 @@ stfas_status stfas_step_forward(const stfas_problem* prob, void* hip_stream, con
     if (!rho || !v || !u || !rho_out || !v_out || !work) return STFAS_E_INVALID;
     return guard([&]() {
         return dispatch_step(p, (hipStream_t)hip_stream, work, true, rho, v, u, nullptr, rho_out, v_out, p_out);
+    });
+}
+
+stfas_status stfas_step_forward_noalloc(const stfas_problem* prob, void* hip_stream, const void* rho, const void* v,
+                                        const void* u, void* rho_out, void* v_out, void* p_out) {
+    Params p;
+    if (!resolve(prob, p)) return STFAS_E_INVALID;
+    if (!rho || !v || !u || !rho_out || !v_out) return STFAS_E_INVALID;
+    return guard([&]() {
+        return dispatch_step(p, (hipStream_t)hip_stream, nullptr, true, rho, v, u, nullptr, rho_out, v_out, p_out,
+                             true);
     });
 }
 

@@ -207,6 +207,16 @@ def stfas_step_forward(prob, rho, v, u, rho_out, v_out, p_out=None, work=None, s
         ctypes.c_void_p(work.data_ptr())), "stfas_step_forward")
 
 
+def stfas_step_forward_noalloc(prob, rho, v, u, rho_out, v_out, p_out=None, stream=None):
+    """stfas_step_forward on the library's static device scratch (no work buffer, no allocation)."""
+    dt = dtype_of(prob)
+    c, f = counts(prob)
+    check(_lib.load().stfas_step_forward_noalloc(
+        ctypes.byref(prob), _stream(stream), _ptr(rho, dt, c, "rho"), _ptr(v, dt, f, "v"), _ptr(u, dt, f, "u"),
+        _ptr(rho_out, dt, c, "rho_out"), _ptr(v_out, dt, f, "v_out"), _ptr(p_out, dt, c, "p_out", optional=True)),
+        "stfas_step_forward_noalloc")
+
+
 def stfas_step_backward(prob, rho, v, g_rho_out, g_v_out, g_rho, g_v, g_u, work=None, stream=None):
     dt = dtype_of(prob)
     c, f = counts(prob)
