@@ -12,7 +12,14 @@ Velocity self-advection: S(v) on every interior a-face backtraces with the
 face velocity (own component, plus the 4-face average of each other
 component) and interpolates v_a on the a-face lattice.  It replaces the
 implicit velocity-vorticity term of eq:NSA, giving the explicit step
-v_{i+1} = Q(S(v_i) + dt u_i).
+v_{i+1} = Q(S(v_i) + dt u_i).  The interpolation of S is the C1 variant of
+the multilinear one (smoothstep of each fraction, see interp.Stencil): the
+KKT residual of the velocity subproblem contains J_S(v)^T u, whose foot-point
+term is the interpolant's gradient, and with plain multilinear weights that
+gradient jumps where a foot point crosses a lattice line, so eq:KKTAO has no
+continuous residual for the FAS cycle of Alg:STFAS to drive to zero (it
+settles into a limit cycle); the paper's own velocity operator is a smooth
+finite-difference one.  The density keeps plain multilinear weights.
 
 All backtraces are computed in index space as  Y = X - (dt/h) * velocity.
 Every function accepts one field (1-D) or a batch of independent fields
@@ -139,7 +146,8 @@ def self_advect(g: Grid, v, dt, h=None):
     oparts = _faces(g, out)
     for a in range(g.dim):
         Y = _interior_positions(g, a)[None] - (dt / h) * face_velocity(g, v, a)
-        val = interp(vparts[a].reshape(B, -1), Y, g.face_lattice_extent(a))
+        ext = g.face_lattice_extent(a)
+        val = interp(vparts[a].reshape(B, -1), Y, ext, Stencil(Y, ext, c1=True))
         dst = oparts[a][_sl(g, a, 1, g.n[a])]
         oparts[a][_sl(g, a, 1, g.n[a])] = val.reshape(dst.shape)
     return _unbatch(out, single)
@@ -167,7 +175,7 @@ def self_advect_T(g: Grid, v, y, dt, h=None):
         Y = _interior_positions(g, a)[None] - (dt / h) * face_velocity(g, v, a)
         yin = yparts[a][_sl(g, a, 1, n[a])]
         ya = yin.reshape(B, -1)
-        st = Stencil(Y, ext)
+        st = Stencil(Y, ext, c1=True)
         acc[a] += interp_transpose(ya, Y, ext, st).reshape(acc[a].shape)
         gp = ya[..., None] * (-dt / h) * interp_grad(vparts[a].reshape(B, -1), Y, ext, st)
         for b in range(g.dim):

@@ -3,7 +3,8 @@ derivative and its transpose (needed because the semi-Lagrangian operator is
 used in place of the paper's upwind exponential, Sec. 4.1: any advection
 operator with partials in density and velocity is admissible).
 
-Convention for a lattice with M_a nodes along axis a (index coordinates):
+Convention for a lattice with M_a nodes along axis a (index coordinates;
+the C1 variant of Stencil replaces t_a below by its smoothstep):
   clamp:     Yc_a = clamp(Y_a, 0, M_a - 1)
   base cell: i0_a = min(floor(Yc_a), M_a - 2),  t_a = Yc_a - i0_a in [0, 1]
   value:     sum over the 2^d corners of prod_a (t_a or 1 - t_a) * q[corner]
@@ -21,9 +22,17 @@ import numpy as np
 
 class Stencil:
     """Corner indices, weights and (on demand) position-derivative weights of
-    the interpolation at points Y (shape (..., d), x first)."""
+    the interpolation at points Y (shape (..., d), x first).
 
-    def __init__(self, Y, extent):
+    c1=True gives the C1 variant: every fraction t is replaced by the
+    smoothstep s(t) = t^2 (3 - 2 t) before the multilinear weights are
+    formed, so the weights stay convex and interpolate the nodes, and the
+    position derivative picks up the factor s'(t) = 6 t (1 - t), which
+    vanishes at every lattice line: the interpolant is continuously
+    differentiable in Y (the plain multilinear one has a gradient that jumps
+    across lattice lines)."""
+
+    def __init__(self, Y, extent, c1=False):
         d = Y.shape[-1]
         self.d = d
         self.i0, self.t, self.inside = [], [], []
@@ -32,9 +41,14 @@ class Stencil:
             y = Y[..., a]
             yc = np.clip(y, 0.0, M - 1.0)
             i = np.minimum(np.floor(yc), M - 2).astype(np.int64)
+            t = yc - i
+            inside = ((y >= 0.0) & (y <= M - 1.0)).astype(np.float64)
+            if c1:
+                inside = inside * 6.0 * t * (1.0 - t)
+                t = t * t * (3.0 - 2.0 * t)
             self.i0.append(i)
-            self.t.append(yc - i)
-            self.inside.append(((y >= 0.0) & (y <= M - 1.0)).astype(np.float64))
+            self.t.append(t)
+            self.inside.append(inside)
         self.stride = [1] * d
         for a in range(1, d):
             self.stride[a] = self.stride[a - 1] * extent[a - 1]

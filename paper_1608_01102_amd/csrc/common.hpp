@@ -154,6 +154,21 @@ struct Interp {
         base = ax[0].i0 + ax[1].i0 * sy + (D == 3 ? ax[2].i0 * sz : 0);
     }
 
+    // C1 variant of the weights, used by the velocity self-advection: every
+    // fraction t becomes the smoothstep s(t) = t^2 (3 - 2t) and the position
+    // derivative gains the factor s'(t) = 6t(1 - t).  The weights stay convex
+    // and interpolate the nodes; the gradient, which the plain multilinear
+    // weights make jump across lattice lines, becomes continuous (s' vanishes
+    // on both sides of every lattice line).  Call after setup/setup_disp.
+    __device__ inline void c1() {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const T t = ax[a].t;
+            ax[a].in *= (T)6 * t * ((T)1 - t);
+            ax[a].t = t * t * ((T)3 - (T)2 * t);
+        }
+    }
+
     __device__ inline int corner(int c) const {
         return base + (c & 1) + ((c >> 1) & 1) * sy + (D == 3 ? ((c >> 2) & 1) * sz : 0);
     }

@@ -5,7 +5,10 @@
 // cell-centred velocity, Y = X - (dt/h) vbar, then clamped multilinear
 // interpolation.  Velocity (replaces the implicit self-advection of eq:NSA):
 // every interior a-face backtraces with its own component and the 4-face
-// averages of the others and interpolates v_a on the a-face lattice.
+// averages of the others and interpolates v_a on the a-face lattice with the
+// C1 (smoothstep) weights of Interp::c1, so that the foot-point term of its
+// transpose, and with it the KKT residual of the velocity subproblem, is
+// continuous in v.
 //
 // Launch shape: one thread per cell or face, blockIdx.y = batch slice.
 // The transposes scatter with global atomics (the foot point of a
@@ -143,6 +146,7 @@ __global__ void k_self_advect(Grid g, T cfl, T dt, const T* __restrict__ v, cons
     for (int b = 0; b < D; ++b) y[b] = -cfl * vh[b];
     Interp<T, D> it;
     it.setup_disp(idx, y, face_ext(g, a, 0), face_ext(g, a, 1), face_ext(g, a, 2));
+    it.c1();
     T s = it.value(v + g.foff[a]);
     if (u) s += dt * u[f];
     out[f] = s;
@@ -178,6 +182,7 @@ __device__ inline void self_advect_T_source(const Grid& g, T cfl, const T* __res
     for (int b = 0; b < D; ++b) dl[b] = -cfl * vh[b];
     Interp<T, D> it;
     it.setup_disp(idx, dl, ex, ey, ez);
+    it.c1();
     T gr[3];
     it.grad(v + g.foff[a], gr);
     if (yv == (T)0) return;
@@ -393,6 +398,7 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
         for (int b = 0; b < D; ++b) dl[b] = -cfl * vh[b];
         Interp<T, D> it;
         it.setup_disp(idx, dl, ex, ey, ez);
+        it.c1();
         T gr[3];
         it.grad(v + g.foff[a], gr);
         if (yv != (T)0) {

@@ -50,6 +50,7 @@ __device__ inline void kkt_face(const Grid& g, int N, T dt, T kr, T cfl, T sgn, 
         for (int b = 0; b < D; ++b) y[b] = -cfl * vh[b];
         Interp<T, D> it;
         it.setup_disp(idx, y, face_ext(g, a, 0), face_ext(g, a, 1), face_ext(g, a, 2));
+        it.c1();
         s = it.value(vp + g.foff[a]);
     }
     const T f3 = (v[e] - s) / dt - u[e] + (p[j * C + c] - p[j * C + cm]) * ih;

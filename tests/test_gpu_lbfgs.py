@@ -52,7 +52,7 @@ def test_lbfgs_mixed():
     u, hist, done, u_ref, hist_ref, done_ref = _pair(w, "mixed", 3)
     assert done == done_ref
     assert np.allclose(hist, hist_ref, rtol=1e-4, atol=0)
-    assert rel(u, u_ref) <= 1e-3
+    assert rel(u, u_ref) <= TOL["mixed"]
 
 
 def test_lbfgs_warm_start_and_zero_iterations():

@@ -51,10 +51,10 @@ def test_upwind_operator_and_adjoints(n, cfl, prec):
         assert abs(k - k_ref) <= 1
     gr, gv = empty(g.ncell, prec), empty(g.nface, prec)
     S.stfas_op_upwind_adj(ctx, to_dev(mu, prec), to_dev(rho, prec), to_dev(v, prec), gr, gv)
-    if prec == "fp64" or k == k_ref:
-        atol = TOL[prec] if prec == "fp64" else 1e-4
-        assert rel(to_np(gr), upwind.advect_up_T(g, mu, rho, v, g.h)) <= atol
-        assert rel(to_np(gv), upwind.advect_up_dv_T(g, mu, rho, v, g.h)) <= atol
+    # the adjoints follow the device's own k; where FP32 rounding moves k by
+    # one, the difference is the last term, below 1e-5 of the field
+    assert rel(to_np(gr), upwind.advect_up_T(g, mu, rho, v, g.h)) <= TOL[prec]
+    assert rel(to_np(gv), upwind.advect_up_dv_T(g, mu, rho, v, g.h)) <= TOL[prec]
     ctx.destroy()
 
 
@@ -139,7 +139,7 @@ def test_density_subproblem_upwind(prec):
     hist = S.stfas_op_ao(ctx, to_dev(rho0, prec), ks, to_dev(np.stack([keys[k] for k in ks]), prec),
                          to_dev(vt, prec), vs, rho)
     vs_ref, rho_ref, hist_ref = ao.solve(g, rho0, keys, vt, K, dt, 2, iters=2, kind="upwind")
-    tol = TOL[prec] if prec == "fp64" else 1e-3
+    tol = TOL[prec]
     assert rel(to_np(vs), vs_ref) <= tol
     assert rel(to_np(rho), rho_ref) <= tol
     assert np.allclose(hist, hist_ref, rtol=1e-9 if prec == "fp64" else 1e-4)
@@ -163,7 +163,7 @@ def test_solve_small_upwind(prec):
     st = S.stfas_solve(ctx, to_dev(rho0, prec), ks, to_dev(np.stack([keys[k] for k in ks]), prec), u)
     ref = admm.solve(admm.Problem(density="upwind", **args), rho0, keys)
     ctx.destroy()
-    tol = TOL[prec] if prec == "fp64" else 1e-3
+    tol = TOL[prec]
     assert rel(to_np(u).reshape(N, -1), ref.u) <= tol
     assert abs(st["objective"] - ref.objective) <= tol * ref.objective
 
@@ -217,7 +217,7 @@ def test_density_subproblem_upwind_mispredicted_terms(prec):
     assert k_fast[0] > k_slow[0] + 3            # the fast flow needs more terms than predicted
     hist = S.stfas_op_ao(ctx, to_dev(rho0, prec), ks, kd, to_dev(fast, prec), vs, rho)
     vs_ref, rho_ref, hist_ref = ao.solve(g, rho0, keys, fast, K, dt, 2, iters=2, kind="upwind")
-    tol = TOL[prec] if prec == "fp64" else 1e-3
+    tol = TOL[prec]
     assert rel(to_np(vs), vs_ref) <= tol
     assert rel(to_np(rho), rho_ref) <= tol
     assert np.allclose(hist, hist_ref, rtol=1e-9 if prec == "fp64" else 1e-4)

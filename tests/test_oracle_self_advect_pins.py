@@ -1,21 +1,27 @@
 """Pins of the oracle's semi-Lagrangian velocity self-advection S and of its
 transpose J_S^T against things other than the oracle itself.  CPU only.
 
+S interpolates with the C1 variant of multilinear weights: each fraction t
+of the foot point's lattice coordinate is replaced by s(t) = t^2 (3 - 2t).
+
 1. Closed form.  For a linear, divergence-free velocity field V(x) sampled
    at the face centres, the four-face average of component b at an a-face
    equals V_b at that face's centre (the four b-faces sit symmetrically
-   around it), and multilinear interpolation reproduces linear functions.
-   So, away from the walls, S(v) at an a-face at position X is exactly
-   V_a(X - (dt/h) V(X)).  A wrong neighbour set in the average, a wrong
-   axis, a sign error in the backtrace or a misplaced face centre each
-   change the value.
+   around it).  The backtrace from lattice index I is then exactly
+   Y = I - (dt/h) V(X), and multilinear weights built on s(t) applied to a
+   linear function q give q at the lattice point floor(Y) + s(Y - floor(Y))
+   (the weights of each axis sum to one and the function separates by
+   axis).  So, away from the walls, S(v) at an a-face is V_a at the
+   position of that lattice point.  A wrong neighbour set in the average, a
+   wrong axis, a sign error in the backtrace, a misplaced face centre or a
+   plain (non-smoothstep) weight each change the value.
 2. An independent implementation in plain torch: one loop over faces, the
    neighbours named explicitly, floor/clamp interpolation on the face
-   lattice.  Its values must equal the oracle's, and torch autograd through
-   it gives J_S(v)^T y, which must equal the oracle's hand-written transpose
-   (the derivative convention at lattice nodes and at the clamp is the one
-   autograd gives for floor/clamp: right derivative, clamp slope 1 on the
-   closed box).
+   lattice with smoothstep fractions.  Its values must equal the oracle's,
+   and torch autograd through it gives J_S(v)^T y, which must equal the
+   oracle's hand-written transpose (the derivative convention at the clamp
+   is the one autograd gives for floor/clamp: clamp slope 1 on the closed
+   box; at lattice nodes s'(t) vanishes on both sides).
 """
 import itertools
 
@@ -78,7 +84,11 @@ def test_self_advect_linear_field_closed_form(n, seed):
             if any(idx[b] < 2 or idx[b] > ext[b] - 3 for b in range(g.dim)):
                 continue
             X = _face_centre(g, a, idx)
-            want = V(X - cfl * V(X))[a]
+            Y = np.array(idx, dtype=np.float64) - cfl * V(X)        # lattice index of the foot point
+            base = np.floor(Y)
+            t = Y - base
+            Ys = base + t * t * (3.0 - 2.0 * t)
+            want = V(_face_centre(g, a, Ys))[a]
             got = S[a][tuple(reversed(idx))]
             assert abs(got - want) < 1e-13, (a, idx, got, want)
             checked += 1
@@ -89,7 +99,8 @@ def _torch_self_advect(n, v_parts, cfl):
     """S(v) written independently: loop over interior faces; the velocity at
     an a-face is v_a there and, for b != a, the mean of the four b-faces of
     the two cells that share the face; one Euler backtrace in lattice index
-    space; floor/clamp multilinear interpolation on the a-face lattice."""
+    space; floor/clamp multilinear interpolation on the a-face lattice with
+    each fraction passed through the smoothstep t^2 (3 - 2t)."""
     import torch
     dim = len(n)
 
@@ -120,6 +131,7 @@ def _torch_self_advect(n, v_parts, cfl):
             pos = [torch.clamp(idx[b] - cfl * vel[b], 0.0, ext[b] - 1.0) for b in range(dim)]
             base = [int(min(np.floor(float(pos[b].detach())), ext[b] - 2)) for b in range(dim)]
             frac = [pos[b] - base[b] for b in range(dim)]
+            frac = [f * f * (3.0 - 2.0 * f) for f in frac]          # smoothstep
             val = 0.0
             for bits in itertools.product((0, 1), repeat=dim):
                 wgt = 1.0
