@@ -93,6 +93,10 @@ typedef struct {
                              * analysis): > 0 makes the multiplier update of an iteration t > 1 only
                              * when the density subproblem's objective fell by at most al_tol
                              * (relative) since iteration t - 1; 0 = plain ADMM; < 0 invalid */
+    double scgs_lm;         /* Levenberg-Marquardt perturbation of K in the smoother's local matrix
+                             * (Sec. 5, convergence analysis; eq:HESS): K/r on every v block becomes
+                             * K/r + scgs_lm / dt^2 (the residual is unchanged, so is the solution);
+                             * 0 selects 1; < 0 turns it off */
 } stfas_problem;
 
 typedef struct {

@@ -15,9 +15,10 @@ Readings: v_0 is the given initial state (zero) and is not optimised; the
 defaults rescale the paper's parameter table to a unit domain (h = 1/n0,
 dt = 1/n0, K = r/dt^2, beta = 1, 2 AO iterations, eps_STFAS = 1e-5
 relative, eps_ADMM = max(rho_0)/100); the smoother is relaxed with
-omega = 0.7 (with omega = 1 the velocity subproblem diverges once the flow
-moves about 0.7 cells per step, because the smoother's local matrix leaves
-out the advection derivative).
+omega = 0.7 and its local matrix carries the Levenberg-Marquardt
+perturbation K/r + 1/dt^2 of Sec. 5 (without it the velocity subproblem
+stalls or diverges once the flow moves about a cell per step, because the
+smoother's local matrix leaves out the advection derivative).
 
 Augmented-Lagrangian fallback (Sec. 5, convergence analysis: ADMM falls
 back to a standard augmented Lagrangian method by leaving out the multiplier
@@ -58,6 +59,7 @@ class Problem:
     scgs_omega: float = 0.7
     density: str = "sl"               # density operator: "sl" or "upwind" (eq:Adv)
     al_tol: float = 0.0               # augmented-Lagrangian fallback threshold (0: plain ADMM)
+    scgs_lm: float = 1.0              # smoother's Levenberg-Marquardt perturbation times dt^2 (< 0: off)
 
     def resolved(self, rho0):
         p = Problem(**self.__dict__)
@@ -67,6 +69,8 @@ class Problem:
             p.K = p.r / (p.dt * p.dt)
         if p.metric_levels < 0:
             p.metric_levels = metric.default_levels(p.n)
+        if p.scgs_lm == 0:
+            p.scgs_lm = 1.0
         if p.eps_admm <= 0:
             p.eps_admm = float(np.max(rho0)) / 100.0
         return p
@@ -115,7 +119,7 @@ def solve(prob: Problem, rho0, keys):
     g = Grid(p.n)
     N = p.num_steps
     kr = p.K / p.r
-    H = stfas.Hierarchy(g, N, p.dt, kr, omega=p.scgs_omega)
+    H = stfas.Hierarchy(g, N, p.dt, kr, omega=p.scgs_omega, lm=max(p.scgs_lm, 0.0))
     F = g.nface
     v_all = np.zeros((N, F))          # v_i, i = 0..N-1 as seen by AO (v_0 = 0)
     lam = np.zeros((N, F))

@@ -30,11 +30,12 @@ class Level:
     advect=False replaces S by the identity (the linear-quadratic special
     case used by the brute-force checks)."""
 
-    def __init__(self, g: Grid, N, dt, K_over_r, advect=True, omega=1.0):
+    def __init__(self, g: Grid, N, dt, K_over_r, advect=True, omega=1.0, lm=0.0):
         self.g, self.N, self.dt, self.kr = g, N, dt, K_over_r
         self.mask = g.interior_mask()
         self.advect = advect
         self.omega = omega          # relaxation weight of the smoother
+        self.lm = lm                # Levenberg-Marquardt perturbation of the smoother's K/r, times dt^2
 
     def S(self, v):
         return advect.self_advect(self.g, v, self.dt, self.g.h) if self.advect else v * self.mask

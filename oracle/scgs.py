@@ -12,6 +12,16 @@ colours in lexicographic order).
 
 The correction is relaxed by the weight omega of the level (1 unless set).
 
+Levenberg-Marquardt safeguard (Sec. 5, convergence analysis: a perturbation
+of the penalty K in the Hessian eq:HESS makes the cycle the inner solver of
+a Levenberg-Marquardt method): with lm > 0 the local matrix has
+K/r + lm/dt^2 on every v block (v_N included, which has no K term).  Only
+the local matrix changes; the residual, and hence the solution the cycles
+converge to, is the unperturbed one.  With the semi-Lagrangian operator the
+local matrix leaves out the advection derivative (du_i/dv_i = -I/dt below),
+which is far from J_S once the flow moves about a cell per step; the
+perturbation keeps the smoother contracting there.
+
 Local unknown blocks, in time order k = 0..2N-1:
   k = 2i     (u_i, p_{i+1})        row F3_i (faces), F4_i (centre)
   k = 2i + 1 (v_{i+1}, pbar_{i+1}) row F1_{i+1},     F2_{i+1}
@@ -24,7 +34,7 @@ the derivative of the advection is left out of the local matrix, i.e.
 du_i/dv_i = -I/dt exactly as eq:KKTAO states; the residual stays exact):
   face rows   T_kk x_k + T_k,k-1 x_{k-1} + T_k,k+1 x_{k+1} - g pi_k
   centre row  g^T x_k
-  T_kk  = -1 (u blocks),  K/r (v_i, i<N),  0 (v_N)
+  T_kk  = -1 (u blocks),  K/r (v_i, i<N),  0 (v_N)   [+ lm/dt^2 on v blocks]
   T(u_{i-1}, v_i) = +1/dt,   T(v_i, u_i) = -1/dt   (symmetric)
   g = divergence coefficients of the cell's faces (-1/h low, +1/h high).
 """
@@ -63,8 +73,9 @@ def _cell_flat(g: Grid, idx):
     return flat
 
 
-def _tmatrix(N, dt, kr):
-    """Diagonal and the coupling T_{k,k+1} of the temporal matrix."""
+def _tmatrix(N, dt, kr, mu=0.0):
+    """Diagonal and the coupling T_{k,k+1} of the temporal matrix; mu is the
+    Levenberg-Marquardt perturbation added to K/r on every v block."""
     diag = np.zeros(2 * N)
     off = np.zeros(2 * N - 1)
     for k in range(2 * N):
@@ -72,7 +83,7 @@ def _tmatrix(N, dt, kr):
             diag[k] = -1.0
         else:
             i = (k + 1) // 2
-            diag[k] = kr if i < N else 0.0
+            diag[k] = (kr if i < N else 0.0) + mu
         if k + 1 < 2 * N:
             off[k] = (1.0 / dt) if k % 2 == 0 else (-1.0 / dt)
     return diag, off
@@ -107,7 +118,7 @@ def smooth_colour(L: Level, x, w, res, colour):
     E = np.zeros((nc, B, B))
     for s in range(2 * d):
         E[:, s, s] = inner[:, s]
-    diag, off = _tmatrix(N, L.dt, L.kr)
+    diag, off = _tmatrix(N, L.dt, L.kr, L.lm / (L.dt * L.dt))
 
     def block(k):
         A = np.zeros((nc, B, B))

@@ -27,6 +27,7 @@ class StfasProblem(ctypes.Structure):
         ("scgs_omega", c_double),
         ("density_op", c_int32),
         ("al_tol", c_double),
+        ("scgs_lm", c_double),
     ]
 
 
@@ -85,7 +86,7 @@ _SIGS = {
                               c_void_p, ctypes.POINTER(c_double)]),
     "stfas_trace_enable": (c_int32, [c_void_p, c_int32, c_int32]),
     "stfas_trace_read": (c_int32, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_double),
-                                   ctypes.POINTER(c_double)]),
+                                   ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
 }
 
 EXPORTED = tuple(_SIGS)

@@ -56,6 +56,7 @@ __global__ void k_blur_axis(Grid g, int axis, int R, const T* __restrict__ taps,
 
 // ---------------------------------------------------------------- reductions
 enum RedOp { RED_DOT = 0, RED_SUMSQ_DIFF = 1, RED_MAXABS_DIFF = 2 };
+constexpr int RED_BS = 256;     // threads per block of the reduction kernels
 
 template <typename T>
 __device__ inline double red_elem(int op, const T* x, const T* y, long e) {
@@ -67,36 +68,81 @@ __device__ inline double red_elem(int op, const T* x, const T* y, long e) {
 
 __device__ inline double red_combine(int op, double a, double b) { return op == RED_MAXABS_DIFF ? fmax(a, b) : a + b; }
 
+// Combine over a wave64 by cross-lane shuffles (after it, lane 0 holds the
+// wave's value), then over the block's waves through a few LDS words; the
+// order is fixed, so the result is deterministic.  Thread 0 of the block
+// gets the block's value.
+__device__ inline double wave_combine(int op, double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = red_combine(op, v, __shfl_down(v, off, 64));
+    return v;
+}
+
+__device__ inline double block_combine(int op, double v) {
+    __shared__ double per_wave[RED_BS / 64];
+    v = wave_combine(op, v);
+    if ((threadIdx.x & 63) == 0) per_wave[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        v = per_wave[0];
+#pragma unroll
+        for (int w = 1; w < RED_BS / 64; ++w) v = red_combine(op, v, per_wave[w]);
+    }
+    return v;
+}
+
 // Block partials of a reduction over n elements (grid-stride, fixed order).
+// Launched with RED_BS threads per block.
 template <typename T>
-__global__ void k_reduce_part(long n, int op, const T* __restrict__ x, const T* __restrict__ y,
-                              double* __restrict__ part) {
-    __shared__ double sm[256];
+__global__ void __launch_bounds__(RED_BS) k_reduce_part(long n, int op, const T* __restrict__ x,
+                                                        const T* __restrict__ y, double* __restrict__ part) {
     double acc = 0;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
         acc = red_combine(op, acc, red_elem(op, x, y, e));
-    sm[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sm[threadIdx.x] = red_combine(op, sm[threadIdx.x], sm[threadIdx.x + s]);
-        __syncthreads();
+    acc = block_combine(op, acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// Block partials of max |x| over up to four arrays at once (the four parts
+// of a KKT residual): one launch instead of one per array.
+template <typename T>
+__global__ void __launch_bounds__(RED_BS) k_maxabs4_part(long n0, const T* __restrict__ x0, long n1,
+                                                         const T* __restrict__ x1, long n2, const T* __restrict__ x2,
+                                                         long n3, const T* __restrict__ x3,
+                                                         double* __restrict__ part) {
+    const long step = (long)gridDim.x * blockDim.x, first = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0;
+    for (long e = first; e < n0; e += step) acc = fmax(acc, fabs((double)x0[e]));
+    for (long e = first; e < n1; e += step) acc = fmax(acc, fabs((double)x1[e]));
+    for (long e = first; e < n2; e += step) acc = fmax(acc, fabs((double)x2[e]));
+    for (long e = first; e < n3; e += step) acc = fmax(acc, fabs((double)x3[e]));
+    acc = block_combine(RED_MAXABS_DIFF, acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// Block partials of max |x| over the interior faces of `slices` consecutive
+// face fields (wall entries are left out, whatever they hold).
+template <typename T>
+__global__ void __launch_bounds__(RED_BS) k_maxabs_interior_part(Grid g, long slices, const T* __restrict__ x,
+                                                                 double* __restrict__ part) {
+    const long n = slices * g.nface;
+    double acc = 0;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        int a, i, j, k;
+        face_decode(g, (int)(e % g.nface), a, i, j, k);
+        if (face_interior(g, a, i, j, k)) acc = fmax(acc, fabs((double)x[e]));
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+    acc = block_combine(RED_MAXABS_DIFF, acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
 // out[slot] = (accumulate ? out[slot] op : ) combine of the partials.
-__global__ void k_reduce_final(int nparts, int op, const double* __restrict__ part, double* out, int slot,
-                               int accumulate) {
-    __shared__ double sm[256];
+__global__ void __launch_bounds__(RED_BS) k_reduce_final(int nparts, int op, const double* __restrict__ part,
+                                                         double* out, int slot, int accumulate) {
     double acc = 0;
     for (int e = threadIdx.x; e < nparts; e += blockDim.x) acc = red_combine(op, acc, part[e]);
-    sm[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sm[threadIdx.x] = red_combine(op, sm[threadIdx.x], sm[threadIdx.x + s]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[slot] = accumulate ? red_combine(op, out[slot], sm[0]) : sm[0];
+    acc = block_combine(op, acc);
+    if (threadIdx.x == 0) out[slot] = accumulate ? red_combine(op, out[slot], acc) : acc;
 }
 
 // Per-slice sums of a cell field (for mean removal).

@@ -57,7 +57,7 @@ struct Arena {
 // Resolved problem constants (defaults of stfas.h applied).
 struct Params {
     int dim, n[3], N;
-    double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol, omega, al_tol;
+    double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol, omega, al_tol, lm;
     int ao_iters, max_admm, max_vcycles, metric_levels, fixed_counts, precision, density;
 };
 
@@ -101,6 +101,8 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     o.density = p->density_op;
     if (!(p->al_tol >= 0) || !std::isfinite(p->al_tol)) return false;
     o.al_tol = p->al_tol;
+    if (std::isnan(p->scgs_lm) || std::isinf(p->scgs_lm)) return false;
+    o.lm = (p->scgs_lm < 0 ? 0.0 : (p->scgs_lm > 0 ? p->scgs_lm : 1.0)) / (o.dt * o.dt);
     const double total = (double)o.n[0] * o.n[1] * o.n[2];
     if (total > 2.0e9 / (o.dim + 1)) return false;
     return true;
@@ -198,7 +200,10 @@ struct TFactors {
     std::vector<double> diag, sub, sup, cp, inv;
 };
 
-inline TFactors temporal_factors(int N, double dt, double kr) {
+// The temporal matrix of the smoother's local system (collapsed form) and its
+// Thomas factors.  kr = K/r; mu = the Levenberg-Marquardt perturbation of K/r
+// on every v block (Sec. 5, convergence analysis).
+inline TFactors temporal_factors(int N, double dt, double kr, double mu) {
     TFactors f;
     const int M = 2 * N;
     f.diag.resize(M);
@@ -207,7 +212,7 @@ inline TFactors temporal_factors(int N, double dt, double kr) {
     f.cp.assign(M, 0.0);
     f.inv.resize(M);
     for (int k = 0; k < M; ++k) {
-        f.diag[k] = (k % 2 == 0) ? -1.0 : (((k + 1) / 2 < N) ? kr : 0.0);
+        f.diag[k] = (k % 2 == 0) ? -1.0 : (((k + 1) / 2 < N) ? kr : 0.0) + mu;
         if (k + 1 < M) f.sup[k] = (k % 2 == 0) ? 1.0 / dt : -1.0 / dt;
         if (k > 0) f.sub[k] = f.sup[k - 1];
     }
@@ -435,7 +440,8 @@ struct Tracer {
     int id = TR_NONE;
     int cap = 0, used = 0;
     long launches = 0;
-    double bytes = 0;
+    double bytes = 0;        // the method's bytes of the recorded launches
+    double impl_bytes = 0;   // every buffer the launches read or write once (with the implementation's scratch)
     std::vector<hipEvent_t> ev;
     bool on(int k) const { return id == k && used < cap; }
     void reset() {
@@ -445,11 +451,13 @@ struct Tracer {
         cap = used = 0;
         launches = 0;
         bytes = 0;
+        impl_bytes = 0;
     }
 };
 
+// impl < 0: the launch moves exactly the method's bytes.
 template <typename Launch>
-inline void traced(Tracer& tr, hipStream_t st, int kind, double bytes, Launch&& launch) {
+inline void traced(Tracer& tr, hipStream_t st, int kind, double bytes, Launch&& launch, double impl = -1) {
     if (!tr.on(kind)) {
         launch();
         return;
@@ -460,6 +468,7 @@ inline void traced(Tracer& tr, hipStream_t st, int kind, double bytes, Launch&& 
     ++tr.used;
     ++tr.launches;
     tr.bytes += bytes;
+    tr.impl_bytes += impl < 0 ? bytes : impl;
 }
 
 // Pinned host buffer for scalar readbacks, one per host thread, kept for the
@@ -511,8 +520,8 @@ public:
         tr.id = kind;
         tr.cap = cap;
     }
-    // launches, total milliseconds, algorithmic bytes of the recorded launches
-    void trace_read(long* n, double* ms, double* bytes) {
+    // launches, total milliseconds, the method's and the implementation's bytes of the recorded launches
+    void trace_read(long* n, double* ms, double* bytes, double* impl_bytes) {
         double tot = 0;
         for (int q = 0; q < tr.used; ++q) {
             HCK(hipEventSynchronize(tr.ev[2 * q + 1]));
@@ -523,6 +532,7 @@ public:
         *n = tr.launches;
         *ms = tot;
         *bytes = tr.bytes;
+        if (impl_bytes) *impl_bytes = tr.impl_bytes;
     }
 };
 
@@ -773,7 +783,7 @@ public:
         // t1a is all zero between SCGS sweeps: every sweep has an even number
         // of colours and the last colour's residual launch clears t1a again
         if (t1a) fill(t1a, (long)N * L[0].nface, (T)0);
-        TFactors f = temporal_factors(N, P.dt, P.K / P.r);
+        TFactors f = temporal_factors(N, P.dt, P.K / P.r, P.lm);
         upload(t_diag, f.diag);
         upload(t_sub, f.sub);
         upload(t_sup, f.sup);
@@ -807,9 +817,23 @@ public:
     }
     // red_out[slot] (op)= reduce(x, y) over n elements
     void reduce(int op, long n, const T* x, const T* y, int slot, bool accumulate) {
-        const int nb = (int)std::min<long>(RED_BLOCKS, std::max<long>(1, blocks_for(n, BS)));
-        k_reduce_part<T><<<nb, BS, 0, st>>>(n, op, x, y, red_part);
-        k_reduce_final<<<1, BS, 0, st>>>(nb, op, red_part, red_out, slot, accumulate ? 1 : 0);
+        const int nb = (int)std::min<long>(RED_BLOCKS, std::max<long>(1, blocks_for(n, RED_BS)));
+        k_reduce_part<T><<<nb, RED_BS, 0, st>>>(n, op, x, y, red_part);
+        k_reduce_final<<<1, RED_BS, 0, st>>>(nb, op, red_part, red_out, slot, accumulate ? 1 : 0);
+    }
+    // red_out[slot] = max |x| over the four arrays
+    void maxabs4(long n0, const T* x0, long n1, const T* x1, long n2, const T* x2, long n3, const T* x3, int slot) {
+        const long n = std::max(std::max(n0, n1), std::max(n2, n3));
+        const int nb = (int)std::min<long>(RED_BLOCKS, std::max<long>(1, blocks_for(n, RED_BS)));
+        k_maxabs4_part<T><<<nb, RED_BS, 0, st>>>(n0, x0, n1, x1, n2, x2, n3, x3, red_part);
+        k_reduce_final<<<1, RED_BS, 0, st>>>(nb, RED_MAXABS_DIFF, red_part, red_out, slot, 0);
+    }
+    // red_out[slot] = max |x| over the interior faces of `slices` level-0 face fields
+    void maxabs_interior(long slices, const T* x, int slot) {
+        const long n = slices * L[0].nface;
+        const int nb = (int)std::min<long>(RED_BLOCKS, std::max<long>(1, blocks_for(n, RED_BS)));
+        k_maxabs_interior_part<T><<<nb, RED_BS, 0, st>>>(L[0], slices, x, red_part);
+        k_reduce_final<<<1, RED_BS, 0, st>>>(nb, RED_MAXABS_DIFF, red_part, red_out, slot, 0);
     }
     void zero_slots(int n) { k_fill<double><<<1, 64, 0, st>>>(n, red_out, 0.0); }
     void readback(int n) {
@@ -959,12 +983,15 @@ public:
         // every sequence the launch reads or writes, once: v and u in (the transpose reads them at
         // every face) and t1, t1z out per face slot; w in and r1, r3 out per face-row slot (+ s1, s3
         // on coarse levels); pbar, p in and r2, r4 out per cell-row slot (+ s2, s4)
-        const double bytes = sz * (fslots * 4 + rslots * (3 + (q.s1 ? 2 : 0)) + cslots * (4 + (q.s2 ? 2 : 0)));
-        traced(tr, st, l == 0 ? TR_KKT_SPLIT : TR_NONE, bytes, [&] {
+        const double impl = sz * (fslots * 4 + rslots * (3 + (q.s1 ? 2 : 0)) + cslots * (4 + (q.s2 ? 2 : 0)));
+        // the method's bytes: (v, u, pbar, p, w, res -> r) once per spacetime cell whose rows the launch
+        // computes, 2d + 2 + d + 2 (2d + 2) words: 20 words (80 B FP32) in 2D, 27 (108 B) in 3D
+        const double method = sz * (D == 2 ? 20.0 : 27.0) * cslots;
+        traced(tr, st, l == 0 ? TR_KKT_SPLIT : TR_NONE, method, [&] {
             k_kkt_split<T, D><<<(unsigned)blocks, 256, 0, st>>>(g, N, (T)P.dt, (T)(P.K / P.r), cfl(l), (T)-1, ks,
                                                                q.v, q.pb, q.u, q.p, q.w, q.s1, q.s2, q.s3, q.s4,
                                                                q.r1, q.r2, q.r3, q.r4, t1, t1z);
-        });
+        }, impl);
     }
     void kkt_level(int l, bool fas_rhs) {
         Lev& q = lev[l];
@@ -1093,10 +1120,7 @@ public:
         Lev& q = lev[0];
         kkt_level(0, false);
         const long F = L[0].nface, C = L[0].ncell;
-        reduce(RED_MAXABS_DIFF, N * F, q.r1, nullptr, 0, false);
-        reduce(RED_MAXABS_DIFF, N * C, q.r2, nullptr, 0, true);
-        reduce(RED_MAXABS_DIFF, N * F, q.r3, nullptr, 0, true);
-        reduce(RED_MAXABS_DIFF, N * C, q.r4, nullptr, 0, true);
+        maxabs4(N * F, q.r1, N * C, q.r2, N * F, q.r3, N * C, q.r4, 0);
         readback(1);
         return host_out[0];
     }
@@ -1105,9 +1129,10 @@ public:
     int nso(double* hist, double* last) {
         for (size_t l = 0; l + 1 < L.size(); ++l) restrict_faces((int)l, lev[l].w, lev[l + 1].w);
         const long F = L[0].nface;
+        // |f(0)|_inf: at the zero state only F1 = -(K/r) w_i (i = 1..N-1, interior faces) is nonzero
         double f0 = 0;
         if (N > 1) {
-            reduce(RED_MAXABS_DIFF, (N - 1) * F, lev[0].w + F, nullptr, 0, false);
+            maxabs_interior(N - 1, lev[0].w + F, 0);
             readback(1);
             f0 = (P.K / P.r) * host_out[0];
         }

@@ -18,7 +18,7 @@ DENSITY_OPS = {"sl": 0, "upwind": 1}
 
 def make_problem(n, num_steps, r, dt=0.0, K=0.0, beta=0.0, ao_iters=0, eps_stfas=0.0, eps_admm=0.0, max_admm=0,
                  max_vcycles=0, metric_levels=-1, poisson_rtol=0.0, fixed_counts=False, precision="fp64",
-                 scgs_omega=0.0, density="sl", al_tol=0.0):
+                 scgs_omega=0.0, density="sl", al_tol=0.0, scgs_lm=0.0):
     """stfas_problem with the C defaults for every field left at 0 (-1 for metric_levels)."""
     p = StfasProblem()
     n = tuple(int(x) for x in n)
@@ -36,6 +36,7 @@ def make_problem(n, num_steps, r, dt=0.0, K=0.0, beta=0.0, ao_iters=0, eps_stfas
     p.scgs_omega = float(scgs_omega)
     p.density_op = DENSITY_OPS[density] if isinstance(density, str) else int(density)
     p.al_tol = float(al_tol)
+    p.scgs_lm = float(scgs_lm)
     return p
 
 
@@ -354,8 +355,8 @@ def stfas_trace_enable(ctx, kernel, max_launches=4096):
 
 
 def stfas_trace_read(ctx):
-    """(launches, total_ms, algorithmic_bytes) of the traced kernel family."""
-    n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
-    check(_lib.load().stfas_trace_read(ctx.handle, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)),
-          "stfas_trace_read")
-    return n.value, ms.value, b.value
+    """(launches, total_ms, algorithmic_bytes, implementation_bytes) of the traced kernel family."""
+    n, ms, b, ib = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    check(_lib.load().stfas_trace_read(ctx.handle, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b),
+                                       ctypes.byref(ib)), "stfas_trace_read")
+    return n.value, ms.value, b.value, ib.value

@@ -20,6 +20,7 @@ def _ctx(n, N, prec, dt=None, K=None, r=1e-2, **kw):
     dt = 0.7 * g.h if dt is None else dt
     K = 3.0 * r / dt ** 2 if K is None else K
     kw.setdefault("scgs_omega", 1.0)
+    kw.setdefault("scgs_lm", -1.0)          # the oracle Level's default: no perturbation
     prob = S.make_problem(n, N, r, dt=dt, K=K, precision=prec, **kw)
     return S, S.stfas_create(prob), g, dt, K
 
@@ -208,16 +209,18 @@ def test_kkt_residual_all_levels(n, N, prec):
     ctx.destroy()
 
 
-@pytest.mark.parametrize("omega", [1.0, 0.7])
+@pytest.mark.parametrize("omega,lm", [(1.0, -1.0), (0.7, -1.0), (0.7, 1.0), (1.0, 2.5)])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,N", CASES)
-def test_scgs_sweep(n, N, prec, omega):
-    S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=omega)
+def test_scgs_sweep(n, N, prec, omega, lm):
+    """One SCGS sweep per level, with and without the Levenberg-Marquardt
+    perturbation of the local matrix."""
+    S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=omega, scgs_lm=lm)
     kr = K / 1e-2
     rng = np.random.default_rng(16)
     for level in (0, ctx.num_levels() - 1):
         gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
-        L = kkt.Level(gl, N, dt, kr, omega=omega)
+        L = kkt.Level(gl, N, dt, kr, omega=omega, lm=max(lm, 0.0))
         x = _state(gl, N, rng, 0.3, prec)
         w = _q(_faces(gl, rng, N), prec)
         res = _state(gl, N, rng, 1.0, prec) if level > 0 else None
@@ -259,11 +262,12 @@ def test_scgs_sweep_benchmark_shapes(n, N, prec):
     """Colours of at least 4096 cells take the row layout of the colour pass
     (chunks across the waves of a workgroup, chunk maps joined in LDS):
     128x128 x 40 is the shape the benchmark times (16 chunks of 6 blocks in
-    FP32), 128x128 x 20 and 32^3 x 10 reach it in FP64 and in 3D."""
-    S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=0.7)
+    FP32), 128x128 x 20 and 32^3 x 10 reach it in FP64 and in 3D; with the
+    solver's default smoother (omega 0.7, Levenberg-Marquardt perturbation on)."""
+    S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=0.7, scgs_lm=1.0)
     kr = K / 1e-2
     rng = np.random.default_rng(19)
-    L = kkt.Level(g, N, dt, kr, omega=0.7)
+    L = kkt.Level(g, N, dt, kr, omega=0.7, lm=1.0)
     x = _state(g, N, rng, 0.3, prec)
     w = _q(_faces(g, rng, N), prec)
     xd = _dev_state(x, prec)

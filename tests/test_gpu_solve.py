@@ -31,7 +31,7 @@ def test_nso_vcycles(n, N, prec):
     xd = tuple(to_dev(a, prec) for a in x)
     flag(f"nso n={n} N={N} {prec}")
     nv, hist = S.stfas_op_nso(ctx, xd, to_dev(w, prec))
-    H = stfas.Hierarchy(g, N, dt, K / r, omega=0.7)
+    H = stfas.Hierarchy(g, N, dt, K / r, omega=0.7, lm=1.0)
     nv_ref, hist_ref = stfas.nso(H, x, w, max_vcycles=3, fixed_counts=True)
     assert nv == nv_ref == 3
     for k in range(4):
