@@ -84,7 +84,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
-    nlaunch, tms, tbytes = S.stfas_trace_read(ctx)
+    nlaunch, tms, tbytes, _impl = S.stfas_trace_read(ctx)
     S.stfas_trace_enable(ctx, 0, 0)
     vcycles = sum(s["vcycles"] for s in stats) / len(stats)
     cells = n[0] * n[1]

@@ -127,9 +127,14 @@ stfas_status stfas_op_ao(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
  * 10 the one-launch residual that precedes each fused colour pass (face
  * rows, cell rows and the velocity-advection transpose side by side).
  * stfas_trace_read synchronises and returns the recorded launch count,
- * their summed duration in milliseconds and their algorithmic bytes. */
+ * their summed duration in milliseconds, their algorithmic bytes (for
+ * family 10: the method's bytes of the rows the launch computes, 80 B per
+ * spacetime cell in 2D and 108 B in 3D in FP32, twice that in FP64) and,
+ * if impl_bytes is not NULL, the bytes of every buffer the launches read or
+ * write once, the implementation's scratch included. */
 stfas_status stfas_trace_enable(stfas_ctx* ctx, int32_t kernel, int32_t max_launches);
-stfas_status stfas_trace_read(stfas_ctx* ctx, int64_t* launches, double* total_ms, double* bytes);
+stfas_status stfas_trace_read(stfas_ctx* ctx, int64_t* launches, double* total_ms, double* bytes,
+                              double* impl_bytes);
 
 #ifdef __cplusplus
 }

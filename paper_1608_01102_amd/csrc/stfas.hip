@@ -517,11 +517,12 @@ stfas_status stfas_trace_enable(stfas_ctx* ctx, int32_t kernel, int32_t max_laun
     });
 }
 
-stfas_status stfas_trace_read(stfas_ctx* ctx, int64_t* launches, double* total_ms, double* bytes) {
+stfas_status stfas_trace_read(stfas_ctx* ctx, int64_t* launches, double* total_ms, double* bytes,
+                              double* impl_bytes) {
     if (!ctx || !launches || !total_ms || !bytes) return STFAS_E_INVALID;
     return guard([&]() -> stfas_status {
         long n = 0;
-        ctx->s->trace_read(&n, total_ms, bytes);
+        ctx->s->trace_read(&n, total_ms, bytes, impl_bytes);
         *launches = n;
         return STFAS_OK;
     });
