@@ -49,16 +49,24 @@ def zeros_state(L: Level):
     return [np.zeros((N, g.nface)), np.zeros((N, g.ncell)), np.zeros((N, g.nface)), np.zeros((N, g.ncell))]
 
 
-def residual_f(L: Level, x, w):
+def transpose_term(L: Level, x):
+    """J_S(v_i)^T u_i / dt for i = 1..N-1 (slots 0..N-2), the non-local part of
+    F1; None when N = 1."""
+    v, u = x[0], x[2]
+    return L.JST(v[:L.N - 1], u[1:L.N]) / L.dt if L.N > 1 else None
+
+
+def residual_f(L: Level, x, w, jst=None):
     """f(x) for the state x = [v, pbar, u, p] and targets w (slot i = w_i).
     The N time slices are independent given x, so they are evaluated as one
-    batch."""
+    batch.  jst, if given, replaces the transpose term of F1 (the smoother
+    holds it over a sweep)."""
     g, N, dt, kr, h = L.g, L.N, L.dt, L.kr, L.g.h
     v, pb, u, p = x
     # F1_i, i = j + 1:  u_{i-1}/dt + G pbar_i  [+ (K/r)(v_i - w_i) - J_S(v_i)^T u_i / dt  if i < N]
     F1 = u / dt + grad(g, pb, h)
     if N > 1:
-        F1[:N - 1] += kr * (v[:N - 1] - w[1:N]) - L.JST(v[:N - 1], u[1:N]) / dt
+        F1[:N - 1] += kr * (v[:N - 1] - w[1:N]) - (transpose_term(L, x) if jst is None else jst)
     F1 *= L.mask
     F2 = div(g, v, h)
     # F3_i, i = j:  (v_{i+1} - S(v_i))/dt - u_i + G p_{i+1},  S(v_0) = 0
@@ -70,9 +78,9 @@ def residual_f(L: Level, x, w):
     return [F1, F2, F3, F4]
 
 
-def residual(L: Level, x, w, res):
+def residual(L: Level, x, w, res, jst=None):
     """r = res - f(x)."""
-    f = residual_f(L, x, w)
+    f = residual_f(L, x, w, jst)
     return [res[k] - f[k] for k in range(4)]
 
 

@@ -152,25 +152,13 @@ __global__ void k_self_advect(Grid g, T cfl, T dt, const T* __restrict__ v, cons
     out[f] = s;
 }
 
-// Is a-face (ci, cj, ck) a face of a cell of the colour cpar (bits 0..2: the
-// parities of the colour's cell coordinates)?  cpar < 0: every face is.
-template <int D>
-__device__ inline bool colour_node(int cpar, int a, int ci, int cj, int ck) {
-    if (cpar < 0) return true;
-    const int x[3] = {ci, cj, ck};
-#pragma unroll
-    for (int d = 0; d < D; ++d)
-        if (d != a && (x[d] & 1) != ((cpar >> d) & 1)) return false;
-    return true;
-}
-
 // J_S(v)^T y for one source, a-face (i, j, k) of one slice, straight into
 // out with global atomics: the same contributions as the tiled kernel below,
 // without its LDS window and barriers.  Used on small levels, where a launch
 // is a chain of dependent memory steps and the atomics are few.
 template <typename T, int D>
 __device__ inline void self_advect_T_source(const Grid& g, T cfl, const T* __restrict__ v, const T* __restrict__ y,
-                                            T scale, T* out, int a, int i, int j, int k, int cpar = -1) {
+                                            T scale, T* out, int a, int i, int j, int k) {
     if (!face_interior(g, a, i, j, k)) return;
     const int f = face_index(g, a, i, j, k);
     const T yv = y[f] * scale;
@@ -194,7 +182,6 @@ __device__ inline void self_advect_T_source(const Grid& g, T cfl, const T* __res
         const int ci = c0[0] + (q & 1), cj = c0[1] + ((q >> 1) & 1), ck = D == 3 ? c0[2] + ((q >> 2) & 1) : 0;
         const int ca = a == 0 ? ci : (a == 1 ? cj : ck);
         if (ca == 0 || ca == g.n[a]) continue;          // wall node of the a-lattice
-        if (!colour_node<D>(cpar, a, ci, cj, ck)) continue;
         atomic_add(out + face_index(g, a, ci, cj, ck), w);
     }
 #pragma unroll
@@ -202,7 +189,7 @@ __device__ inline void self_advect_T_source(const Grid& g, T cfl, const T* __res
         const T gb = yv * (-cfl) * gr[b];
         if (gb == (T)0) continue;
         if (b == a) {
-            if (colour_node<D>(cpar, a, i, j, k)) atomic_add(out + f, gb);
+            atomic_add(out + f, gb);
             continue;
         }
         // a quarter to each of the four b-faces averaged at I (walls dropped)
@@ -211,14 +198,12 @@ __device__ inline void self_advect_T_source(const Grid& g, T cfl, const T* __res
         const int db0 = (b == 0), db1 = (b == 1), db2 = (b == 2);
         const int bi = b == 0 ? i : (b == 1 ? j : k);
         if (bi != 0) {
-            if (colour_node<D>(cpar, b, ia, ja, ka)) atomic_add(out + face_index(g, b, ia, ja, ka), qv);
-            if (colour_node<D>(cpar, b, i, j, k)) atomic_add(out + face_index(g, b, i, j, k), qv);
+            atomic_add(out + face_index(g, b, ia, ja, ka), qv);
+            atomic_add(out + face_index(g, b, i, j, k), qv);
         }
         if (bi + 1 != g.n[b]) {
-            if (colour_node<D>(cpar, b, ia + db0, ja + db1, ka + db2))
-                atomic_add(out + face_index(g, b, ia + db0, ja + db1, ka + db2), qv);
-            if (colour_node<D>(cpar, b, i + db0, j + db1, k + db2))
-                atomic_add(out + face_index(g, b, i + db0, j + db1, k + db2), qv);
+            atomic_add(out + face_index(g, b, ia + db0, ja + db1, ka + db2), qv);
+            atomic_add(out + face_index(g, b, i + db0, j + db1, k + db2), qv);
         }
     }
 }
@@ -346,7 +331,7 @@ inline void launch_advect_T(const Grid& g, T cfl, const T* mu, const T* v, T* ou
 
 template <typename T, int D>
 __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restrict__ v, const T* __restrict__ y,
-                                          T scale, T* out, long vs, int tile, int slice, int a, int cpar = -1) {
+                                          T scale, T* out, long vs, int tile, int slice, int a) {
     using TS = TileShape<D>;
     constexpr int H = TS::H;
     constexpr int WX = TS::X + 2 * H, WY = TS::Y + 2 * H, WZ = (D == 3) ? TS::Z + 2 * H : 1;
@@ -442,7 +427,6 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
             const int ci = c0[0] + e;
             const int ca = a == 0 ? ci : (a == 1 ? cj : ck);
             if (ca == 0 || ca == g.n[a]) continue;          // wall node of the a-lattice
-            if (!colour_node<D>(cpar, a, ci, cj, ck)) continue; // not read by the colour pass
             const int wx = ci - ox, wy = cj - oy, wz = ck - oz;
             if (wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
                 atomicAdd(&win[(wz * WY + wy) * WX + wx], (unsigned long long)llrint((double)w * fx));
@@ -462,7 +446,6 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
     // flush the a-window: weights plus the foot-point term of the source at the node
     for (int e = threadIdx.x; e < WN; e += blockDim.x) {
         const int ci = ox + e % WX, cj = oy + (e / WX) % WY, ck = oz + e / (WX * WY);
-        if (!colour_node<D>(cpar, a, ci, cj, ck)) continue;
         T val = (T)((double)(long long)win[e] * ifx) + src(a, ci, cj, ck);
         if (val == (T)0) continue;
         if (ci < 0 || cj < 0 || ck < 0 || ci >= ex || cj >= ey || (D == 3 && ck >= ez)) continue;
@@ -478,7 +461,6 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
         for (int e = threadIdx.x; e < BN; e += blockDim.x) {
             const int ci = tx0 - 1 + e % BX, cj = ty0 - 1 + (e / BX) % BY, ck = (D == 3) ? tz0 - 1 + e / (BX * BY) : 0;
             if (ci < 0 || cj < 0 || ck < 0 || ci >= bx || cj >= by || (D == 3 && ck >= bz)) continue;
-            if (!colour_node<D>(cpar, b, ci, cj, ck)) continue;
             const int Jb = b == 0 ? ci : (b == 1 ? cj : ck);
             T s = 0;
             if (Jb != 0) s += src(b, ci, cj, ck) + src(b, ci + da0, cj + da1, ck + da2);

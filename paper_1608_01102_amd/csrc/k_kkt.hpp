@@ -79,17 +79,15 @@ __device__ inline void kkt_cell(const Grid& g, T sgn, const T* __restrict__ v, c
     out4[e] = (res4 ? res4[e] : (T)0) + sgn * du * ih;
 }
 
-// The residual of one level in one launch, for the SCGS colour passes:
-// blocks [0, nbf N) face rows, then [.., + nbc N) cell rows, then the tiles
-// of the velocity-advection transpose (slices 0..N-2, d axes), which add
-// their J_S^T term into t1 (zero on entry) instead of F1, then blocks that
-// clear t1z (the other t1 buffer, for the next pass).  All four parts read
-// only the state, so they run side by side; the SCGS pass reads F1 + t1.
-// With `rows` set the face and cell rows are those of one colour only: the
-// faces of its cells and the cells themselves, all that its pass reads (the
-// rows elsewhere are computed again before the pass that reads them).  The
-// transpose then still runs every source (any of them can land on a face of
-// the colour) but, in 3D, adds into t1 only at the colour's faces.
+// The split residual of one level: blocks [0, nbf N) face rows, then
+// [.., + nbc N) cell rows, then the tiles of the velocity-advection transpose
+// (slices 0..N-2, d axes), which add their J_S^T term into t1 (zero on entry)
+// instead of F1, then blocks that clear t1z.  All parts read only the state,
+// so they run side by side; a launch uses any subset of them (nbf, nbc,
+// ntile, nbz zero for the parts it leaves out).  An SCGS sweep launches the
+// transpose (with the clear of the next sweep's t1) once and then, per colour,
+// the rows of that colour (`rows` set: the faces of its cells and the cells
+// themselves, all that its pass reads); the pass reads F1 + t1.
 struct KktSplit {
     int nbf, nbc, ntile, nbz;
     int direct;     // 1: the transpose part runs one thread per source (ntile = blocks per slice)
@@ -148,10 +146,6 @@ __global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T 
     }
     b -= bc;
     if (b < bt) {
-        // with colour rows in 3D, J_S^T only where the colour pass reads t1: its faces (a quarter of
-        // them; in 2D, where half would go, the tiles are bound by instruction issue and the extra
-        // tests cost more than the skipped flush, so there every face is written)
-        const int cpar = (D == 3 && ks.rows) ? (ks.par[0] | (ks.par[1] << 1) | (ks.par[2] << 2)) : -1;
         const int slice = (int)((b / ks.ntile) % (N - 1));
         if (ks.direct) {
             // one thread per (slice, face); y = u_{j+1} (the u slots shifted by one), scale -sgn/dt
@@ -160,14 +154,14 @@ __global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T 
                 int a, i, j, k;
                 face_decode(g, f, a, i, j, k);
                 self_advect_T_source<T, D>(g, cfl, v + (long)slice * g.nface, u + (long)(slice + 1) * g.nface,
-                                           -sgn / dt, t1 + (long)slice * g.nface, a, i, j, k, cpar);
+                                           -sgn / dt, t1 + (long)slice * g.nface, a, i, j, k);
             }
             return;
         }
         // tile, slice, axis; y = u_{j+1} (the u slots shifted by one), scale -sgn/dt
         const int tile = (int)(b % ks.ntile);
         const int a = (int)(b / ((long)ks.ntile * (N - 1)));
-        self_advect_T_tile<T, D>(g, cfl, v, u + g.nface, -sgn / dt, t1, g.nface, tile, slice, a, cpar);
+        self_advect_T_tile<T, D>(g, cfl, v, u + g.nface, -sgn / dt, t1, g.nface, tile, slice, a);
         return;
     }
     b -= bt;

@@ -648,6 +648,7 @@ public:
     std::vector<Lev> lev;
     T* scgs_scratch = nullptr;   // two-kernel SCGS path only (horizons too long for the fused kernel)
     T *t1a = nullptr, *t1b = nullptr;   // J_S^T part of F1 for the SCGS colour passes (any level)
+    T *t1_zero = nullptr, *t1_used = nullptr;   // t1a / t1b: the one that is all zero, the other
     T *t_diag, *t_sub, *t_sup, *t_cp, *t_inv;
     Poisson<T, D> pois;      // projection, batched over up to N slices
     // density subproblem
@@ -711,17 +712,17 @@ public:
             }
             q.w = A.take<T>(N * F);
         }
-        // SCGS scratch: the largest colour of level 0, 2N blocks, 2d faces per cell
+        // the J_S^T part of F1 held over a sweep, and its cleared successor (any level)
+        t1a = A.take<T>(N * F0);
+        t1b = A.take<T>(N * F0);
+        // SCGS scratch of long horizons: the largest colour of level 0, 2N blocks, 2d faces per cell
         int Gs, Ls, CHs;
         if (colour_shape<T, D>(2 * N, 1, Gs, Ls, CHs)) {
             scgs_scratch = nullptr;
-            t1a = A.take<T>(N * F0);
-            t1b = A.take<T>(N * F0);
         } else {
             long maxcol = 0;
             for (int c = 0; c < (1 << D); ++c) maxcol = std::max<long>(maxcol, colour_set(L[0], c).total);
             scgs_scratch = A.take<T>((size_t)maxcol * 2 * D * 2 * N);
-            t1a = t1b = nullptr;
         }
         t_diag = A.take<T>(2 * N);
         t_sub = A.take<T>(2 * N);
@@ -780,9 +781,11 @@ public:
 
     void init_tables() override {
         host_out = thread_pinned();
-        // t1a is all zero between SCGS sweeps: every sweep has an even number
-        // of colours and the last colour's residual launch clears t1a again
-        if (t1a) fill(t1a, (long)N * L[0].nface, (T)0);
+        // t1_zero is all zero between SCGS sweeps: each sweep's transpose
+        // launch fills the other buffer's successor (see sweep)
+        fill(t1a, (long)N * L[0].nface, (T)0);
+        t1_zero = t1a;
+        t1_used = t1b;
         TFactors f = temporal_factors(N, P.dt, P.K / P.r, P.lm);
         upload(t_diag, f.diag);
         upload(t_sub, f.sub);
@@ -933,57 +936,94 @@ public:
                    [&] { self_advect_T(l, v, u + g.nface, (T)(-sgn / dt), o1, N - 1); });
         }
     }
-    // The residual r = res - f(x) of level l for an SCGS colour pass in one
-    // launch: F1 without its J_S^T term in r1, that term in t1 (zero on
-    // entry), and t1z cleared for the next pass.
-    // colour >= 0: the face and cell rows of that colour only (see KktSplit)
-    void kkt_split(int l, T* t1, T* t1z, int colour = -1) {
+    // The two launches of a sweep's residual (r = res - f(x) on level l), both
+    // with the split residual kernel:
+    //  kkt_transpose: the J_S^T u / dt part of F1 from the state at the start of
+    //    the sweep into t1 (zero on entry; all faces), with t1z cleared for the
+    //    next sweep;
+    //  kkt_rows: per colour, the face and cell rows of that colour without that
+    //    part (r1 .. r4), from the current state.
+    void kkt_transpose(int l, T* t1, T* t1z) {
         const Grid& g = L[l];
         Lev& q = lev[l];
         using TS = TileShape<D>;
         KktSplit ks{};
-        long nfr = g.nface, ncr = g.ncell;     // face and cell rows per slice
-        if (colour >= 0) {
-            const ColourSet cs = colour_set(g, colour);
-            ks.rows = 1;
-            for (int a = 0; a < 3; ++a) {
-                ks.par[a] = cs.p[a];
-                ks.cnt[a] = cs.cnt[a];
-            }
-            ks.nfc = 0;
-            for (int a = 0; a < D; ++a) {
-                long m = g.n[a] + 1;
-                for (int b2 = 0; b2 < 3; ++b2)
-                    if (b2 != a) m *= cs.cnt[b2];
-                ks.nfc += (int)m;
-            }
-            nfr = ks.nfc;
-            ncr = cs.total;
-        }
-        ks.nbf = blocks_for(nfr, 256);
-        ks.nbc = blocks_for(ncr, 256);
         // small levels: the transpose without tiles (no LDS window, no barriers), since there a launch is
         // a chain of dependent memory steps and its few atomics are cheap
         ks.direct = (long)N * g.nface <= DIRECT_T_SLOTS ? 1 : 0;
         ks.ntile = 0;
-        if (ks.direct) {
-            ks.ntile = blocks_for(g.nface, 256);
-        } else {
-            for (int a = 0; a < D; ++a) {
-                const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
-                const int t = ((ex + TS::X - 1) / TS::X) * ((ey + TS::Y - 1) / TS::Y) *
-                              (D == 3 ? (ez + TS::Z - 1) / TS::Z : 1);
-                ks.ntile = std::max(ks.ntile, t);
+        if (N > 1) {
+            if (ks.direct) {
+                ks.ntile = blocks_for(g.nface, 256);
+            } else {
+                for (int a = 0; a < D; ++a) {
+                    const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
+                    const int t = ((ex + TS::X - 1) / TS::X) * ((ey + TS::Y - 1) / TS::Y) *
+                                  (D == 3 ? (ez + TS::Z - 1) / TS::Z : 1);
+                    ks.ntile = std::max(ks.ntile, t);
+                }
             }
         }
         ks.nbz = std::min(blocks_for((long)N * g.nface, 256), 2048);
-        const long blocks = (long)(ks.nbf + ks.nbc) * N + (long)ks.ntile * (N - 1) * (ks.direct ? 1 : D) + ks.nbz;
+        const long blocks = (long)ks.ntile * std::max(N - 1, 0) * (ks.direct ? 1 : D) + ks.nbz;
         const double sz = sizeof(T);
-        const double fslots = (double)g.nface * N, rslots = (double)nfr * N, cslots = (double)ncr * N;
-        // every sequence the launch reads or writes, once: v and u in (the transpose reads them at
-        // every face) and t1, t1z out per face slot; w in and r1, r3 out per face-row slot (+ s1, s3
-        // on coarse levels); pbar, p in and r2, r4 out per cell-row slot (+ s2, s4)
-        const double impl = sz * (fslots * 4 + rslots * (3 + (q.s1 ? 2 : 0)) + cslots * (4 + (q.s2 ? 2 : 0)));
+        // the method's bytes (v, y -> J_S^T y): 3d words per spacetime cell (24 B in 2D, 36 B in 3D, FP32);
+        // the launch also clears t1z
+        const double method = sz * 3.0 * D * (double)g.ncell * std::max(N - 1, 0);
+        const double impl = sz * ((double)g.nface * std::max(N - 1, 0) * 3 + (double)g.nface * N);
+        traced(tr, st, l == 0 ? TR_SELF_ADVECT_T : TR_NONE, method, [&] {
+            k_kkt_split<T, D><<<(unsigned)blocks, 256, 0, st>>>(g, N, (T)P.dt, (T)(P.K / P.r), cfl(l), (T)-1, ks,
+                                                               q.v, q.pb, q.u, q.p, q.w, q.s1, q.s2, q.s3, q.s4,
+                                                               q.r1, q.r2, q.r3, q.r4, t1, t1z);
+        }, impl);
+    }
+    // t1 != nullptr: the same launch also computes the J_S^T part (every
+    // face, into t1, zero on entry) and clears t1z: one launch per colour
+    // with the transpose refreshed for that colour.
+    void kkt_rows(int l, int colour, T* t1 = nullptr, T* t1z = nullptr) {
+        const Grid& g = L[l];
+        Lev& q = lev[l];
+        using TS = TileShape<D>;
+        KktSplit ks{};
+        const ColourSet cs = colour_set(g, colour);
+        ks.rows = 1;
+        for (int a = 0; a < 3; ++a) {
+            ks.par[a] = cs.p[a];
+            ks.cnt[a] = cs.cnt[a];
+        }
+        ks.nfc = 0;
+        for (int a = 0; a < D; ++a) {
+            long m = g.n[a] + 1;
+            for (int b2 = 0; b2 < 3; ++b2)
+                if (b2 != a) m *= cs.cnt[b2];
+            ks.nfc += (int)m;
+        }
+        const long nfr = ks.nfc, ncr = cs.total;     // face and cell rows per slice
+        ks.nbf = blocks_for(nfr, 256);
+        ks.nbc = blocks_for(ncr, 256);
+        if (t1 && N > 1) {
+            ks.direct = (long)N * g.nface <= DIRECT_T_SLOTS ? 1 : 0;
+            if (ks.direct) {
+                ks.ntile = blocks_for(g.nface, 256);
+            } else {
+                for (int a = 0; a < D; ++a) {
+                    const int ex = face_ext(g, a, 0), ey = face_ext(g, a, 1), ez = face_ext(g, a, 2);
+                    const int t = ((ex + TS::X - 1) / TS::X) * ((ey + TS::Y - 1) / TS::Y) *
+                                  (D == 3 ? (ez + TS::Z - 1) / TS::Z : 1);
+                    ks.ntile = std::max(ks.ntile, t);
+                }
+            }
+        }
+        if (t1z) ks.nbz = std::min(blocks_for((long)N * g.nface, 256), 2048);
+        const long blocks = (long)(ks.nbf + ks.nbc) * N + (long)ks.ntile * std::max(N - 1, 0) * (ks.direct ? 1 : D) +
+                            ks.nbz;
+        const double sz = sizeof(T);
+        const double rslots = (double)nfr * N, cslots = (double)ncr * N;
+        // every sequence the launch reads or writes, once: v, u, w in and r1, r3 out per face-row slot
+        // (+ s1, s3 on coarse levels; the S gather reads v around each face); pbar, p in and r2, r4
+        // out per cell-row slot (+ s2, s4); with the transpose, v, u in and t1, t1z out per face slot
+        const double impl = sz * (rslots * (5 + (q.s1 ? 2 : 0)) + cslots * (4 + (q.s2 ? 2 : 0)) +
+                                  (t1 ? (double)g.nface * N * 4 : 0.0));
         // the method's bytes: (v, u, pbar, p, w, res -> r) once per spacetime cell whose rows the launch
         // computes, 2d + 2 + d + 2 (2d + 2) words: 20 words (80 B FP32) in 2D, 27 (108 B) in 3D
         const double method = sz * (D == 2 ? 20.0 : 27.0) * cslots;
@@ -1018,32 +1058,44 @@ public:
         return tot;
     }
 
+    // One SCGS sweep on level l.  3D: the J_S^T part of F1 once from the state
+    // at the sweep's start, held for every colour, then per colour its rows
+    // and its local solves.  2D: per colour, its rows and the J_S^T part from
+    // the current state in one launch, then its local solves.
     void sweep(int l) {
         const Grid& g = L[l];
         Lev& q = lev[l];
-        T* t1c = t1a;     // zero on entry (see init_tables)
-        T* t1n = t1b;
+        T* t1 = nullptr;
+        if (D == 3) {
+            t1 = t1_zero;
+            kkt_transpose(l, t1, t1_used);          // t1_used is cleared for the next sweep
+            std::swap(t1_zero, t1_used);
+        }
         for (int colour = 0; colour < (1 << D); ++colour) {
             const ColourSet cs = colour_set(g, colour);
             const int nf = cs.total * 2 * D;
             const double inner = (double)colour_inner_faces(g, colour);
             const double sz = sizeof(T), M2 = 2.0 * N;
             int G = 1, Lc = 0, CH = 0;
-            if (t1c && colour_shape<T, D>(2 * N, cs.total, G, Lc, CH)) {
-                // two launches per colour: the residual (faces, cells and the J_S^T term side by side),
-                // then one kernel that reads r1 + t1, r2..r4 once and updates u/v and p/pbar
-                kkt_split(l, t1c, t1n, colour);
+            if (D == 3) {
+                kkt_rows(l, colour);
+            } else {
+                t1 = t1_zero;
+                kkt_rows(l, colour, t1, t1_used);   // t1_used is cleared for the next colour
+                std::swap(t1_zero, t1_used);
+            }
+            if (colour_shape<T, D>(2 * N, cs.total, G, Lc, CH)) {
+                // one kernel reads r1 + t1, r2..r4 once and updates u/v and p/pbar;
                 // per block pair: r1, t1, r3 read, u and v read + written at each interior face;
                 // per block: the divergence residual read, p or pbar read + written at each cell
                 traced(tr, st, l == 0 ? TR_SCGS_COLOUR : TR_NONE, sz * M2 * (inner * 3.5 + cs.total * 3), [&] {
-                    launch_scgs_colour<T, D>(G, Lc, CH, g, N, cs, q.r1, t1c, q.r2, q.r3, q.r4, q.v, q.pb, q.u,
+                    launch_scgs_colour<T, D>(G, Lc, CH, g, N, cs, q.r1, t1, q.r2, q.r3, q.r4, q.v, q.pb, q.u,
                                              q.p, t_diag, t_sub, t_sup, t_cp, t_inv, (T)P.omega, st);
                 });
-                std::swap(t1c, t1n);
                 continue;
             }
-            kkt_level(l, false);
-            // long horizons: project: read r1/r3 at the colour's faces, write (P r)
+            // long horizons: r1 += t1, then project: read r1/r3 at the colour's faces, write (P r)
+            axpby((long)N * g.nface, (T)1, q.r1, (T)1, t1, q.r1);
             traced(tr, st, l == 0 ? TR_SCGS_PROJECT : TR_NONE, sz * M2 * inner * 2, [&] {
                 k_scgs_project<T, D><<<blocks_for((long)nf * 2 * N, BS), BS, 0, st>>>(g, N, cs, q.r1, q.r3,
                                                                                       scgs_scratch);

@@ -216,12 +216,15 @@ def _stfas_expectations(n0, n1, n2, N, C, F):
     Fc = 3 * (n0 // 2) * (n0 // 2) * (n0 // 2 + 1)
     full = (nb(F) + nb(C)) * N * 256
     tiles = (-(-(n0 + 1) // 8)) * (-(-n1 // 8)) * (-(-n2 // 4))
-    colour = ((nb(fc) + nb(cc)) * N + tiles * (N - 1) * 3 + min(nb(N * F), 2048)) * 256
+    rows = (nb(fc) + nb(cc)) * N * 256
+    transpose = (tiles * (N - 1) * 3 + min(nb(N * F), 2048)) * 256
     return [
-        ("KKT residual rows (whole level)", "k_kkt_split<", full, 1, N * (F * 5 + C * 4) * 4,
-         "v, u, w in, r1, r3 out per face; p-bar, p in, r2, r4 out per cell"),
-        ("colour-pass residual with the transpose", "k_kkt_split<", colour, 1, N * (F * 16 + fc * 12 + cc * 16),
-         "v, u in, t1, t1z out per face; w, r1, r3 at the colour's faces; 4 per colour cell"),
+        ("KKT residual rows (whole level)", "k_kkt_split<", full, 1, N * C * 108,
+         "the method's bytes: v, u, w, res in and r out per face (3 per cell), p-bar, p in per cell"),
+        ("colour-pass rows (one colour)", "k_kkt_split<", rows, 1, N * cc * 108,
+         "the method's bytes of the colour's cells (108 B per spacetime cell)"),
+        ("sweep transpose J_S^T u (once per sweep)", "k_kkt_split<", transpose, 1, (N - 1) * C * 36,
+         "the method's bytes: v, y in, J_S^T y out, 3 faces per cell"),
         ("SCGS colour pass", "k_scgs_colour_rows<", None, 1, 4 * 2 * N * (inner * 3.5 + cc * 3),
          "r1, t1, r3 read and u/v read+written per face block pair; 3 per cell block"),
         ("FAS restriction, faces", "k_restrict_faces<", _ceil256(Fc), N, N * (F + Fc) * 4, "fine in, coarse out"),

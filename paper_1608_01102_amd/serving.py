@@ -6,11 +6,15 @@ solver workspace from stfas_workspace_bytes plus its input and output
 buffers) fits in the remaining HBM budget; each slot owns a HIP stream
 (default priority) and a solver context, and runs its solve on a worker
 thread (the C call releases the Python interpreter lock, so slots overlap on
-the device).  When a solve finishes its memory is released and the next
-waiting request is admitted.  Latency is measured from arrival to result.
+the device).  When a solve finishes its memory is released and waiting
+requests are admitted.  Admission is in arrival order, except that a request
+that has arrived and fits may pass a waiting head that does not fit (a large
+request waiting for memory); the head can be passed at most `max_bypass`
+times, after which nothing passes it until it is admitted.  Latency is
+measured from arrival to result.
 
 The sequential baseline runs the same requests first-in first-out, one at a
-time, on the same arrivals.
+time, on the same arrivals, in real time.
 """
 import dataclasses
 import threading
@@ -87,6 +91,21 @@ def _solve_on(req, precision, stream):
     return out, stats
 
 
+def pick_next(pending, fps, now, free_bytes, bypassed, max_bypass):
+    """Index in `pending` (sorted by arrival) of the request to admit now, or
+    None.  now = None: every request has arrived.  The first arrived request
+    whose footprint fits in free_bytes is taken, except that once the head
+    has been passed max_bypass times only the head may be taken."""
+    for pos, q in enumerate(pending):
+        if now is not None and now < q.arrival:
+            return None                       # later ones have not arrived either
+        if fps[q.rid] <= free_bytes:
+            return pos
+        if pos == 0 and bypassed >= max_bypass:
+            return None                       # the head waits; nothing may pass it now
+    return None
+
+
 class Server:
     """Continuous-batching request loop.
 
@@ -94,13 +113,14 @@ class Server:
     max_slots:    concurrent solves (each a stream, a context and a thread).
     """
 
-    def __init__(self, budget_bytes=None, max_slots=4, precision="mixed"):
+    def __init__(self, budget_bytes=None, max_slots=4, precision="mixed", max_bypass=8):
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
             budget_bytes = int(0.8 * free)
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.precision = precision
+        self.max_bypass = int(max_bypass)
         self.streams = [torch.cuda.Stream() for _ in range(self.max_slots)]
 
     def run(self, requests, realtime=True):
@@ -130,22 +150,27 @@ class Server:
                     lock.notify_all()
 
         pending = list(reqs)
+        fps = {q.rid: footprint(q, self.precision) for q in reqs}
+        bypassed = 0                      # times the current head has been passed
         while pending:
-            q = pending[0]
-            fp = footprint(q, self.precision)
             with lock:
                 while True:
                     now = time.perf_counter() - t0
-                    arrived = (not realtime) or now >= q.arrival
-                    fits = state["used"] + fp <= self.budget and state["free_slots"]
-                    if arrived and fits:
+                    pick = None
+                    if state["free_slots"]:
+                        pick = pick_next(pending, fps, now if realtime else None, self.budget - state["used"],
+                                         bypassed, self.max_bypass)
+                    if pick is not None:
                         break
-                    wait = None if arrived else max(0.0, q.arrival - now)
-                    lock.wait(timeout=wait if wait is not None else 0.5)
+                    future = [q.arrival - now for q in pending if realtime and q.arrival > now]
+                    wait = min(future) if future else 0.5
+                    lock.wait(timeout=max(1e-3, min(wait, 0.5)))
+                q = pending.pop(pick)
+                bypassed = bypassed + 1 if pick > 0 else 0
                 slot = state["free_slots"].pop(0)
+                fp = fps[q.rid]
                 state["used"] += fp
                 admitted = time.perf_counter() - t0
-            pending.pop(0)
             th = threading.Thread(target=worker, args=(q, slot, fp, admitted), daemon=True)
             th.start()
             threads.append(th)

@@ -59,3 +59,20 @@ def test_source_hash_covers_the_kernel_sources():
     h = P.kernel_source_hash()
     assert h == P.kernel_source_hash() and len(h) == 16
     int(h, 16)
+
+
+def test_serving_admission_order():
+    """Admission of the continuous-batching server (host logic): arrival
+    order, a fitting request may pass a head that does not fit, at most
+    max_bypass times in a row, and nothing that has not arrived is taken."""
+    import types
+    from paper_1608_01102_amd.serving import pick_next
+    q = [types.SimpleNamespace(rid=i, arrival=float(i)) for i in range(4)]
+    fps = {0: 10, 1: 3, 2: 3, 3: 1}
+    assert pick_next(q, fps, None, 20, 0, 8) == 0          # head fits: first come first served
+    assert pick_next(q, fps, None, 5, 0, 8) == 1           # head does not fit: the next fitting one passes it
+    assert pick_next(q, fps, None, 5, 8, 8) is None        # passed too often: nothing passes it any more
+    assert pick_next(q, fps, 1.5, 5, 0, 8) == 1            # request 1 has arrived at t = 1.5
+    assert pick_next(q, fps, 0.5, 5, 0, 8) is None         # at t = 0.5 only the (too large) head has arrived
+    assert pick_next(q, fps, None, 2, 0, 8) == 3           # only the smallest fits
+    assert pick_next(q, fps, None, 0, 0, 8) is None
