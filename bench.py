@@ -42,7 +42,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--trace-kernel", default="kkt_split",
-                    help="kernel family whose launches on the finest level are timed with HIP events")
+                    help="kernel family of the roofline: its launches on the finest level are timed with HIP events "
+                         "in an extra (untimed) solve")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="start with the 256 MiB device copy the counter passes are scaled by")
     ap.add_argument("--lbfgs-iters", type=int, default=200,
                     help="iteration cap of the L-BFGS comparison (0 skips it)")
     ap.add_argument("--no-sl", action="store_true", help="skip the solve with the semi-Lagrangian density operator")
@@ -87,6 +90,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate:
+        from paper_1608_01102_amd.profiling import calibration_copy
+        calibration_copy()
     w = synthetic.c2_plain_2d_128(args.seed)
     n, N = w["n"], w["num_steps"]
     kw = dict(max_admm=args.max_admm)
@@ -100,7 +106,6 @@ def main():
     for _ in range(args.warmup):
         S.stfas_solve(ctx, rho0, ks, keys, u)
     torch.cuda.synchronize()
-    S.stfas_trace_enable(ctx, args.trace_kernel, 1 << 16)
     stats = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -108,8 +113,6 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
-    nlaunch, tms, tbytes, timpl = S.stfas_trace_read(ctx)
-    S.stfas_trace_enable(ctx, 0, 0)
     vcycles = sum(s["vcycles"] for s in stats) / len(stats)
     cells = n[0] * n[1]
     value = cells * N * vcycles / (ms * 1e-3)
@@ -130,16 +133,12 @@ def main():
         "admm_iters": last["admm_iters"], "vcycles": last["vcycles"], "converged": bool(last["converged"]),
         "objective": last["objective"], "kkt_res_inf": last["kkt_res_inf"], "visual_diff": last["visual_diff"],
     }
-    if nlaunch:
-        avg_us = tms * 1e3 / nlaunch
-        achieved = tbytes / (tms * 1e-3) / 1e9
-        traffic = measured_traffic(args.trace_kernel)
-        out["roofline"] = {"bound": "hbm", "kernel": args.trace_kernel, "achieved": achieved, "peak": 8000.0,
-                           "unit": "GB/s", "frac": achieved / 8000.0, "traffic": traffic,
-                           "avg_launch_us": avg_us, "launches_timed": nlaunch,
-                           "alg_bytes_per_launch": tbytes / nlaunch,
-                           "impl_bytes_per_launch": timpl / nlaunch,
-                           "alg_bytes_rule": alg_rule(args.trace_kernel)}
+    # rooflines: one more solve per kernel family with its finest-level launches timed by HIP events
+    out["roofline"] = roofline(S, ctx, rho0, ks, keys, u, args.trace_kernel)
+    if args.density == "upwind" and args.trace_kernel != "up_term":
+        # the upwind series term: most kernel time in total, but each launch is a 16384-cell dispatch of a
+        # few microseconds, which a per-launch event pair cannot resolve (it adds the dispatch gap)
+        out["roofline_density_op"] = roofline(S, ctx, rho0, ks, keys, u, "up_term")
     ctx.destroy()
     if not args.no_fp64_check:
         # the same solve in FP64 on the GPU (untimed): the mixed form's keyframe error against it
@@ -165,11 +164,36 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def roofline(S, ctx, rho0, ks, keys, u, kernel):
+    """Achieved HBM rate of one kernel family over one solve: the method's
+    bytes of its launches / their summed duration (HIP events on the solver's
+    stream), against 8 TB/s; `traffic` is the counter-measured HBM bytes per
+    launch from the committed profile (None when there is none or the kernel
+    sources changed since)."""
+    import torch
+    S.stfas_trace_enable(ctx, kernel, 1 << 17)
+    S.stfas_solve(ctx, rho0, ks, keys, u)
+    torch.cuda.synchronize()
+    n, tms, tbytes, timpl = S.stfas_trace_read(ctx)
+    S.stfas_trace_enable(ctx, 0, 0)
+    if not n:
+        return None
+    achieved = tbytes / (tms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+            "frac": achieved / 8000.0, "traffic": measured_traffic(kernel),
+            "avg_launch_us": tms * 1e3 / n, "launches_timed": n, "alg_bytes_per_launch": tbytes / n,
+            "impl_bytes_per_launch": timpl / n, "alg_bytes_rule": alg_rule(kernel)}
+
+
 def alg_rule(kernel):
     rules = {"kkt_split": "the rows of one colour's cells per SCGS colour pass (and every cell for a whole-level "
                           "residual): 80 B per spacetime cell in 2D, 108 B in 3D (v, u, pbar, p, w, res in, r out; "
                           "FP32)",
-             "self_advect_T": "v, y in and J_S^T y out: 24 B per spacetime cell in 2D, 36 B in 3D (FP32)"}
+             "self_advect_T": "v, y in and J_S^T y out: 24 B per spacetime cell in 2D, 36 B in 3D (FP32)",
+             "up_term": "per working term of the upwind series (launches past the series' stop credited 0): "
+                        "T_(j-1) in, T_j out, the running sum read and written per cell and v per face "
+                        "(16 B per cell + 4 B per face, FP32); the first launch (j = 0) reads rho and copies it "
+                        "into the sum (8 B per cell)"}
     return rules.get(kernel, "the kernel family's inputs and outputs once")
 
 

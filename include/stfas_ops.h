@@ -124,8 +124,11 @@ stfas_status stfas_op_ao(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
  * separate launch any more; records nothing), 8 SCGS pressure
  * (1, 2 and 8 run only for horizons too long for the fused kernel), 9 SCGS
  * whole-colour kernel (faces and pressure of one colour, time-parallel),
- * 10 the one-launch residual that precedes each fused colour pass (face
- * rows, cell rows and the velocity-advection transpose side by side).
+ * 10 the residual rows of one SCGS colour (in 2D with the velocity-advection
+ * transpose in the same launch; in 3D the transpose is launched once per
+ * sweep and counts as family 4), 11 the working terms (j >= 1) of the upwind
+ * exponential density operator's series (a launch after the series has
+ * stopped returns at once and is still counted).
  * stfas_trace_read synchronises and returns the recorded launch count,
  * their summed duration in milliseconds, their algorithmic bytes (for
  * family 10: the method's bytes of the rows the launch computes, 80 B per

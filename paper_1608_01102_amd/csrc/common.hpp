@@ -6,9 +6,84 @@
 // held at zero.  2D problems use n2 = 1 and have no z block.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stdint.h>
 
 namespace stfas {
+
+// A failed HIP call on the host side throws; the C interface turns it into
+// STFAS_E_DEVICE.
+struct HipError {
+    hipError_t e;
+};
+#define HCK(x)                                   \
+    do {                                         \
+        hipError_t _e = (x);                     \
+        if (_e != hipSuccess) throw HipError{_e}; \
+    } while (0)
+#define LAUNCH_CHECK() HCK(hipPeekAtLastError())
+
+// Event tracing of one kernel family: when enabled, launches of that
+// family on the finest level are bracketed by events on the context's
+// stream (up to `cap` launches per enable) and their algorithmic bytes are
+// summed on the host.
+enum TraceKernel {
+    TR_NONE = 0,
+    TR_SCGS_THOMAS = 1,
+    TR_SCGS_PROJECT = 2,
+    TR_KKT_FACES = 3,
+    TR_SELF_ADVECT_T = 4,
+    TR_RBGS = 5,
+    TR_ADVECT = 6,
+    TR_KKT_CELLS = 7,
+    TR_SCGS_CELLS = 8,
+    TR_SCGS_COLOUR = 9,
+    TR_KKT_SPLIT = 10,
+    TR_UP_TERM = 11
+};
+
+struct Tracer {
+    int id = TR_NONE;
+    int cap = 0, used = 0;
+    long launches = 0;
+    double bytes = 0;        // the method's bytes of the recorded launches
+    double impl_bytes = 0;   // every buffer the launches read or write once (with the implementation's scratch)
+    std::vector<hipEvent_t> ev;
+    bool on(int k) const { return id == k && used < cap; }
+    // correction of the bytes credited to launches already recorded (a launch
+    // that turned out to have no work, known only once the host has synchronised)
+    void credit(int k, double b) {
+        if (id == k) bytes += b;
+    }
+    void reset() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        id = TR_NONE;
+        cap = used = 0;
+        launches = 0;
+        bytes = 0;
+        impl_bytes = 0;
+    }
+};
+
+// impl < 0: the launch moves exactly the method's bytes.
+template <typename Launch>
+inline void traced(Tracer& tr, hipStream_t st, int kind, double bytes, Launch&& launch, double impl = -1) {
+    if (!tr.on(kind)) {
+        launch();
+        return;
+    }
+    HCK(hipEventRecord(tr.ev[2 * tr.used], st));
+    launch();
+    HCK(hipEventRecord(tr.ev[2 * tr.used + 1], st));
+    ++tr.used;
+    ++tr.launches;
+    tr.bytes += bytes;
+    tr.impl_bytes += impl < 0 ? bytes : impl;
+}
+
+
 
 struct Grid {
     int n[3];        // n0, n1, n2 (n2 = 1 in 2D)

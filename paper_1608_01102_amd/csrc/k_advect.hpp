@@ -290,8 +290,15 @@ __global__ void __launch_bounds__(256) k_advect_T_tiled(Grid g, T cfl, const T* 
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = my;
     __syncthreads();
     my = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    // a non-finite weight anywhere in the tile (fmax drops NaNs, so it is
+    // tested apart): every weight goes straight to out with float atomics, so
+    // that the NaN or Inf reaches the result instead of an undefined integer
+    bool nf = false;
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) nf = nf || !isfinite(wq[q]);
+    const bool direct = __syncthreads_or(nf) != 0 || !isfinite(my);
     int e2 = 0;
-    (void)frexp((double)my, &e2);
+    (void)frexp((double)(direct ? (T)1 : my), &e2);
     const double fx = ldexp(1.0, 52 - e2), ifx = ldexp(1.0, e2 - 52);
 #pragma unroll
     for (int q = 0; q < (1 << D); ++q) {
@@ -299,7 +306,7 @@ __global__ void __launch_bounds__(256) k_advect_T_tiled(Grid g, T cfl, const T* 
         if (w == (T)0) continue;
         const int ci = c0[0] + (q & 1), cj = c0[1] + ((q >> 1) & 1), ck = D == 3 ? c0[2] + ((q >> 2) & 1) : 0;
         const int wx = ci - ox, wy = cj - oy, wz = ck - oz;
-        if (wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
+        if (!direct && wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
             atomicAdd(&win[(wz * WY + wy) * WX + wx], (unsigned long long)llrint((double)w * fx));
         else
             atomic_add(out + cell_index(g, ci, cj, ck), w);
@@ -329,9 +336,14 @@ inline void launch_advect_T(const Grid& g, T cfl, const T* mu, const T* v, T* ou
     k_advect_T_tiled<T, D><<<dim3(tiles, batch), 256, 0, st>>>(g, cfl, mu, v, out, g.ncell, g.nface);
 }
 
+// gq != nullptr: the quarters of the foot-point term that go to the faces of
+// the other axes are not added here; instead every a-face of the tile stores
+// its components b != a in gq (slice s, k-th axis other than a at
+// gq[(2 s + k) F + f]), and k_quarter_gather adds them afterwards as a
+// gather (no atomics).
 template <typename T, int D>
 __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restrict__ v, const T* __restrict__ y,
-                                          T scale, T* out, long vs, int tile, int slice, int a) {
+                                          T scale, T* out, long vs, int tile, int slice, int a, T* gq = nullptr) {
     using TS = TileShape<D>;
     constexpr int H = TS::H;
     constexpr int WX = TS::X + 2 * H, WY = TS::Y + 2 * H, WZ = (D == 3) ? TS::Z + 2 * H : 1;
@@ -404,8 +416,14 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = my;
     __syncthreads();
     my = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    // a non-finite weight anywhere in the tile: every weight goes straight to
+    // out with float atomics (as in the density adjoint above)
+    bool nf = false;
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) nf = nf || !isfinite(wq[q]);
+    const bool direct = __syncthreads_or(nf) != 0 || !isfinite(my);
     int e2 = 0;
-    (void)frexp((double)my, &e2);
+    (void)frexp((double)(direct ? (T)1 : my), &e2);
     const double fx = ldexp(1.0, 52 - e2), ifx = ldexp(1.0, e2 - 52);
     // Weights.  Neighbouring lanes of a row usually backtrace into
     // neighbouring cells, so the +x corner of lane l is the 0 corner of lane
@@ -428,7 +446,7 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
             const int ca = a == 0 ? ci : (a == 1 ? cj : ck);
             if (ca == 0 || ca == g.n[a]) continue;          // wall node of the a-lattice
             const int wx = ci - ox, wy = cj - oy, wz = ck - oz;
-            if (wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
+            if (!direct && wx >= 0 && wx < WX && wy >= 0 && wy < WY && wz >= 0 && wz < WZ)
                 atomicAdd(&win[(wz * WY + wy) * WX + wx], (unsigned long long)llrint((double)w * fx));
             else
                 atomic_add(out + face_index(g, a, ci, cj, ck), w);
@@ -436,6 +454,12 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
     }
 #pragma unroll
     for (int b = 0; b < D; ++b) slot[b][threadIdx.x] = gs[b];
+    if (gq && valid) {
+        const long f = face_index(g, a, i, j, k);
+#pragma unroll
+        for (int b = 0; b < D; ++b)
+            if (b != a) gq[(2L * slice + (b < a ? b : b - 1)) * vs + f] = gs[b];
+    }
     __syncthreads();
     // foot-point component b of the tile's source at a-lattice node (si, sj, sk), 0 outside the tile
     auto src = [&](int b, int si, int sj, int sk) -> T {
@@ -451,6 +475,7 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
         if (ci < 0 || cj < 0 || ck < 0 || ci >= ex || cj >= ey || (D == 3 && ck >= ez)) continue;
         atomic_add(out + face_index(g, a, ci, cj, ck), val);
     }
+    if (gq) return;
     // b-nodes next to the tile: gather the quarters of the b-components
 #pragma unroll
     for (int b = 0; b < D; ++b) {
@@ -470,6 +495,32 @@ __device__ inline void self_advect_T_tile(const Grid& g, T cfl, const T* __restr
             atomic_add(out + face_index(g, b, ci, cj, ck), (T)0.25 * s);
         }
     }
+}
+
+// out += the quarters of the foot-point term stored in gq by the tiles: a
+// b-face J takes, from each other axis a, a quarter of the b-component of
+// the a-faces J, J + e_a, J - e_b and J + e_a - e_b (the four whose averaged
+// b-velocity includes J); wall b-faces take nothing.  blockIdx.y = slice.
+template <typename T, int D>
+__global__ void k_quarter_gather(Grid g, const T* __restrict__ gq, T* __restrict__ out, long vs) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= g.nface) return;
+    int b, i, j, k;
+    face_decode(g, f, b, i, j, k);
+    if (!face_interior(g, b, i, j, k)) return;
+    const long s = blockIdx.y;
+    T acc = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (a == b) continue;
+        const T* q = gq + (2 * s + (b < a ? b : b - 1)) * vs;
+        const int da0 = a == 0, da1 = a == 1, da2 = a == 2;
+        const int db0 = b == 0, db1 = b == 1, db2 = b == 2;
+        acc += q[face_index(g, a, i, j, k)] + q[face_index(g, a, i + da0, j + da1, k + da2)] +
+               q[face_index(g, a, i - db0, j - db1, k - db2)] +
+               q[face_index(g, a, i + da0 - db0, j + da1 - db1, k + da2 - db2)];
+    }
+    out[s * vs + f] += (T)0.25 * acc;
 }
 
 template <typename T, int D>

@@ -95,6 +95,7 @@ struct KktSplit {
     int par[3];     // coordinate parities of the colour's cells
     int cnt[3];     // cells of the colour along each axis
     int nfc;        // faces of the colour's cells (per slice), with rows set
+    void* gq;       // tiled transpose: where the quarters for the other axes go (k_quarter_gather adds them)
 };
 
 // Face e (0 <= e < nfc) of the colour's cells: a-faces whose coordinates
@@ -161,7 +162,7 @@ __global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T 
         // tile, slice, axis; y = u_{j+1} (the u slots shifted by one), scale -sgn/dt
         const int tile = (int)(b % ks.ntile);
         const int a = (int)(b / ((long)ks.ntile * (N - 1)));
-        self_advect_T_tile<T, D>(g, cfl, v, u + g.nface, -sgn / dt, t1, g.nface, tile, slice, a);
+        self_advect_T_tile<T, D>(g, cfl, v, u + g.nface, -sgn / dt, t1, g.nface, tile, slice, a, (T*)ks.gq);
         return;
     }
     b -= bt;

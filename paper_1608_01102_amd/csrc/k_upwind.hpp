@@ -226,6 +226,7 @@ struct UpwindExp {
     T* terms = nullptr;   // [UP_KMAX][ncell]: T_1 .. T_KMAX
     T* z[2] = {nullptr, nullptr};
     UpCtl<T> ctl{};
+    Tracer* tr = nullptr;   // records the working term launches (j >= 1) when tracing is on
 
     template <typename Ar>
     void layout(Ar& A, long ncell) {
@@ -247,13 +248,31 @@ struct UpwindExp {
         const U tolb = UpBits<T>::of((T)UP_TOL);
         const int nb = blocks_for(C, 256);
         nl = nl < 0 ? 0 : (nl > UP_KMAX ? UP_KMAX : nl);
-        for (int j = 0; j <= nl; ++j)
-            k_up_term<T, D><<<nb, 256, 0, st>>>(g, j ? (T)(dt / (j * g.h)) : (T)0, j,
-                                                 j ? term(rho, j - 1, C) : rho, v,
-                                                 j ? terms + (long)(j - 1) * C : nullptr, out, ctl, tolb);
+        for (int j = 0; j <= nl; ++j) {
+            auto launch = [&] {
+                k_up_term<T, D><<<nb, 256, 0, st>>>(g, j ? (T)(dt / (j * g.h)) : (T)0, j,
+                                                     j ? term(rho, j - 1, C) : rho, v,
+                                                     j ? terms + (long)(j - 1) * C : nullptr, out, ctl, tolb);
+            };
+            // every launch is recorded and credited as working; the caller takes back the credit of
+            // launches past the stop (term_bytes each) once it knows k
+            if (tr)
+                traced(*tr, st, TR_UP_TERM, j ? term_bytes(g) : copy_bytes(g, out != nullptr), launch);
+            else
+                launch();
+        }
     }
-    void forward(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st, int nl = UP_KMAX) {
+    // The method's bytes of one working term: T_{j-1} in, T_j out, the sum read and written per cell, v
+    // per face; of the first launch (j = 0): rho in, and copied into the sum when there is one.
+    static double term_bytes(const Grid& g) { return (double)sizeof(T) * (4.0 * g.ncell + (double)g.nface); }
+    static double copy_bytes(const Grid& g, bool sum) { return (double)sizeof(T) * g.ncell * (sum ? 2.0 : 1.0); }
+    // record = false: the call's launches are not recorded by the tracer (the caller will not learn k)
+    void forward(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st, int nl = UP_KMAX,
+                 bool record = false) {
+        Tracer* keep = tr;
+        if (!record) tr = nullptr;
         series(g, dt, rho, v, out, st, nl);
+        tr = keep;
     }
     // k and the stopped flag of the last series (launched to nl) into device ints
     void record(int nl, int* k_out, int* ok_out, hipStream_t st) {
@@ -267,7 +286,11 @@ struct UpwindExp {
                  T scale, hipStream_t st, int k_known = -1) {
         const long C = g.ncell;
         const int nl = k_known >= 0 ? k_known : UP_KMAX;
+        // with k unknown the launches past the stop cannot be told apart: such calls are not recorded
+        Tracer* keep = tr;
+        if (k_known < 0) tr = nullptr;
         series(g, dt, rho, v, nullptr, st, nl);
+        tr = keep;
         k_up_gv_init<T><<<blocks_for(g.nface, 256), 256, 0, st>>>(g, base, gv);
         const int nb = blocks_for(C, 256);
         const T inv_h = (T)(1.0 / g.h);

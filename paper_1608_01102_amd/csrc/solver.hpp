@@ -30,15 +30,6 @@ constexpr int MAX_COARSE_CELLS = 4096;
 constexpr int MAX_PROJECT_CYCLES = 60;
 constexpr long DIRECT_T_SLOTS = 131072;   // face slots up to which the residual's transpose runs untiled
 
-struct HipError {
-    hipError_t e;
-};
-#define HCK(x)                                   \
-    do {                                         \
-        hipError_t _e = (x);                     \
-        if (_e != hipSuccess) throw HipError{_e}; \
-    } while (0)
-#define LAUNCH_CHECK() HCK(hipPeekAtLastError())
 
 // Bump allocator with a planning pass: plan() sizes every buffer, carve()
 // hands out the same offsets inside one allocation.
@@ -418,59 +409,6 @@ struct Poisson {
     }
 };
 
-// Event tracing of one kernel family: when enabled, launches of that
-// family on the finest level are bracketed by events on the context's
-// stream (up to `cap` launches per enable) and their algorithmic bytes are
-// summed on the host.
-enum TraceKernel {
-    TR_NONE = 0,
-    TR_SCGS_THOMAS = 1,
-    TR_SCGS_PROJECT = 2,
-    TR_KKT_FACES = 3,
-    TR_SELF_ADVECT_T = 4,
-    TR_RBGS = 5,
-    TR_ADVECT = 6,
-    TR_KKT_CELLS = 7,
-    TR_SCGS_CELLS = 8,
-    TR_SCGS_COLOUR = 9,
-    TR_KKT_SPLIT = 10
-};
-
-struct Tracer {
-    int id = TR_NONE;
-    int cap = 0, used = 0;
-    long launches = 0;
-    double bytes = 0;        // the method's bytes of the recorded launches
-    double impl_bytes = 0;   // every buffer the launches read or write once (with the implementation's scratch)
-    std::vector<hipEvent_t> ev;
-    bool on(int k) const { return id == k && used < cap; }
-    void reset() {
-        for (auto e : ev) (void)hipEventDestroy(e);
-        ev.clear();
-        id = TR_NONE;
-        cap = used = 0;
-        launches = 0;
-        bytes = 0;
-        impl_bytes = 0;
-    }
-};
-
-// impl < 0: the launch moves exactly the method's bytes.
-template <typename Launch>
-inline void traced(Tracer& tr, hipStream_t st, int kind, double bytes, Launch&& launch, double impl = -1) {
-    if (!tr.on(kind)) {
-        launch();
-        return;
-    }
-    HCK(hipEventRecord(tr.ev[2 * tr.used], st));
-    launch();
-    HCK(hipEventRecord(tr.ev[2 * tr.used + 1], st));
-    ++tr.used;
-    ++tr.launches;
-    tr.bytes += bytes;
-    tr.impl_bytes += impl < 0 ? bytes : impl;
-}
-
 // Pinned host buffer for scalar readbacks, one per host thread, kept for the
 // life of the process (freeing pinned memory would synchronise the device).
 inline double* thread_pinned() {
@@ -649,6 +587,7 @@ public:
     T* scgs_scratch = nullptr;   // two-kernel SCGS path only (horizons too long for the fused kernel)
     T *t1a = nullptr, *t1b = nullptr;   // J_S^T part of F1 for the SCGS colour passes (any level)
     T *t1_zero = nullptr, *t1_used = nullptr;   // t1a / t1b: the one that is all zero, the other
+    T* tq = nullptr;                            // quarters of the 3D sweep transpose (k_quarter_gather)
     T *t_diag, *t_sub, *t_sup, *t_cp, *t_inv;
     Poisson<T, D> pois;      // projection, batched over up to N slices
     // density subproblem
@@ -715,6 +654,8 @@ public:
         // the J_S^T part of F1 held over a sweep, and its cleared successor (any level)
         t1a = A.take<T>(N * F0);
         t1b = A.take<T>(N * F0);
+        // 3D: the foot-point quarters of the sweep's transpose, two per face slot (any level)
+        tq = D == 3 ? A.take<T>((size_t)2 * N * F0) : nullptr;
         // SCGS scratch of long horizons: the largest colour of level 0, 2N blocks, 2d faces per cell
         int Gs, Ls, CHs;
         if (colour_shape<T, D>(2 * N, 1, Gs, Ls, CHs)) {
@@ -756,6 +697,7 @@ public:
         red_out = A.take<double>(64);
         if (upwind()) {
             up.layout(A, C0);
+            up.tr = &tr;
             up_kd = A.template take<int>(N);
             up_okd = A.template take<int>(N);
         }
@@ -965,6 +907,9 @@ public:
             }
         }
         ks.nbz = std::min(blocks_for((long)N * g.nface, 256), 2048);
+        // 3D tiles: the quarters of the foot-point term for the other axes through tq and a gather
+        const bool gather = D == 3 && !ks.direct && N > 1;
+        ks.gq = gather ? (void*)tq : nullptr;
         const long blocks = (long)ks.ntile * std::max(N - 1, 0) * (ks.direct ? 1 : D) + ks.nbz;
         const double sz = sizeof(T);
         // the method's bytes (v, y -> J_S^T y): 3d words per spacetime cell (24 B in 2D, 36 B in 3D, FP32);
@@ -975,7 +920,9 @@ public:
             k_kkt_split<T, D><<<(unsigned)blocks, 256, 0, st>>>(g, N, (T)P.dt, (T)(P.K / P.r), cfl(l), (T)-1, ks,
                                                                q.v, q.pb, q.u, q.p, q.w, q.s1, q.s2, q.s3, q.s4,
                                                                q.r1, q.r2, q.r3, q.r4, t1, t1z);
-        }, impl);
+            if (gather)
+                k_quarter_gather<T, D><<<dim3(blocks_for(g.nface, 256), N - 1), 256, 0, st>>>(g, tq, t1, g.nface);
+        }, impl + (gather ? sz * (double)g.nface * (N - 1) * (2 * 2 + 1 + 1) : 0.0));
     }
     // t1 != nullptr: the same launch also computes the J_S^T part (every
     // face, into t1, zero on entry) and clears t1z: one launch per colour
@@ -1227,13 +1174,16 @@ public:
         int from = 0;
         while (from < N) {
             for (int i = from; i < N; ++i) {
-                up.forward(L[0], P.dt, r + i * C, vs + i * F, r + (i + 1) * C, st, nl[i]);
+                up.forward(L[0], P.dt, r + i * C, vs + i * F, r + (i + 1) * C, st, nl[i], true);
                 up.record(nl[i], up_kd + i, up_okd + i, st);
             }
             HCK(hipMemcpyAsync(kh.data() + from, up_kd + from, (N - from) * sizeof(int), hipMemcpyDeviceToHost, st));
             HCK(hipMemcpyAsync(okh.data() + from, up_okd + from, (N - from) * sizeof(int), hipMemcpyDeviceToHost,
                                st));
             HCK(hipStreamSynchronize(st));
+            // the launches past each series' stop did no work: take back their credit
+            for (int i = from; i < N; ++i)
+                tr.credit(TR_UP_TERM, -(double)(nl[i] - kh[i]) * UpwindExp<T, D>::term_bytes(L[0]));
             int bad = N;
             for (int i = from; i < N; ++i)
                 if (!okh[i]) {

@@ -508,7 +508,7 @@ stfas_status stfas_op_ao(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
 }
 
 stfas_status stfas_trace_enable(stfas_ctx* ctx, int32_t kernel, int32_t max_launches) {
-    if (!ctx || kernel < 0 || kernel > TR_KKT_SPLIT || max_launches < 0 || max_launches > (1 << 20))
+    if (!ctx || kernel < 0 || kernel > TR_UP_TERM || max_launches < 0 || max_launches > (1 << 20))
         return STFAS_E_INVALID;
     return guard([&]() -> stfas_status {
         HCK(hipStreamSynchronize(ctx->s->st));

@@ -56,6 +56,18 @@ def stats(db, kernel=None, grid_x=None):
     return "\n".join(lines)
 
 
+def calibration_copy():
+    """Four plain device copies of COPY_BYTES each (the reference the counter
+    readings are scaled by)."""
+    import torch
+    dev = torch.device("cuda:0")
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
 def workload(reps=20):
     import numpy as np
     import torch
@@ -63,11 +75,7 @@ def workload(reps=20):
     import synthetic
     from paper_1608_01102_amd import stfas as S
     dev = torch.device("cuda:0")
-    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
-    b = torch.empty_like(a)
-    for _ in range(4):
-        b.copy_(a)
-    torch.cuda.synchronize()
+    calibration_copy()
     w = synthetic.c2_plain_2d_128(0)
     n, N = w["n"], w["num_steps"]
     prob = S.make_problem(n, N, w["r"], dt=w["dt"], precision="mixed")

@@ -346,7 +346,7 @@ def stfas_op_ao(ctx, rho0, key_steps, key_rho, vt, vstar, rho):
 
 TRACE_KERNELS = {"scgs_thomas": 1, "scgs_project": 2, "kkt_faces": 3, "self_advect_T": 4, "rbgs": 5, "advect": 6,
                  "kkt_cells": 7, "scgs_cells": 8, "scgs_colour": 9,
-                 "kkt_split": 10}
+                 "kkt_split": 10, "up_term": 11}
 
 
 def stfas_trace_enable(ctx, kernel, max_launches=4096):

@@ -318,3 +318,43 @@ def test_invalid_arguments_rejected(prec):
         with pytest.raises(StfasError):
             S.stfas_solve(ctx, rho0, bad, zeros(len(bad) * g.ncell, prec), u)
     ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_tiled_adjoints_propagate_nonfinite(prec):
+    """A NaN in the cotangent of the tiled density adjoint and of the tiled
+    velocity-advection transpose (both sum their windows in fixed point)
+    reaches the output at the affected nodes instead of turning into an
+    arbitrary integer; every other node keeps the oracle's value."""
+    n, B = (64, 64), 40
+    S, ctx, g, dt, K = _ctx(n, 2, prec, dt=1.0 / n[0])
+    rng = np.random.default_rng(26)
+    assert g.ncell * B >= 131072
+    v = _q(np.stack([synthetic.curl_noise_velocity(n, rng, 2.0, 1.0, dt / g.h) for _ in range(B)]), prec)
+    mu = _q(rng.standard_normal((B, g.ncell)), prec)
+    bad = (3, 2000)
+    mu[bad] = np.nan
+    out = empty(B * g.ncell, prec)
+    flag(f"advect_T tiled with a NaN {prec}")
+    S.stfas_op_advect_T(ctx, B, to_dev(mu, prec), to_dev(v, prec), None, out)
+    got = to_np(out).reshape(B, -1)
+    mu_ok = mu.copy()
+    mu_ok[bad] = 0.0
+    ref = advect.advect_scalar_T(g, mu_ok, v, dt)
+    nan = ~np.isfinite(got)
+    assert nan[3].any() and not nan[np.arange(B) != 3].any() and nan[3].sum() <= 4
+    assert rel(got[~nan], ref[~nan]) <= TOL[prec]
+    # the velocity-advection transpose, tiled (one slice covers more than the untiled limit per launch)
+    y = _q(np.stack([synthetic.random_faces(n, rng) for _ in range(B)]), prec)
+    badf = (5, g.face_offsets[0] + 40 * (n[0] + 1) + 30)        # an interior x-face
+    y[badf] = np.nan
+    outf = zeros(B * g.nface, prec)
+    flag(f"self_advect_T tiled with a NaN {prec}")
+    S.stfas_op_self_advect_T(ctx, 0, B, to_dev(v, prec), to_dev(y, prec), 1.0, outf)
+    gotf = to_np(outf).reshape(B, -1)
+    y_ok = y.copy()
+    y_ok[badf] = 0.0
+    reff = advect.self_advect_T(g, v, y_ok, dt)
+    nanf = ~np.isfinite(gotf)
+    assert nanf[5].any() and not nanf[np.arange(B) != 5].any()
+    assert rel(gotf[~nanf], reff[~nanf]) <= TOL[prec]
