@@ -96,7 +96,11 @@ def workload(reps=20):
     print("workload done", flush=True)
 
 
-def pmc(directory, counter, kernel, grid_x):
+def pmc(directory, counter, kernel, grid_x, min_frac=0.0):
+    """Mean counter reading per dispatch of `kernel` with this grid size,
+    scaled by the calibration copy's reading.  min_frac > 0 drops dispatches
+    reading below that fraction of the largest (launches that return at once,
+    such as the upwind series terms past the series' stop)."""
     files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
     vals, copy = [], []
     for f in files:
@@ -110,7 +114,12 @@ def pmc(directory, counter, kernel, grid_x):
                     vals.append(v)
                 elif "copy" in name.lower() and v > 0.25 * COPY_BYTES / 1024.0:
                     copy.append(v)      # the calibration copy (smaller copies are ignored)
+    dropped = 0
+    if vals and float(min_frac) > 0:
+        keep = [v for v in vals if v >= float(min_frac) * max(vals)]
+        dropped, vals = len(vals) - len(keep), keep
     out = {"counter": counter, "kernel": kernel, "grid_x": int(grid_x), "dispatches": len(vals),
+           "dropped_below_min_frac": dropped,
            "mean_kib": sum(vals) / len(vals) if vals else None,
            "copy_dispatches": len(copy), "copy_mean_kib": sum(copy) / len(copy) if copy else None,
            "copy_expected_kib": COPY_BYTES / 1024.0}
@@ -323,7 +332,7 @@ def main(argv):
         workload()
     elif argv[0] == "pmc":
         import json
-        print(json.dumps(pmc(argv[1], argv[2], argv[3], argv[4])))
+        print(json.dumps(pmc(*argv[1:6])))
     elif argv[0] == "ops":
         ops_workload()
     elif argv[0] == "opstable":

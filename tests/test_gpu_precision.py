@@ -84,6 +84,9 @@ def test_mixed_vs_fp64_gpu_on_64cubed():
     ekf = max(rel(km[t], kd[t]) for t in kd)
     eobj = abs(sm["objective"] - sd["objective"]) / abs(sd["objective"])
     print(f"64^3x60: |u_mixed - u_fp64|/|u_fp64| = {e_u:.2e}, keyframe error = {ekf:.2e}, objective = {eobj:.2e}")
-    # controls differ most where a foot point sits near a lattice line; the keyframe
-    # densities (the metric) and the objective are far tighter
-    assert e_u <= 5e-3 and ekf <= 1e-4 and eobj <= 1e-5
+    # The controls of 2 ADMM x 4 V-cycles differ by 0.95-1.1e-3 between runs (the mixed
+    # transposes add with FP32 atomics in a varying order, and the SL density gathers carry
+    # kinks where a foot point crosses a lattice line, which turn FP32 rounding into
+    # first-order differences of the density subproblem's direction); the bound is twice
+    # that.  The keyframe densities (the metric) and the objective are held to 1e-4 and 1e-5.
+    assert e_u <= 2e-3 and ekf <= 1e-4 and eobj <= 1e-5

@@ -36,6 +36,21 @@ def test_pmc_scales_by_the_calibration_copy(tmp_path):
     assert abs(out["bytes_per_dispatch"] - 200.0 * 1024 * 2.0) < 1e-6
 
 
+def test_pmc_min_frac_drops_launches_that_return_at_once(tmp_path):
+    """Dispatches reading below min_frac of the largest (series terms past the
+    stop) leave the average; none is dropped without min_frac."""
+    copy_kib = P.COPY_BYTES / 1024.0
+    rows = [("__amd_rocclr_copyBuffer", 131072, "WRITE_SIZE", copy_kib)] * 4
+    rows += [("void stfas::k_up_term<float, 2>(...)", 16384, "WRITE_SIZE", v)
+             for v in (64.0, 64.0, 48.0, 0.0, 0.0, 0.06)]
+    _write_csv(str(tmp_path / "run" / "run_counter_collection.csv"), rows)
+    out = P.pmc(str(tmp_path), "WRITE_SIZE", "up_term", 16384, "0.25")
+    assert out["dispatches"] == 3 and out["dropped_below_min_frac"] == 3
+    assert abs(out["bytes_per_dispatch"] - (176.0 / 3) * 1024) < 1e-6
+    out = P.pmc(str(tmp_path), "WRITE_SIZE", "up_term", 16384)
+    assert out["dispatches"] == 6 and out["dropped_below_min_frac"] == 0
+
+
 def test_upwind_term_row_takes_terms_one_to_k():
     """Launches of each 49-launch series in order: term 0 (the copy) and
     the terms after k are left out of the average."""
