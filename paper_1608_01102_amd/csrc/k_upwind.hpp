@@ -19,12 +19,14 @@
 // of A and A^T carries dt a! b! / (a+b+1)!, which is what the recursion
 // accumulates.
 //
-// Device form: one launch per term.  Each block folds max|T_j| into a
-// per-term word with atomicMax on the bit pattern (non-negative floats order
-// like their bits); launch j + 1 reads that word and returns at once when
-// the series has already stopped, so a fixed sequence of launches needs no
-// host synchronisation.  Every active launch records its j, so the last one
-// leaves k.  The adjoint launches read k and are empty for b >= k.
+// Device form: each block folds max|T_j| into a per-term word with atomicMax
+// on the bit pattern (non-negative floats order like their bits); a launch
+// reads the words of the terms before it and returns at once when the series
+// has already stopped, so a fixed sequence of launches needs no host
+// synchronisation.  A closing launch finds k from the words.  The adjoint
+// launches read k and are empty for b >= k.  In 3D a launch is one term (or
+// one adjoint step) of the whole grid; in 2D a launch is several terms of
+// one tile (below).
 #pragma once
 
 #include "common.hpp"
@@ -52,6 +54,7 @@ template <typename T>
 struct UpCtl {
     typename UpBits<T>::U* maxb;   // [UP_KMAX + 1]: bits of max|T_j|
     int* k;                        // index of the last summed term
+    int* stopped;                  // 1 when the series stopped within the launched terms (or at the cap)
 };
 
 __device__ inline void cell_decode(const Grid& g, int c, int (&x)[3]) {
@@ -132,7 +135,6 @@ __global__ void __launch_bounds__(256) k_up_term(Grid g, T coef, int j, const T*
             if (sum) sum[c] += val;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *ctl.k = j;
     block_max_fold<T>(fabs(val), ctl.maxb + j);
 }
 
@@ -199,14 +201,12 @@ __global__ void __launch_bounds__(256) k_up_adj(Grid g, T dtb, T inv_h, int b, c
     }
 }
 
-// The series after launches 0..nl: its k, and whether it stopped (the last
-// launched term passed the test, or the cap was reached).
+// The last series' k and whether it stopped, into the caller's words.
 template <typename T>
-__global__ void k_up_record(UpCtl<T> ctl, int nl, typename UpBits<T>::U tolb, int* __restrict__ k_out,
-                            int* __restrict__ ok_out) {
+__global__ void k_up_record(UpCtl<T> ctl, int* __restrict__ k_out, int* __restrict__ ok_out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     *k_out = *ctl.k;
-    *ok_out = (nl >= UP_KMAX || ctl.maxb[nl] < tolb) ? 1 : 0;
+    *ok_out = *ctl.stopped;
 }
 
 // gv = base (or 0) on interior faces, 0 on walls.
@@ -217,6 +217,309 @@ __global__ void k_up_gv_init(Grid g, const T* __restrict__ base, T* __restrict__
     int a, i, j, k;
     face_decode(g, f, a, i, j, k);
     gv[f] = face_interior(g, a, i, j, k) && base ? base[f] : (T)0;
+}
+
+// ---------------------------------------------------------------- 2D: several terms per launch
+//
+// On a 2D grid one term is a few microseconds of work behind a launch, so a
+// launch here takes UP_M consecutive terms (or adjoint steps) of one TS x TS
+// tile of cells.  Term j at a cell reads term j-1 within two cells along each
+// axis (the second-order upstream value), so after t terms only the cells at
+// least 2t from the edge of the loaded region are exact: the tile is loaded
+// with a halo of 2 UP_M cells and each term is computed on the region shrunk
+// by two more cells, in LDS.  Every term at every cell is the same expression
+// of the same values as in the one-term launch; the halo cells are computed
+// again by the neighbouring tiles.
+//
+// A launch cannot know whether one of its own terms ends the series (that is
+// a maximum over all tiles), so it computes all of its terms and the sum is
+// formed after the last launch (k_up_close), in the order of the one-term
+// launches: rho, then T_1, T_2, ... T_k.
+
+constexpr int UP_M = 4;          // terms (adjoint steps) per launch
+constexpr int UP_TS = 16;        // tile edge in cells
+constexpr int UP_NT = 512;       // threads per launch block
+
+// Fold the per-wave maxima of nt terms (wm[t][wave]) into ctl words j0 .. j0+nt-1.
+template <typename T>
+__device__ inline void fold_term_maxima(T (*wm)[UP_NT / 64], int nt, int j0, typename UpBits<T>::U* maxb) {
+    const int t = threadIdx.x;
+    if (t >= nt) return;
+    T b = wm[t][0];
+#pragma unroll
+    for (int w = 1; w < UP_NT / 64; ++w) b = fmax(b, wm[t][w]);
+    const typename UpBits<T>::U bb = UpBits<T>::of(b);
+    if (bb > __hip_atomic_load(maxb + j0 + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(maxb + j0 + t, bb);
+}
+
+template <typename T>
+__device__ inline T wave_max(T m) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    return m;
+}
+
+// Upwind face value from an LDS row: cells at offsets -2 .. +1 around the face
+// (lo2 = x[cL - s], lo1 = x[cL], hi1 = x[cR], hi2 = x[cR + s]); I is the face's
+// index along the axis, n the cell count.
+template <typename T>
+__device__ inline T up_face_lds(T vf, T lo2, T lo1, T hi1, T hi2, int I, int n) {
+    if (vf >= (T)0) return I >= 2 ? (T)1.5 * lo1 - (T)0.5 * lo2 : lo1;
+    return I + 1 <= n - 1 ? (T)1.5 * hi1 - (T)0.5 * hi2 : hi1;
+}
+
+// Terms j0 .. j0+nt-1 of the series of one tile (2D).  prev = T_{j0-1} on
+// the whole grid (rho when j0 = 1, whose maximum this launch also measures);
+// T_j goes to terms + (j-1) C.  Returns at once when an earlier term has
+// already passed the test.
+template <typename T>
+__global__ void __launch_bounds__(UP_NT) k_up_fwd_block(Grid g, double dt, int j0, int nt, const T* __restrict__ prev,
+                                                        const T* __restrict__ v, T* __restrict__ terms, UpCtl<T> ctl,
+                                                        typename UpBits<T>::U tolb) {
+    constexpr int H = 2 * UP_M, R = UP_TS + 2 * H;
+    __shared__ T buf[2][R * R];
+    __shared__ T vx[R * (R + 1)];     // x-face at (rx, ry): vx[ry (R+1) + rx], rx in [0, R]
+    __shared__ T vy[(R + 1) * R];     // y-face at (rx, ry): vy[ry R + rx], ry in [0, R]
+    __shared__ T wm[UP_M + 1][UP_NT / 64];
+    int stop = 0;   // an earlier launch's term (T_0 .. T_{j0-1}) passed the test
+    for (int j = threadIdx.x; j0 > 1 && j < j0; j += blockDim.x) stop |= ctl.maxb[j] < tolb;
+    if (__syncthreads_or(stop)) return;
+    const int nx = g.n[0], ny = g.n[1];
+    const long C = g.ncell;
+    const int ox = blockIdx.x * UP_TS - H, oy = blockIdx.y * UP_TS - H;
+    for (int q = threadIdx.x; q < R * R; q += blockDim.x) {
+        const int x = ox + q % R, y = oy + q / R;
+        buf[0][q] = (x >= 0 && x < nx && y >= 0 && y < ny) ? prev[x + (long)y * nx] : (T)0;
+    }
+    for (int q = threadIdx.x; q < R * (R + 1); q += blockDim.x) {
+        int x = ox + q % (R + 1), y = oy + q / (R + 1);
+        vx[q] = (x >= 0 && x <= nx && y >= 0 && y < ny) ? v[face_index(g, 0, x, y, 0)] : (T)0;
+        x = ox + q % R;
+        y = oy + q / R;
+        vy[q] = (x >= 0 && x < nx && y >= 0 && y <= ny) ? v[face_index(g, 1, x, y, 0)] : (T)0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (j0 == 1) {   // this launch also measures T_0
+        T m = 0;
+        for (int q = threadIdx.x; q < UP_TS * UP_TS; q += blockDim.x) {
+            const int rx = H + q % UP_TS, ry = H + q / UP_TS;
+            if (ox + rx < nx && oy + ry < ny) m = fmax(m, fabs(buf[0][ry * R + rx]));
+        }
+        m = wave_max(m);
+        if (lane == 0) wm[0][wave] = m;
+    }
+    int cur = 0;
+    for (int t = 1; t <= nt; ++t) {
+        const int j = j0 - 1 + t;
+        const T coef = (T)(dt / (j * g.h));
+        const int lo = 2 * t, w = R - 4 * t;
+        const T* p = buf[cur];
+        T* o = buf[cur ^ 1];
+        T m = 0;
+        for (int q = threadIdx.x; q < w * w; q += blockDim.x) {
+            const int rx = lo + q % w, ry = lo + q / w, x = ox + rx, y = oy + ry;
+            if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
+            const int c = ry * R + rx;
+            T acc = 0;
+            if (x >= 1) {                          // x: lower face x
+                const T vf = vx[ry * (R + 1) + rx];
+                acc += vf * up_face_lds(vf, p[c - 2], p[c - 1], p[c], p[c + 1], x, nx);
+            }
+            if (x + 1 <= nx - 1) {                 // x: upper face x + 1
+                const T vf = vx[ry * (R + 1) + rx + 1];
+                acc -= vf * up_face_lds(vf, p[c - 1], p[c], p[c + 1], p[c + 2], x + 1, nx);
+            }
+            if (y >= 1) {                          // y: lower face y
+                const T vf = vy[ry * R + rx];
+                acc += vf * up_face_lds(vf, p[c - 2 * R], p[c - R], p[c], p[c + R], y, ny);
+            }
+            if (y + 1 <= ny - 1) {                 // y: upper face y + 1
+                const T vf = vy[(ry + 1) * R + rx];
+                acc -= vf * up_face_lds(vf, p[c - R], p[c], p[c + R], p[c + 2 * R], y + 1, ny);
+            }
+            const T val = coef * acc;
+            o[c] = val;
+            if (rx >= H && rx < H + UP_TS && ry >= H && ry < H + UP_TS) {
+                terms[(long)(j - 1) * C + x + (long)y * nx] = val;
+                m = fmax(m, fabs(val));
+            }
+        }
+        m = wave_max(m);
+        if (lane == 0) wm[t][wave] = m;
+        __syncthreads();
+        cur ^= 1;
+    }
+    __syncthreads();
+    if (j0 == 1) fold_term_maxima<T>(wm, nt + 1, 0, ctl.maxb);
+    else fold_term_maxima<T>(wm + 1, nt, j0, ctl.maxb);
+}
+
+// acc + (A^T z) h at an LDS cell c for one axis, cell stride s: vf0 points
+// at the cell's lower face of that axis (index I along it, n cells), the
+// faces I-1 .. I+2 are at face offsets -1 .. +2 (pitch sv).  The terms are
+// added in the order of the one-step kernel.
+template <typename T>
+__device__ inline T up_AT_axis(T acc, const T* __restrict__ z, int c, int s, const T* __restrict__ vf0, int sv, int I,
+                               int n) {
+    if (I + 1 <= n - 1) {
+        const T vf = vf0[sv];
+        if (vf >= (T)0) acc += (I >= 1 ? (T)1.5 : (T)1) * vf * (z[c + s] - z[c]);
+    }
+    if (I + 2 <= n - 1) {
+        const T vf = vf0[2 * sv];
+        if (vf >= (T)0) acc -= (T)0.5 * vf * (z[c + 2 * s] - z[c + s]);
+    }
+    if (I >= 1) {
+        const T vf = vf0[0];
+        if (vf < (T)0) acc += (I + 1 <= n - 1 ? (T)1.5 : (T)1) * vf * (z[c] - z[c - s]);
+    }
+    if (I >= 2) {
+        const T vf = vf0[-sv];
+        if (vf < (T)0) acc -= (T)0.5 * vf * (z[c - s] - z[c - 2 * s]);
+    }
+    return acc;
+}
+
+// Adjoint steps b = b0 .. max(b0 - UP_M + 1, -1) of one tile (2D); steps
+// with b >= k are skipped.  zin = Z_{b0+1} (read only when the first active
+// step needs it), zout = Z of the last step when that step is >= 0; grho at
+// b = -1; gv of the tile's cells' lower faces gathered in registers over the
+// steps, in the order of the one-step launches.
+template <typename T>
+__global__ void __launch_bounds__(UP_NT) k_up_adj_block(Grid g, double dt, int b0, const T* __restrict__ mu,
+                                                        const T* __restrict__ zin, T* __restrict__ zout,
+                                                        const T* __restrict__ rho, const T* __restrict__ terms,
+                                                        const T* __restrict__ v, T* __restrict__ grho,
+                                                        T* __restrict__ gv, T scale, const int* __restrict__ kp) {
+    constexpr int H = 2 * UP_M, R = UP_TS + 2 * H, X = UP_TS + 4;
+    constexpr int NI = (UP_TS * UP_TS + UP_NT - 1) / UP_NT;
+    __shared__ T zb[2][R * R];
+    __shared__ T mus[R * R];
+    __shared__ T vx[R * (R + 1)];
+    __shared__ T vy[(R + 1) * R];
+    __shared__ T xb[X * X];          // T_{b+1} on the tile and two cells around it
+    const int k = *kp;
+    const int blo = b0 - UP_M + 1 < -1 ? -1 : b0 - UP_M + 1;
+    const int bs = b0 < k - 1 ? b0 : k - 1;
+    if (bs < blo) return;            // every step of this launch is past the series
+    const int nx = g.n[0], ny = g.n[1];
+    const long C = g.ncell;
+    const int ox = blockIdx.x * UP_TS - H, oy = blockIdx.y * UP_TS - H;
+    const bool zin_used = bs + 1 < k;
+    for (int q = threadIdx.x; q < R * R; q += blockDim.x) {
+        const int x = ox + q % R, y = oy + q / R;
+        const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
+        mus[q] = in ? mu[x + (long)y * nx] : (T)0;
+        zb[0][q] = in && zin_used ? zin[x + (long)y * nx] : (T)0;
+    }
+    for (int q = threadIdx.x; q < R * (R + 1); q += blockDim.x) {
+        int x = ox + q % (R + 1), y = oy + q / (R + 1);
+        vx[q] = (x >= 0 && x <= nx && y >= 0 && y < ny) ? v[face_index(g, 0, x, y, 0)] : (T)0;
+        x = ox + q % R;
+        y = oy + q / R;
+        vy[q] = (x >= 0 && x < nx && y >= 0 && y <= ny) ? v[face_index(g, 1, x, y, 0)] : (T)0;
+    }
+    // this thread's tile cells and their lower faces' gv
+    T gvr[NI][2];
+    int fx[NI], fy[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int q = threadIdx.x + i * UP_NT;
+        const int x = ox + H + q % UP_TS, y = oy + H + q / UP_TS;
+        const bool own = q < UP_TS * UP_TS && x < nx && y < ny;
+        fx[i] = own && x >= 1 ? face_index(g, 0, x, y, 0) : -1;
+        fy[i] = own && y >= 1 ? face_index(g, 1, x, y, 0) : -1;
+        gvr[i][0] = fx[i] >= 0 ? gv[fx[i]] : (T)0;
+        gvr[i][1] = fy[i] >= 0 ? gv[fy[i]] : (T)0;
+    }
+    const T inv_h = (T)(1.0 / g.h);
+    int cur = 0;
+    for (int b = bs, t = 0; b >= blo; --b, ++t) {
+        const bool has_z = b + 1 < k;
+        if (has_z) {
+            const T* xs = b + 1 == 0 ? rho : terms + (long)b * C;      // T_{b+1}
+            for (int q = threadIdx.x; q < X * X; q += blockDim.x) {
+                const int x = ox + H - 2 + q % X, y = oy + H - 2 + q / X;
+                xb[q] = (x >= 0 && x < nx && y >= 0 && y < ny) ? xs[x + (long)y * nx] : (T)0;
+            }
+        }
+        __syncthreads();
+        const T* z = zb[cur];
+        T* zo = zb[cur ^ 1];
+        const T dtb = (T)(dt / (b + 1 > 0 ? b + 1 : 1));
+        const int lo = b >= 0 ? 2 * (t + 1) : H, w = b >= 0 ? R - 4 * (t + 1) : UP_TS;
+        for (int q = threadIdx.x; q < w * w; q += blockDim.x) {
+            const int rx = lo + q % w, ry = lo + q / w, x = ox + rx, y = oy + ry;
+            if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
+            const int c = ry * R + rx;
+            T atz = 0;
+            if (has_z)
+                atz = up_AT_axis<T>(up_AT_axis<T>((T)0, z, c, 1, vx + ry * (R + 1) + rx, 1, x, nx), z, c, R,
+                                    vy + ry * R + rx, R, y, ny) * inv_h;
+            if (b >= 0)
+                zo[c] = dtb * (mus[c] + atz);
+            else if (grho)
+                grho[x + (long)y * nx] += mus[c] + atz;
+        }
+        if (has_z) {
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int q = threadIdx.x + i * UP_NT;
+                const int tx = q % UP_TS, ty = q / UP_TS, x = ox + H + tx, y = oy + H + ty;
+                const int c = (H + ty) * R + H + tx, e = (ty + 2) * X + tx + 2;
+                if (fx[i] >= 0) {
+                    const T vf = vx[(H + ty) * (R + 1) + H + tx];
+                    const T xf = up_face_lds(vf, xb[e - 2], xb[e - 1], xb[e], xb[e + 1], x, nx);
+                    gvr[i][0] += scale * (z[c] - z[c - 1]) * xf * inv_h;
+                }
+                if (fy[i] >= 0) {
+                    const T vf = vy[(H + ty) * R + H + tx];
+                    const T xf = up_face_lds(vf, xb[e - 2 * X], xb[e - X], xb[e], xb[e + X], y, ny);
+                    gvr[i][1] += scale * (z[c] - z[c - R]) * xf * inv_h;
+                }
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    if (blo >= 0) {
+        for (int q = threadIdx.x; q < UP_TS * UP_TS; q += blockDim.x) {
+            const int x = ox + H + q % UP_TS, y = oy + H + q / UP_TS;
+            if (x < nx && y < ny) zout[x + (long)y * nx] = zb[cur][(H + q / UP_TS) * R + H + q % UP_TS];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        if (fx[i] >= 0) gv[fx[i]] = gvr[i][0];
+        if (fy[i] >= 0) gv[fy[i]] = gvr[i][1];
+    }
+}
+
+// After a series launched to nl: k = the first j <= nl with max|T_j| below
+// the threshold (nl when there is none), whether the series stopped, and,
+// when out is given, out = rho + T_1 + ... + T_k in that order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_up_close(UpCtl<T> ctl, int nl, typename UpBits<T>::U tolb,
+                                                  const T* __restrict__ rho, const T* __restrict__ terms,
+                                                  T* __restrict__ out, long C) {
+    int k = nl, found = 0;
+    for (int j = 0; j <= nl; ++j)
+        if (ctl.maxb[j] < tolb) {
+            k = j;
+            found = 1;
+            break;
+        }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *ctl.k = k;
+        *ctl.stopped = found || nl >= UP_KMAX;
+    }
+    if (!out) return;
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    T s = rho[c];
+    for (int j = 1; j <= k; ++j) s += terms[(long)(j - 1) * C + c];
+    out[c] = s;
 }
 
 // Buffers and launch sequences of the operator on one grid.
@@ -235,6 +538,7 @@ struct UpwindExp {
         z[1] = A.template take<T>(ncell);
         ctl.maxb = A.template take<U>(UP_KMAX + 1);
         ctl.k = A.template take<int>(1);
+        ctl.stopped = A.template take<int>(1);
     }
     const T* term(const T* rho, int j, long C) const { return j == 0 ? rho : terms + (long)(j - 1) * C; }
 
@@ -246,8 +550,30 @@ struct UpwindExp {
         const long C = g.ncell;
         k_fill<U><<<1, 64, 0, st>>>(UP_KMAX + 1, ctl.maxb, (U)0);
         const U tolb = UpBits<T>::of((T)UP_TOL);
-        const int nb = blocks_for(C, 256);
         nl = nl < 0 ? 0 : (nl > UP_KMAX ? UP_KMAX : nl);
+        if constexpr (D == 2) {
+            const dim3 tiles(blocks_for(g.n[0], UP_TS), blocks_for(g.n[1], UP_TS));
+            for (int j0 = 1; j0 == 1 || j0 <= nl; j0 += UP_M) {
+                const int nt = nl - j0 + 1 < UP_M ? nl - j0 + 1 : UP_M;   // 0 only when nl = 0
+                auto launch = [&] {
+                    k_up_fwd_block<T><<<tiles, UP_NT, 0, st>>>(g, dt, j0, nt, j0 == 1 ? rho : term(rho, j0 - 1, C),
+                                                               v, terms, ctl, tolb);
+                };
+                if (tr)
+                    traced(*tr, st, TR_UP_TERM,
+                           nt * term_bytes(g) + (j0 == 1 ? copy_bytes(g, out != nullptr) : 0.0), launch);
+                else
+                    launch();
+            }
+            k_up_close<T><<<blocks_for(C, 256), 256, 0, st>>>(ctl, nl, tolb, rho, terms, out, C);
+        } else {
+            series_terms(g, dt, rho, v, out, st, nl, tolb);
+        }
+    }
+    // 3D: one launch per term over the whole grid, the sum added in each
+    void series_terms(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st, int nl, U tolb) {
+        const long C = g.ncell;
+        const int nb = blocks_for(C, 256);
         for (int j = 0; j <= nl; ++j) {
             auto launch = [&] {
                 k_up_term<T, D><<<nb, 256, 0, st>>>(g, j ? (T)(dt / (j * g.h)) : (T)0, j,
@@ -261,6 +587,7 @@ struct UpwindExp {
             else
                 launch();
         }
+        k_up_close<T><<<1, 64, 0, st>>>(ctl, nl, tolb, rho, terms, nullptr, C);
     }
     // The method's bytes of one working term: T_{j-1} in, T_j out, the sum read and written per cell, v
     // per face; of the first launch (j = 0): rho in, and copied into the sum when there is one.
@@ -275,16 +602,13 @@ struct UpwindExp {
         tr = keep;
     }
     // k and the stopped flag of the last series (launched to nl) into device ints
-    void record(int nl, int* k_out, int* ok_out, hipStream_t st) {
-        k_up_record<T><<<1, 64, 0, st>>>(ctl, nl, UpBits<T>::of((T)UP_TOL), k_out, ok_out);
-    }
+    void record(int* k_out, int* ok_out, hipStream_t st) { k_up_record<T><<<1, 64, 0, st>>>(ctl, k_out, ok_out); }
     // grho += (dA/drho)^T mu (grho may be null); gv = base + scale (dA/dv)^T mu
     // on interior faces, 0 on walls (base may be null).  k_known >= 0: the
     // series of (rho, v) is known to stop at that k (the forward sweep of the
     // same trajectory measured it), so exactly the needed launches are made.
     void adjoint(const Grid& g, double dt, const T* mu, const T* rho, const T* v, T* grho, T* gv, const T* base,
                  T scale, hipStream_t st, int k_known = -1) {
-        const long C = g.ncell;
         const int nl = k_known >= 0 ? k_known : UP_KMAX;
         // with k unknown the launches past the stop cannot be told apart: such calls are not recorded
         Tracer* keep = tr;
@@ -292,9 +616,24 @@ struct UpwindExp {
         series(g, dt, rho, v, nullptr, st, nl);
         tr = keep;
         k_up_gv_init<T><<<blocks_for(g.nface, 256), 256, 0, st>>>(g, base, gv);
+        const int top = (nl < UP_KMAX ? nl : UP_KMAX) - 1;
+        if constexpr (D == 2) {
+            const dim3 tiles(blocks_for(g.n[0], UP_TS), blocks_for(g.n[1], UP_TS));
+            int p = 0;
+            for (int b0 = top; b0 >= -1; b0 -= UP_M, p ^= 1)
+                k_up_adj_block<T><<<tiles, UP_NT, 0, st>>>(g, dt, b0, mu, z[p], z[p ^ 1], rho, terms, v, grho, gv,
+                                                           scale, ctl.k);
+        } else {
+            adjoint_steps(g, dt, mu, rho, v, grho, gv, scale, st, top);
+        }
+    }
+    // 3D: one launch per step of the recursion over the whole grid
+    void adjoint_steps(const Grid& g, double dt, const T* mu, const T* rho, const T* v, T* grho, T* gv, T scale,
+                       hipStream_t st, int top) {
+        const long C = g.ncell;
         const int nb = blocks_for(C, 256);
         const T inv_h = (T)(1.0 / g.h);
-        for (int b = (nl < UP_KMAX ? nl : UP_KMAX) - 1; b >= -1; --b)
+        for (int b = top; b >= -1; --b)
             k_up_adj<T, D><<<nb, 256, 0, st>>>(g, (T)(dt / (b + 1 > 0 ? b + 1 : 1)), inv_h, b, mu, z[(b + 1) & 1],
                                                 b >= 0 ? z[b & 1] : nullptr, term(rho, b + 1, C), v, grho, gv,
                                                 scale, ctl.k);

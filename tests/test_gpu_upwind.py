@@ -32,7 +32,7 @@ def _fields(n, rng, cfl, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("n,cfl", [((16, 12), 1.0), ((33, 17), 2.5), ((8, 6, 10), 1.5), ((4, 4), 0.8),
-                                   ((24, 20, 16), 2.0)])
+                                   ((24, 20, 16), 2.0), ((70, 41), 2.5), ((128, 128), 2.0)])
 def test_upwind_operator_and_adjoints(n, cfl, prec):
     S, ctx, g = _ctx(n, 1, prec)
     rng = np.random.default_rng(51)
@@ -55,6 +55,29 @@ def test_upwind_operator_and_adjoints(n, cfl, prec):
     # one, the difference is the last term, below 1e-5 of the field
     assert rel(to_np(gr), upwind.advect_up_T(g, mu, rho, v, g.h)) <= TOL[prec]
     assert rel(to_np(gv), upwind.advect_up_dv_T(g, mu, rho, v, g.h)) <= TOL[prec]
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [(20, 14), (6, 6, 5)])
+def test_upwind_series_at_the_term_cap(n, prec):
+    """A flow fast enough that no term up to the 48th passes the test: every
+    form sums T_0 .. T_48.  The terms grow to about 1e4 times the sum, so the
+    mixed form is held against the largest term."""
+    S, ctx, g = _ctx(n, 1, prec)
+    rng = np.random.default_rng(55)
+    rho, v = _fields(n, rng, 6.0, prec)
+    out = empty(g.ncell, prec)
+    flag(f"upwind cap n={n} {prec}")
+    k = S.stfas_op_upwind(ctx, to_dev(rho, prec), to_dev(v, prec), out)
+    terms, k_ref = upwind.series(g, rho, v, g.h)
+    assert k_ref == upwind.KMAX and k == upwind.KMAX
+    ref = np.sum(terms, axis=0)
+    if prec == "fp64":
+        assert rel(to_np(out), ref) <= 1e-10
+    else:
+        big = max(np.abs(t).max() for t in terms)
+        assert np.abs(to_np(out) - ref).max() <= 1e-5 * big
     ctx.destroy()
 
 
