@@ -201,24 +201,6 @@ __global__ void __launch_bounds__(256) k_up_adj(Grid g, T dtb, T inv_h, int b, c
     }
 }
 
-// The last series' k and whether it stopped, into the caller's words.
-template <typename T>
-__global__ void k_up_record(UpCtl<T> ctl, int* __restrict__ k_out, int* __restrict__ ok_out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    *k_out = *ctl.k;
-    *ok_out = *ctl.stopped;
-}
-
-// gv = base (or 0) on interior faces, 0 on walls.
-template <typename T>
-__global__ void k_up_gv_init(Grid g, const T* __restrict__ base, T* __restrict__ gv) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= g.nface) return;
-    int a, i, j, k;
-    face_decode(g, f, a, i, j, k);
-    gv[f] = face_interior(g, a, i, j, k) && base ? base[f] : (T)0;
-}
-
 // ---------------------------------------------------------------- 2D: several terms per launch
 //
 // On a 2D grid one term is a few microseconds of work behind a launch, so a
@@ -252,6 +234,25 @@ __device__ inline void fold_term_maxima(T (*wm)[UP_NT / 64], int nt, int j0, typ
     if (bb > __hip_atomic_load(maxb + j0 + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(maxb + j0 + t, bb);
 }
 
+// dst[q] = value(q) for q < n (n <= NMAX), q = threadIdx.x + i UP_NT: a
+// thread issues all of its loads before its first LDS store, so the load
+// latencies overlap.
+template <int NMAX, typename T, typename F>
+__device__ inline void stage_lds(T* dst, int n, F value) {
+    constexpr int K = (NMAX + UP_NT - 1) / UP_NT;
+    T r[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int q = threadIdx.x + i * UP_NT;
+        r[i] = q < n ? value(q) : (T)0;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int q = threadIdx.x + i * UP_NT;
+        if (q < n) dst[q] = r[i];
+    }
+}
+
 template <typename T>
 __device__ inline T wave_max(T m) {
 #pragma unroll
@@ -282,27 +283,28 @@ __global__ void __launch_bounds__(UP_NT) k_up_fwd_block(Grid g, double dt, int j
     __shared__ T vy[(R + 1) * R];     // y-face at (rx, ry): vy[ry R + rx], ry in [0, R]
     __shared__ T wm[UP_M + 1][UP_NT / 64];
     int stop = 0;   // an earlier launch's term (T_0 .. T_{j0-1}) passed the test
-    for (int j = threadIdx.x; j0 > 1 && j < j0; j += blockDim.x) stop |= ctl.maxb[j] < tolb;
+    for (int j = threadIdx.x; j0 > 1 && j < j0; j += UP_NT) stop |= ctl.maxb[j] < tolb;
     if (__syncthreads_or(stop)) return;
     const int nx = g.n[0], ny = g.n[1];
     const long C = g.ncell;
     const int ox = blockIdx.x * UP_TS - H, oy = blockIdx.y * UP_TS - H;
-    for (int q = threadIdx.x; q < R * R; q += blockDim.x) {
+    stage_lds<R * R>(buf[0], R * R, [&](int q) {
         const int x = ox + q % R, y = oy + q / R;
-        buf[0][q] = (x >= 0 && x < nx && y >= 0 && y < ny) ? prev[x + (long)y * nx] : (T)0;
-    }
-    for (int q = threadIdx.x; q < R * (R + 1); q += blockDim.x) {
-        int x = ox + q % (R + 1), y = oy + q / (R + 1);
-        vx[q] = (x >= 0 && x <= nx && y >= 0 && y < ny) ? v[face_index(g, 0, x, y, 0)] : (T)0;
-        x = ox + q % R;
-        y = oy + q / R;
-        vy[q] = (x >= 0 && x < nx && y >= 0 && y <= ny) ? v[face_index(g, 1, x, y, 0)] : (T)0;
-    }
+        return (x >= 0 && x < nx && y >= 0 && y < ny) ? prev[x + (long)y * nx] : (T)0;
+    });
+    stage_lds<R * (R + 1)>(vx, R * (R + 1), [&](int q) {
+        const int x = ox + q % (R + 1), y = oy + q / (R + 1);
+        return (x >= 0 && x <= nx && y >= 0 && y < ny) ? v[face_index(g, 0, x, y, 0)] : (T)0;
+    });
+    stage_lds<(R + 1) * R>(vy, (R + 1) * R, [&](int q) {
+        const int x = ox + q % R, y = oy + q / R;
+        return (x >= 0 && x < nx && y >= 0 && y <= ny) ? v[face_index(g, 1, x, y, 0)] : (T)0;
+    });
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (j0 == 1) {   // this launch also measures T_0
         T m = 0;
-        for (int q = threadIdx.x; q < UP_TS * UP_TS; q += blockDim.x) {
+        for (int q = threadIdx.x; q < UP_TS * UP_TS; q += UP_NT) {
             const int rx = H + q % UP_TS, ry = H + q / UP_TS;
             if (ox + rx < nx && oy + ry < ny) m = fmax(m, fabs(buf[0][ry * R + rx]));
         }
@@ -317,7 +319,7 @@ __global__ void __launch_bounds__(UP_NT) k_up_fwd_block(Grid g, double dt, int j
         const T* p = buf[cur];
         T* o = buf[cur ^ 1];
         T m = 0;
-        for (int q = threadIdx.x; q < w * w; q += blockDim.x) {
+        for (int q = threadIdx.x; q < w * w; q += UP_NT) {
             const int rx = lo + q % w, ry = lo + q / w, x = ox + rx, y = oy + ry;
             if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
             const int c = ry * R + rx;
@@ -407,19 +409,22 @@ __global__ void __launch_bounds__(UP_NT) k_up_adj_block(Grid g, double dt, int b
     const long C = g.ncell;
     const int ox = blockIdx.x * UP_TS - H, oy = blockIdx.y * UP_TS - H;
     const bool zin_used = bs + 1 < k;
-    for (int q = threadIdx.x; q < R * R; q += blockDim.x) {
+    stage_lds<R * R>(mus, R * R, [&](int q) {
         const int x = ox + q % R, y = oy + q / R;
-        const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
-        mus[q] = in ? mu[x + (long)y * nx] : (T)0;
-        zb[0][q] = in && zin_used ? zin[x + (long)y * nx] : (T)0;
-    }
-    for (int q = threadIdx.x; q < R * (R + 1); q += blockDim.x) {
-        int x = ox + q % (R + 1), y = oy + q / (R + 1);
-        vx[q] = (x >= 0 && x <= nx && y >= 0 && y < ny) ? v[face_index(g, 0, x, y, 0)] : (T)0;
-        x = ox + q % R;
-        y = oy + q / R;
-        vy[q] = (x >= 0 && x < nx && y >= 0 && y <= ny) ? v[face_index(g, 1, x, y, 0)] : (T)0;
-    }
+        return (x >= 0 && x < nx && y >= 0 && y < ny) ? mu[x + (long)y * nx] : (T)0;
+    });
+    stage_lds<R * R>(zb[0], R * R, [&](int q) {
+        const int x = ox + q % R, y = oy + q / R;
+        return (zin_used && x >= 0 && x < nx && y >= 0 && y < ny) ? zin[x + (long)y * nx] : (T)0;
+    });
+    stage_lds<R * (R + 1)>(vx, R * (R + 1), [&](int q) {
+        const int x = ox + q % (R + 1), y = oy + q / (R + 1);
+        return (x >= 0 && x <= nx && y >= 0 && y < ny) ? v[face_index(g, 0, x, y, 0)] : (T)0;
+    });
+    stage_lds<(R + 1) * R>(vy, (R + 1) * R, [&](int q) {
+        const int x = ox + q % R, y = oy + q / R;
+        return (x >= 0 && x < nx && y >= 0 && y <= ny) ? v[face_index(g, 1, x, y, 0)] : (T)0;
+    });
     // this thread's tile cells and their lower faces' gv
     T gvr[NI][2];
     int fx[NI], fy[NI];
@@ -439,17 +444,17 @@ __global__ void __launch_bounds__(UP_NT) k_up_adj_block(Grid g, double dt, int b
         const bool has_z = b + 1 < k;
         if (has_z) {
             const T* xs = b + 1 == 0 ? rho : terms + (long)b * C;      // T_{b+1}
-            for (int q = threadIdx.x; q < X * X; q += blockDim.x) {
+            stage_lds<X * X>(xb, X * X, [&](int q) {
                 const int x = ox + H - 2 + q % X, y = oy + H - 2 + q / X;
-                xb[q] = (x >= 0 && x < nx && y >= 0 && y < ny) ? xs[x + (long)y * nx] : (T)0;
-            }
+                return (x >= 0 && x < nx && y >= 0 && y < ny) ? xs[x + (long)y * nx] : (T)0;
+            });
         }
         __syncthreads();
         const T* z = zb[cur];
         T* zo = zb[cur ^ 1];
         const T dtb = (T)(dt / (b + 1 > 0 ? b + 1 : 1));
         const int lo = b >= 0 ? 2 * (t + 1) : H, w = b >= 0 ? R - 4 * (t + 1) : UP_TS;
-        for (int q = threadIdx.x; q < w * w; q += blockDim.x) {
+        for (int q = threadIdx.x; q < w * w; q += UP_NT) {
             const int rx = lo + q % w, ry = lo + q / w, x = ox + rx, y = oy + ry;
             if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
             const int c = ry * R + rx;
@@ -484,7 +489,7 @@ __global__ void __launch_bounds__(UP_NT) k_up_adj_block(Grid g, double dt, int b
         cur ^= 1;
     }
     if (blo >= 0) {
-        for (int q = threadIdx.x; q < UP_TS * UP_TS; q += blockDim.x) {
+        for (int q = threadIdx.x; q < UP_TS * UP_TS; q += UP_NT) {
             const int x = ox + H + q % UP_TS, y = oy + H + q / UP_TS;
             if (x < nx && y < ny) zout[x + (long)y * nx] = zb[cur][(H + q / UP_TS) * R + H + q % UP_TS];
         }
@@ -496,13 +501,34 @@ __global__ void __launch_bounds__(UP_NT) k_up_adj_block(Grid g, double dt, int b
     }
 }
 
+// What the closing launch of a series also does: the caller's copies of k
+// and of the stop flag (either may be null), and gv = base (or 0) on interior
+// faces and 0 on walls when gv is given (the start of an adjoint).
+template <typename T>
+struct UpClose {
+    int* k_out = nullptr;
+    int* ok_out = nullptr;
+    const T* gv_base = nullptr;
+    T* gv = nullptr;
+};
+
 // After a series launched to nl: k = the first j <= nl with max|T_j| below
 // the threshold (nl when there is none), whether the series stopped, and,
-// when out is given, out = rho + T_1 + ... + T_k in that order.
+// when out is given, out = rho + T_1 + ... + T_k in that order.  It also
+// clears `next`, the threshold words of the following series (the words
+// alternate between two sets, so no launch clears the set in use), and does
+// the extras of `x`.
 template <typename T>
-__global__ void __launch_bounds__(256) k_up_close(UpCtl<T> ctl, int nl, typename UpBits<T>::U tolb,
-                                                  const T* __restrict__ rho, const T* __restrict__ terms,
-                                                  T* __restrict__ out, long C) {
+__global__ void __launch_bounds__(256) k_up_close(Grid g, UpCtl<T> ctl, typename UpBits<T>::U* __restrict__ next,
+                                                  int nl, typename UpBits<T>::U tolb, const T* __restrict__ rho,
+                                                  const T* __restrict__ terms, T* __restrict__ out, UpClose<T> x) {
+    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id <= UP_KMAX) next[id] = 0;
+    if (x.gv && id < g.nface) {
+        int a, i, j, kk;
+        face_decode(g, (int)id, a, i, j, kk);
+        x.gv[id] = face_interior(g, a, i, j, kk) && x.gv_base ? x.gv_base[id] : (T)0;
+    }
     int k = nl, found = 0;
     for (int j = 0; j <= nl; ++j)
         if (ctl.maxb[j] < tolb) {
@@ -510,16 +536,18 @@ __global__ void __launch_bounds__(256) k_up_close(UpCtl<T> ctl, int nl, typename
             found = 1;
             break;
         }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (id == 0) {
+        const int stopped = found || nl >= UP_KMAX;
         *ctl.k = k;
-        *ctl.stopped = found || nl >= UP_KMAX;
+        *ctl.stopped = stopped;
+        if (x.k_out) *x.k_out = k;
+        if (x.ok_out) *x.ok_out = stopped;
     }
-    if (!out) return;
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    T s = rho[c];
-    for (int j = 1; j <= k; ++j) s += terms[(long)(j - 1) * C + c];
-    out[c] = s;
+    const long C = g.ncell;
+    if (!out || id >= C) return;
+    T s = rho[id];
+    for (int j = 1; j <= k; ++j) s += terms[(long)(j - 1) * C + id];
+    out[id] = s;
 }
 
 // Buffers and launch sequences of the operator on one grid.
@@ -529,6 +557,9 @@ struct UpwindExp {
     T* terms = nullptr;   // [UP_KMAX][ncell]: T_1 .. T_KMAX
     T* z[2] = {nullptr, nullptr};
     UpCtl<T> ctl{};
+    U* maxb_set[2] = {nullptr, nullptr};   // the threshold words of alternate series
+    int par = 0;
+    bool primed = false;                   // both sets cleared once
     Tracer* tr = nullptr;   // records the working term launches (j >= 1) when tracing is on
 
     template <typename Ar>
@@ -536,7 +567,9 @@ struct UpwindExp {
         terms = A.template take<T>((size_t)UP_KMAX * ncell);
         z[0] = A.template take<T>(ncell);
         z[1] = A.template take<T>(ncell);
-        ctl.maxb = A.template take<U>(UP_KMAX + 1);
+        maxb_set[0] = A.template take<U>(UP_KMAX + 1);
+        maxb_set[1] = A.template take<U>(UP_KMAX + 1);
+        ctl.maxb = maxb_set[0];
         ctl.k = A.template take<int>(1);
         ctl.stopped = A.template take<int>(1);
     }
@@ -546,9 +579,18 @@ struct UpwindExp {
     // device.  Launches terms 0..nl only: when the series has not stopped by
     // then (record() tells), the result is truncated and the caller runs it
     // again with a larger nl.
-    void series(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st, int nl = UP_KMAX) {
+    void series(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st, int nl = UP_KMAX,
+                UpClose<T> x = {}) {
         const long C = g.ncell;
-        k_fill<U><<<1, 64, 0, st>>>(UP_KMAX + 1, ctl.maxb, (U)0);
+        if (!primed) {
+            k_fill<U><<<1, 64, 0, st>>>(UP_KMAX + 1, maxb_set[0], (U)0);
+            k_fill<U><<<1, 64, 0, st>>>(UP_KMAX + 1, maxb_set[1], (U)0);
+            primed = true;
+        }
+        ctl.maxb = maxb_set[par];
+        U* next = maxb_set[par ^ 1];
+        par ^= 1;
+        const long nclose = std::max<long>(std::max<long>(out ? C : 0, UP_KMAX + 1), x.gv ? g.nface : 0);
         const U tolb = UpBits<T>::of((T)UP_TOL);
         nl = nl < 0 ? 0 : (nl > UP_KMAX ? UP_KMAX : nl);
         if constexpr (D == 2) {
@@ -565,9 +607,10 @@ struct UpwindExp {
                 else
                     launch();
             }
-            k_up_close<T><<<blocks_for(C, 256), 256, 0, st>>>(ctl, nl, tolb, rho, terms, out, C);
+            k_up_close<T><<<blocks_for(nclose, 256), 256, 0, st>>>(g, ctl, next, nl, tolb, rho, terms, out, x);
         } else {
             series_terms(g, dt, rho, v, out, st, nl, tolb);
+            k_up_close<T><<<blocks_for(nclose, 256), 256, 0, st>>>(g, ctl, next, nl, tolb, rho, terms, nullptr, x);
         }
     }
     // 3D: one launch per term over the whole grid, the sum added in each
@@ -587,22 +630,23 @@ struct UpwindExp {
             else
                 launch();
         }
-        k_up_close<T><<<1, 64, 0, st>>>(ctl, nl, tolb, rho, terms, nullptr, C);
     }
     // The method's bytes of one working term: T_{j-1} in, T_j out, the sum read and written per cell, v
     // per face; of the first launch (j = 0): rho in, and copied into the sum when there is one.
     static double term_bytes(const Grid& g) { return (double)sizeof(T) * (4.0 * g.ncell + (double)g.nface); }
     static double copy_bytes(const Grid& g, bool sum) { return (double)sizeof(T) * g.ncell * (sum ? 2.0 : 1.0); }
     // record = false: the call's launches are not recorded by the tracer (the caller will not learn k)
+    // k_out, ok_out (device ints, may be null): the series' k and whether it stopped within the nl terms
     void forward(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st, int nl = UP_KMAX,
-                 bool record = false) {
+                 bool record = false, int* k_out = nullptr, int* ok_out = nullptr) {
         Tracer* keep = tr;
         if (!record) tr = nullptr;
-        series(g, dt, rho, v, out, st, nl);
+        UpClose<T> x;
+        x.k_out = k_out;
+        x.ok_out = ok_out;
+        series(g, dt, rho, v, out, st, nl, x);
         tr = keep;
     }
-    // k and the stopped flag of the last series (launched to nl) into device ints
-    void record(int* k_out, int* ok_out, hipStream_t st) { k_up_record<T><<<1, 64, 0, st>>>(ctl, k_out, ok_out); }
     // grho += (dA/drho)^T mu (grho may be null); gv = base + scale (dA/dv)^T mu
     // on interior faces, 0 on walls (base may be null).  k_known >= 0: the
     // series of (rho, v) is known to stop at that k (the forward sweep of the
@@ -613,9 +657,11 @@ struct UpwindExp {
         // with k unknown the launches past the stop cannot be told apart: such calls are not recorded
         Tracer* keep = tr;
         if (k_known < 0) tr = nullptr;
-        series(g, dt, rho, v, nullptr, st, nl);
+        UpClose<T> x;
+        x.gv_base = base;
+        x.gv = gv;
+        series(g, dt, rho, v, nullptr, st, nl, x);
         tr = keep;
-        k_up_gv_init<T><<<blocks_for(g.nface, 256), 256, 0, st>>>(g, base, gv);
         const int top = (nl < UP_KMAX ? nl : UP_KMAX) - 1;
         if constexpr (D == 2) {
             const dim3 tiles(blocks_for(g.n[0], UP_TS), blocks_for(g.n[1], UP_TS));

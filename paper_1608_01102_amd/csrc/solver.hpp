@@ -1174,8 +1174,8 @@ public:
         int from = 0;
         while (from < N) {
             for (int i = from; i < N; ++i) {
-                up.forward(L[0], P.dt, r + i * C, vs + i * F, r + (i + 1) * C, st, nl[i], true);
-                up.record(up_kd + i, up_okd + i, st);
+                up.forward(L[0], P.dt, r + i * C, vs + i * F, r + (i + 1) * C, st, nl[i], true, up_kd + i,
+                           up_okd + i);
             }
             HCK(hipMemcpyAsync(kh.data() + from, up_kd + from, (N - from) * sizeof(int), hipMemcpyDeviceToHost, st));
             HCK(hipMemcpyAsync(okh.data() + from, up_okd + from, (N - from) * sizeof(int), hipMemcpyDeviceToHost,
