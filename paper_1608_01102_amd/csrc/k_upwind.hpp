@@ -211,16 +211,19 @@ __global__ void __launch_bounds__(256) k_up_adj(Grid g, T dtb, T inv_h, int b, c
 // with a halo of 2 UP_M cells and each term is computed on the region shrunk
 // by two more cells, in LDS.  Every term at every cell is the same expression
 // of the same values as in the one-term launch; the halo cells are computed
-// again by the neighbouring tiles.
+// again by the neighbouring tiles.  A launch block has one thread per cell
+// of the loaded 32 x 32 region.
 //
 // A launch cannot know whether one of its own terms ends the series (that is
 // a maximum over all tiles), so it computes all of its terms and the sum is
 // formed after the last launch (k_up_close), in the order of the one-term
 // launches: rho, then T_1, T_2, ... T_k.
 
-constexpr int UP_M = 4;          // terms (adjoint steps) per launch
-constexpr int UP_TS = 16;        // tile edge in cells
-constexpr int UP_NT = 512;       // threads per launch block
+constexpr int UP_M = 4;                          // terms (adjoint steps) per launch
+constexpr int UP_TS = 16;                        // tile edge in cells
+constexpr int UP_R = UP_TS + 4 * UP_M;           // edge of the loaded region (tile + halo)
+constexpr int UP_NT = UP_R * UP_R;               // one thread per region cell
+static_assert(UP_NT <= 1024, "one thread per cell of the loaded region");
 
 // Fold the per-wave maxima of nt terms (wm[t][wave]) into ctl words j0 .. j0+nt-1.
 template <typename T>
@@ -277,7 +280,7 @@ template <typename T>
 __global__ void __launch_bounds__(UP_NT) k_up_fwd_block(Grid g, double dt, int j0, int nt, const T* __restrict__ prev,
                                                         const T* __restrict__ v, T* __restrict__ terms, UpCtl<T> ctl,
                                                         typename UpBits<T>::U tolb) {
-    constexpr int H = 2 * UP_M, R = UP_TS + 2 * H;
+    constexpr int H = 2 * UP_M, R = UP_R;
     __shared__ T buf[2][R * R];
     __shared__ T vx[R * (R + 1)];     // x-face at (rx, ry): vx[ry (R+1) + rx], rx in [0, R]
     __shared__ T vy[(R + 1) * R];     // y-face at (rx, ry): vy[ry R + rx], ry in [0, R]
@@ -301,28 +304,25 @@ __global__ void __launch_bounds__(UP_NT) k_up_fwd_block(Grid g, double dt, int j
         return (x >= 0 && x < nx && y >= 0 && y <= ny) ? v[face_index(g, 1, x, y, 0)] : (T)0;
     });
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (j0 == 1) {   // this launch also measures T_0
-        T m = 0;
-        for (int q = threadIdx.x; q < UP_TS * UP_TS; q += UP_NT) {
-            const int rx = H + q % UP_TS, ry = H + q / UP_TS;
-            if (ox + rx < nx && oy + ry < ny) m = fmax(m, fabs(buf[0][ry * R + rx]));
-        }
-        m = wave_max(m);
-        if (lane == 0) wm[0][wave] = m;
-    }
+    // this thread's region cell; its maxima of |T_j| when it is a tile cell
+    // (mt[0]: T_0, measured by the first launch), reduced after the last term
+    const int rx = threadIdx.x % R, ry = threadIdx.x / R, x = ox + rx, y = oy + ry, c = threadIdx.x;
+    const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
+    const bool mine = in && rx >= H && rx < H + UP_TS && ry >= H && ry < H + UP_TS;
+    T mt[UP_M + 1];
+#pragma unroll
+    for (int t = 0; t <= UP_M; ++t) mt[t] = 0;
+    if (j0 == 1 && mine) mt[0] = fabs(buf[0][c]);
     int cur = 0;
-    for (int t = 1; t <= nt; ++t) {
+#pragma unroll
+    for (int t = 1; t <= UP_M; ++t) {
+        if (t > nt) break;
         const int j = j0 - 1 + t;
         const T coef = (T)(dt / (j * g.h));
-        const int lo = 2 * t, w = R - 4 * t;
         const T* p = buf[cur];
         T* o = buf[cur ^ 1];
-        T m = 0;
-        for (int q = threadIdx.x; q < w * w; q += UP_NT) {
-            const int rx = lo + q % w, ry = lo + q / w, x = ox + rx, y = oy + ry;
-            if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
-            const int c = ry * R + rx;
+        // exact on the region shrunk by 2t (each term reads two cells along each axis)
+        if (in && rx >= 2 * t && rx < R - 2 * t && ry >= 2 * t && ry < R - 2 * t) {
             T acc = 0;
             if (x >= 1) {                          // x: lower face x
                 const T vf = vx[ry * (R + 1) + rx];
@@ -342,15 +342,19 @@ __global__ void __launch_bounds__(UP_NT) k_up_fwd_block(Grid g, double dt, int j
             }
             const T val = coef * acc;
             o[c] = val;
-            if (rx >= H && rx < H + UP_TS && ry >= H && ry < H + UP_TS) {
+            if (mine) {
                 terms[(long)(j - 1) * C + x + (long)y * nx] = val;
-                m = fmax(m, fabs(val));
+                mt[t] = fabs(val);
             }
         }
-        m = wave_max(m);
-        if (lane == 0) wm[t][wave] = m;
         __syncthreads();
         cur ^= 1;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = 0; t <= UP_M; ++t) {
+        const T m = wave_max(mt[t]);
+        if (lane == 0) wm[t][wave] = m;
     }
     __syncthreads();
     if (j0 == 1) fold_term_maxima<T>(wm, nt + 1, 0, ctl.maxb);
@@ -394,8 +398,7 @@ __global__ void __launch_bounds__(UP_NT) k_up_adj_block(Grid g, double dt, int b
                                                         const T* __restrict__ rho, const T* __restrict__ terms,
                                                         const T* __restrict__ v, T* __restrict__ grho,
                                                         T* __restrict__ gv, T scale, const int* __restrict__ kp) {
-    constexpr int H = 2 * UP_M, R = UP_TS + 2 * H, X = UP_TS + 4;
-    constexpr int NI = (UP_TS * UP_TS + UP_NT - 1) / UP_NT;
+    constexpr int H = 2 * UP_M, R = UP_R, X = UP_TS + 4;
     __shared__ T zb[2][R * R];
     __shared__ T mus[R * R];
     __shared__ T vx[R * (R + 1)];
@@ -425,19 +428,15 @@ __global__ void __launch_bounds__(UP_NT) k_up_adj_block(Grid g, double dt, int b
         const int x = ox + q % R, y = oy + q / R;
         return (x >= 0 && x < nx && y >= 0 && y <= ny) ? v[face_index(g, 1, x, y, 0)] : (T)0;
     });
-    // this thread's tile cells and their lower faces' gv
-    T gvr[NI][2];
-    int fx[NI], fy[NI];
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const int q = threadIdx.x + i * UP_NT;
-        const int x = ox + H + q % UP_TS, y = oy + H + q / UP_TS;
-        const bool own = q < UP_TS * UP_TS && x < nx && y < ny;
-        fx[i] = own && x >= 1 ? face_index(g, 0, x, y, 0) : -1;
-        fy[i] = own && y >= 1 ? face_index(g, 1, x, y, 0) : -1;
-        gvr[i][0] = fx[i] >= 0 ? gv[fx[i]] : (T)0;
-        gvr[i][1] = fy[i] >= 0 ? gv[fy[i]] : (T)0;
-    }
+    // this thread's region cell; a tile cell also owns its lower faces' gv,
+    // gathered in registers over the steps
+    const int rx = threadIdx.x % R, ry = threadIdx.x / R, x = ox + rx, y = oy + ry, c = threadIdx.x;
+    const bool in = x >= 0 && x < nx && y >= 0 && y < ny;
+    const bool mine = in && rx >= H && rx < H + UP_TS && ry >= H && ry < H + UP_TS;
+    const int fx = mine && x >= 1 ? face_index(g, 0, x, y, 0) : -1;
+    const int fy = mine && y >= 1 ? face_index(g, 1, x, y, 0) : -1;
+    T gx = fx >= 0 ? gv[fx] : (T)0, gy = fy >= 0 ? gv[fy] : (T)0;
+    const int e = (ry - H + 2) * X + (rx - H + 2);     // the cell in xb (tile cells only)
     const T inv_h = (T)(1.0 / g.h);
     int cur = 0;
     for (int b = bs, t = 0; b >= blo; --b, ++t) {
@@ -445,19 +444,18 @@ __global__ void __launch_bounds__(UP_NT) k_up_adj_block(Grid g, double dt, int b
         if (has_z) {
             const T* xs = b + 1 == 0 ? rho : terms + (long)b * C;      // T_{b+1}
             stage_lds<X * X>(xb, X * X, [&](int q) {
-                const int x = ox + H - 2 + q % X, y = oy + H - 2 + q / X;
-                return (x >= 0 && x < nx && y >= 0 && y < ny) ? xs[x + (long)y * nx] : (T)0;
+                const int xx = ox + H - 2 + q % X, yy = oy + H - 2 + q / X;
+                return (xx >= 0 && xx < nx && yy >= 0 && yy < ny) ? xs[xx + (long)yy * nx] : (T)0;
             });
         }
         __syncthreads();
         const T* z = zb[cur];
         T* zo = zb[cur ^ 1];
         const T dtb = (T)(dt / (b + 1 > 0 ? b + 1 : 1));
-        const int lo = b >= 0 ? 2 * (t + 1) : H, w = b >= 0 ? R - 4 * (t + 1) : UP_TS;
-        for (int q = threadIdx.x; q < w * w; q += UP_NT) {
-            const int rx = lo + q % w, ry = lo + q / w, x = ox + rx, y = oy + ry;
-            if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
-            const int c = ry * R + rx;
+        // Z_b is exact on the region shrunk by 2 (t + 1); at b = -1 only the tile's grho is formed
+        const int lo = 2 * (t + 1);
+        const bool act = b >= 0 ? in && rx >= lo && rx < R - lo && ry >= lo && ry < R - lo : mine;
+        if (act) {
             T atz = 0;
             if (has_z)
                 atz = up_AT_axis<T>(up_AT_axis<T>((T)0, z, c, 1, vx + ry * (R + 1) + rx, 1, x, nx), z, c, R,
@@ -467,38 +465,24 @@ __global__ void __launch_bounds__(UP_NT) k_up_adj_block(Grid g, double dt, int b
             else if (grho)
                 grho[x + (long)y * nx] += mus[c] + atz;
         }
-        if (has_z) {
-#pragma unroll
-            for (int i = 0; i < NI; ++i) {
-                const int q = threadIdx.x + i * UP_NT;
-                const int tx = q % UP_TS, ty = q / UP_TS, x = ox + H + tx, y = oy + H + ty;
-                const int c = (H + ty) * R + H + tx, e = (ty + 2) * X + tx + 2;
-                if (fx[i] >= 0) {
-                    const T vf = vx[(H + ty) * (R + 1) + H + tx];
-                    const T xf = up_face_lds(vf, xb[e - 2], xb[e - 1], xb[e], xb[e + 1], x, nx);
-                    gvr[i][0] += scale * (z[c] - z[c - 1]) * xf * inv_h;
-                }
-                if (fy[i] >= 0) {
-                    const T vf = vy[(H + ty) * R + H + tx];
-                    const T xf = up_face_lds(vf, xb[e - 2 * X], xb[e - X], xb[e], xb[e + X], y, ny);
-                    gvr[i][1] += scale * (z[c] - z[c - R]) * xf * inv_h;
-                }
+        if (has_z && mine) {
+            if (fx >= 0) {
+                const T vf = vx[ry * (R + 1) + rx];
+                const T xf = up_face_lds(vf, xb[e - 2], xb[e - 1], xb[e], xb[e + 1], x, nx);
+                gx += scale * (z[c] - z[c - 1]) * xf * inv_h;
+            }
+            if (fy >= 0) {
+                const T vf = vy[ry * R + rx];
+                const T xf = up_face_lds(vf, xb[e - 2 * X], xb[e - X], xb[e], xb[e + X], y, ny);
+                gy += scale * (z[c] - z[c - R]) * xf * inv_h;
             }
         }
         __syncthreads();
         cur ^= 1;
     }
-    if (blo >= 0) {
-        for (int q = threadIdx.x; q < UP_TS * UP_TS; q += UP_NT) {
-            const int x = ox + H + q % UP_TS, y = oy + H + q / UP_TS;
-            if (x < nx && y < ny) zout[x + (long)y * nx] = zb[cur][(H + q / UP_TS) * R + H + q % UP_TS];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        if (fx[i] >= 0) gv[fx[i]] = gvr[i][0];
-        if (fy[i] >= 0) gv[fy[i]] = gvr[i][1];
-    }
+    if (blo >= 0 && mine) zout[x + (long)y * nx] = zb[cur][c];
+    if (fx >= 0) gv[fx] = gx;
+    if (fy >= 0) gv[fy] = gy;
 }
 
 // What the closing launch of a series also does: the caller's copies of k
@@ -529,13 +513,12 @@ __global__ void __launch_bounds__(256) k_up_close(Grid g, UpCtl<T> ctl, typename
         face_decode(g, (int)id, a, i, j, kk);
         x.gv[id] = face_interior(g, a, i, j, kk) && x.gv_base ? x.gv_base[id] : (T)0;
     }
-    int k = nl, found = 0;
-    for (int j = 0; j <= nl; ++j)
-        if (ctl.maxb[j] < tolb) {
-            k = j;
-            found = 1;
-            break;
-        }
+    // k: the lowest word below the threshold, one word per lane (nl <= 48 < 64)
+    const int lane = threadIdx.x & 63;
+    const bool below = lane <= nl && ctl.maxb[lane] < tolb;
+    const unsigned long long mask = __ballot(below);
+    const int found = mask != 0;
+    const int k = found ? __builtin_ctzll(mask) : nl;
     if (id == 0) {
         const int stopped = found || nl >= UP_KMAX;
         *ctl.k = k;
@@ -545,8 +528,18 @@ __global__ void __launch_bounds__(256) k_up_close(Grid g, UpCtl<T> ctl, typename
     }
     const long C = g.ncell;
     if (!out || id >= C) return;
+    // added in the order j = 1 .. k; four terms' loads issued together
     T s = rho[id];
-    for (int j = 1; j <= k; ++j) s += terms[(long)(j - 1) * C + id];
+    int j = 1;
+    for (; j + 3 <= k; j += 4) {
+        const T* t = terms + (long)(j - 1) * C + id;
+        const T a0 = t[0], a1 = t[C], a2 = t[2 * C], a3 = t[3 * C];
+        s += a0;
+        s += a1;
+        s += a2;
+        s += a3;
+    }
+    for (; j <= k; ++j) s += terms[(long)(j - 1) * C + id];
     out[id] = s;
 }
 
