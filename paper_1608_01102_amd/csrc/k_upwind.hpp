@@ -494,6 +494,7 @@ struct UpClose {
     int* ok_out = nullptr;
     const T* gv_base = nullptr;
     T* gv = nullptr;
+    int k_set = -1;   // >= 0: no series was launched; k is this (known) value
 };
 
 // After a series launched to nl: k = the first j <= nl with max|T_j| below
@@ -501,13 +502,13 @@ struct UpClose {
 // when out is given, out = rho + T_1 + ... + T_k in that order.  It also
 // clears `next`, the threshold words of the following series (the words
 // alternate between two sets, so no launch clears the set in use), and does
-// the extras of `x`.
+// the extras of `x`.  next may be null (nothing to clear).
 template <typename T>
 __global__ void __launch_bounds__(256) k_up_close(Grid g, UpCtl<T> ctl, typename UpBits<T>::U* __restrict__ next,
                                                   int nl, typename UpBits<T>::U tolb, const T* __restrict__ rho,
                                                   const T* __restrict__ terms, T* __restrict__ out, UpClose<T> x) {
     const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id <= UP_KMAX) next[id] = 0;
+    if (next && id <= UP_KMAX) next[id] = 0;
     if (x.gv && id < g.nface) {
         int a, i, j, kk;
         face_decode(g, (int)id, a, i, j, kk);
@@ -515,10 +516,10 @@ __global__ void __launch_bounds__(256) k_up_close(Grid g, UpCtl<T> ctl, typename
     }
     // k: the lowest word below the threshold, one word per lane (nl <= 48 < 64)
     const int lane = threadIdx.x & 63;
-    const bool below = lane <= nl && ctl.maxb[lane] < tolb;
+    const bool below = x.k_set < 0 && lane <= nl && ctl.maxb[lane] < tolb;
     const unsigned long long mask = __ballot(below);
-    const int found = mask != 0;
-    const int k = found ? __builtin_ctzll(mask) : nl;
+    const int found = x.k_set >= 0 || mask != 0;
+    const int k = x.k_set >= 0 ? x.k_set : (mask ? __builtin_ctzll(mask) : nl);
     if (id == 0) {
         const int stopped = found || nl >= UP_KMAX;
         *ctl.k = k;
@@ -549,6 +550,9 @@ struct UpwindExp {
     using U = typename UpBits<T>::U;
     T* terms = nullptr;   // [UP_KMAX][ncell]: T_1 .. T_KMAX
     T* z[2] = {nullptr, nullptr};
+    // 2D: the terms of every step of two density trajectories, [steps][UP_KMAX][ncell] each, so that an
+    // adjoint sweep over a trajectory whose forward sweep stored its terms launches no series
+    T* hist[2] = {nullptr, nullptr};
     UpCtl<T> ctl{};
     U* maxb_set[2] = {nullptr, nullptr};   // the threshold words of alternate series
     int par = 0;
@@ -556,8 +560,12 @@ struct UpwindExp {
     Tracer* tr = nullptr;   // records the working term launches (j >= 1) when tracing is on
 
     template <typename Ar>
-    void layout(Ar& A, long ncell) {
+    void layout(Ar& A, long ncell, int hist_steps = 0) {
         terms = A.template take<T>((size_t)UP_KMAX * ncell);
+        if (D == 2 && hist_steps > 0) {
+            hist[0] = A.template take<T>((size_t)hist_steps * UP_KMAX * ncell);
+            hist[1] = A.template take<T>((size_t)hist_steps * UP_KMAX * ncell);
+        }
         z[0] = A.template take<T>(ncell);
         z[1] = A.template take<T>(ncell);
         maxb_set[0] = A.template take<U>(UP_KMAX + 1);
@@ -567,14 +575,18 @@ struct UpwindExp {
         ctl.stopped = A.template take<int>(1);
     }
     const T* term(const T* rho, int j, long C) const { return j == 0 ? rho : terms + (long)(j - 1) * C; }
+    // where step i of trajectory `set` keeps its terms (null without stored trajectories)
+    T* hist_step(int set, int i, long C) const { return hist[set] ? hist[set] + (size_t)i * UP_KMAX * C : nullptr; }
 
     // terms T_1..T_k of rho (and their sum into out, unless null); k on the
     // device.  Launches terms 0..nl only: when the series has not stopped by
     // then (record() tells), the result is truncated and the caller runs it
     // again with a larger nl.
+    // tb (2D, may be null): where the terms go instead of the operator's own buffer
     void series(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st, int nl = UP_KMAX,
-                UpClose<T> x = {}) {
+                UpClose<T> x = {}, T* tb = nullptr) {
         const long C = g.ncell;
+        T* tt = tb ? tb : terms;
         if (!primed) {
             k_fill<U><<<1, 64, 0, st>>>(UP_KMAX + 1, maxb_set[0], (U)0);
             k_fill<U><<<1, 64, 0, st>>>(UP_KMAX + 1, maxb_set[1], (U)0);
@@ -591,8 +603,9 @@ struct UpwindExp {
             for (int j0 = 1; j0 == 1 || j0 <= nl; j0 += UP_M) {
                 const int nt = nl - j0 + 1 < UP_M ? nl - j0 + 1 : UP_M;   // 0 only when nl = 0
                 auto launch = [&] {
-                    k_up_fwd_block<T><<<tiles, UP_NT, 0, st>>>(g, dt, j0, nt, j0 == 1 ? rho : term(rho, j0 - 1, C),
-                                                               v, terms, ctl, tolb);
+                    k_up_fwd_block<T><<<tiles, UP_NT, 0, st>>>(g, dt, j0, nt,
+                                                               j0 == 1 ? rho : tt + (long)(j0 - 2) * C, v, tt,
+                                                               ctl, tolb);
                 };
                 if (tr)
                     traced(*tr, st, TR_UP_TERM,
@@ -600,7 +613,7 @@ struct UpwindExp {
                 else
                     launch();
             }
-            k_up_close<T><<<blocks_for(nclose, 256), 256, 0, st>>>(g, ctl, next, nl, tolb, rho, terms, out, x);
+            k_up_close<T><<<blocks_for(nclose, 256), 256, 0, st>>>(g, ctl, next, nl, tolb, rho, tt, out, x);
         } else {
             series_terms(g, dt, rho, v, out, st, nl, tolb);
             k_up_close<T><<<blocks_for(nclose, 256), 256, 0, st>>>(g, ctl, next, nl, tolb, rho, terms, nullptr, x);
@@ -630,23 +643,39 @@ struct UpwindExp {
     static double copy_bytes(const Grid& g, bool sum) { return (double)sizeof(T) * g.ncell * (sum ? 2.0 : 1.0); }
     // record = false: the call's launches are not recorded by the tracer (the caller will not learn k)
     // k_out, ok_out (device ints, may be null): the series' k and whether it stopped within the nl terms
+    // tb (2D, may be null): keep the terms there (a stored trajectory's step)
     void forward(const Grid& g, double dt, const T* rho, const T* v, T* out, hipStream_t st, int nl = UP_KMAX,
-                 bool record = false, int* k_out = nullptr, int* ok_out = nullptr) {
+                 bool record = false, int* k_out = nullptr, int* ok_out = nullptr, T* tb = nullptr) {
         Tracer* keep = tr;
         if (!record) tr = nullptr;
         UpClose<T> x;
         x.k_out = k_out;
         x.ok_out = ok_out;
-        series(g, dt, rho, v, out, st, nl, x);
+        series(g, dt, rho, v, out, st, nl, x, tb);
         tr = keep;
     }
     // grho += (dA/drho)^T mu (grho may be null); gv = base + scale (dA/dv)^T mu
     // on interior faces, 0 on walls (base may be null).  k_known >= 0: the
     // series of (rho, v) is known to stop at that k (the forward sweep of the
     // same trajectory measured it), so exactly the needed launches are made.
+    // stored (2D, with k_known): the terms of this series as its forward sweep kept them; no series is
+    // launched then
     void adjoint(const Grid& g, double dt, const T* mu, const T* rho, const T* v, T* grho, T* gv, const T* base,
-                 T scale, hipStream_t st, int k_known = -1) {
+                 T scale, hipStream_t st, int k_known = -1, const T* stored = nullptr) {
         const int nl = k_known >= 0 ? k_known : UP_KMAX;
+        if constexpr (D == 2) {
+            if (stored && k_known >= 0) {
+                UpClose<T> x;
+                x.gv_base = base;
+                x.gv = gv;
+                x.k_set = k_known;
+                const long nclose = std::max<long>(UP_KMAX + 1, g.nface);
+                k_up_close<T><<<blocks_for(nclose, 256), 256, 0, st>>>(g, ctl, nullptr, nl, (U)0, rho, stored,
+                                                                       nullptr, x);
+                adjoint_tiles(g, dt, mu, rho, v, grho, gv, scale, st, nl - 1, stored);
+                return;
+            }
+        }
         // with k unknown the launches past the stop cannot be told apart: such calls are not recorded
         Tracer* keep = tr;
         if (k_known < 0) tr = nullptr;
@@ -656,15 +685,19 @@ struct UpwindExp {
         series(g, dt, rho, v, nullptr, st, nl, x);
         tr = keep;
         const int top = (nl < UP_KMAX ? nl : UP_KMAX) - 1;
-        if constexpr (D == 2) {
-            const dim3 tiles(blocks_for(g.n[0], UP_TS), blocks_for(g.n[1], UP_TS));
-            int p = 0;
-            for (int b0 = top; b0 >= -1; b0 -= UP_M, p ^= 1)
-                k_up_adj_block<T><<<tiles, UP_NT, 0, st>>>(g, dt, b0, mu, z[p], z[p ^ 1], rho, terms, v, grho, gv,
-                                                           scale, ctl.k);
-        } else {
+        if constexpr (D == 2)
+            adjoint_tiles(g, dt, mu, rho, v, grho, gv, scale, st, top, terms);
+        else
             adjoint_steps(g, dt, mu, rho, v, grho, gv, scale, st, top);
-        }
+    }
+    // 2D: UP_M steps of the recursion per launch, from b = top down to -1 (k on the device)
+    void adjoint_tiles(const Grid& g, double dt, const T* mu, const T* rho, const T* v, T* grho, T* gv, T scale,
+                       hipStream_t st, int top, const T* tt) {
+        const dim3 tiles(blocks_for(g.n[0], UP_TS), blocks_for(g.n[1], UP_TS));
+        int p = 0;
+        for (int b0 = top; b0 >= -1; b0 -= UP_M, p ^= 1)
+            k_up_adj_block<T><<<tiles, UP_NT, 0, st>>>(g, dt, b0, mu, z[p], z[p ^ 1], rho, tt, v, grho, gv, scale,
+                                                       ctl.k);
     }
     // 3D: one launch per step of the recursion over the whole grid
     void adjoint_steps(const Grid& g, double dt, const T* mu, const T* rho, const T* v, T* grho, T* gv, T scale,

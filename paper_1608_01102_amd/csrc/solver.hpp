@@ -696,7 +696,7 @@ public:
         red_part = A.take<double>(RED_BLOCKS);
         red_out = A.take<double>(64);
         if (upwind()) {
-            up.layout(A, C0);
+            up.layout(A, C0, N);
             up.tr = &tr;
             up_kd = A.template take<int>(N);
             up_okd = A.template take<int>(N);
@@ -817,9 +817,10 @@ public:
     // grho += (dA/drho)^T m (grho may be null); gv = base + scale (dA/dv)^T m
     // on interior faces, 0 on walls (base may be null); k_known: the upwind
     // series' k for (r, v) when the forward sweep measured it
-    void dens_adj(const T* m, const T* r, const T* v, T* grho, T* gv, const T* base, T scale, int k_known = -1) {
+    void dens_adj(const T* m, const T* r, const T* v, T* grho, T* gv, const T* base, T scale, int k_known = -1,
+                  const T* stored = nullptr) {
         if (upwind()) {
-            up.adjoint(L[0], P.dt, m, r, v, grho, gv, base, scale, st, k_known);
+            up.adjoint(L[0], P.dt, m, r, v, grho, gv, base, scale, st, k_known, stored);
             return;
         }
         if (grho) advect_T(m, v, grho, 1);
@@ -1151,11 +1152,12 @@ public:
     }
 
     // ------------------------------------------------------------ density subproblem
-    void forward_sweep(const T* rho0, const T* vs, T* r, std::vector<int>* kout = nullptr) {
+    // hset >= 0 (upwind, 2D): the series' terms of every step are kept in stored trajectory hset
+    void forward_sweep(const T* rho0, const T* vs, T* r, std::vector<int>* kout = nullptr, int hset = -1) {
         const long C = L[0].ncell, F = L[0].nface;
         copy(r, rho0, C);
         if (upwind()) {
-            up_sweep(r, vs, kout);
+            up_sweep(r, vs, kout, hset);
             return;
         }
         for (int i = 0; i < N; ++i) dens_fwd(r + i * C, vs + i * F, r + (i + 1) * C);
@@ -1167,7 +1169,7 @@ public:
     // which steps had not stopped by then, and the sweep is run again from
     // the first of them with the full 48 launches for that step.  k per step
     // goes to kout.
-    void up_sweep(T* r, const T* vs, std::vector<int>* kout) {
+    void up_sweep(T* r, const T* vs, std::vector<int>* kout, int hset = -1) {
         const long C = L[0].ncell, F = L[0].nface;
         if ((int)up_pred.size() != N) up_pred.assign(N, UP_KMAX);
         std::vector<int> nl(up_pred), kh(N), okh(N);
@@ -1175,7 +1177,7 @@ public:
         while (from < N) {
             for (int i = from; i < N; ++i) {
                 up.forward(L[0], P.dt, r + i * C, vs + i * F, r + (i + 1) * C, st, nl[i], true, up_kd + i,
-                           up_okd + i);
+                           up_okd + i, hset >= 0 ? up.hist_step(hset, i, C) : nullptr);
             }
             HCK(hipMemcpyAsync(kh.data() + from, up_kd + from, (N - from) * sizeof(int), hipMemcpyDeviceToHost, st));
             HCK(hipMemcpyAsync(okh.data() + from, up_okd + from, (N - from) * sizeof(int), hipMemcpyDeviceToHost,
@@ -1231,21 +1233,25 @@ public:
             }
             if (i < N) {
                 if (upwind())
-                    dens_adj(mu + i * C, r + i * C, vs + i * F, out, cand + i * F, vt + i * F, ik, kr_of(i));
+                    dens_adj(mu + i * C, r + i * C, vs + i * F, out, cand + i * F, vt + i * F, ik, kr_of(i),
+                             stored_of(i));
                 else
                     advect_T(mu + i * C, vs + i * F, out, 1);
             }
         }
-        if (upwind()) dens_adj(mu, r, vs, nullptr, cand, vt, ik, kr_of(0));
+        if (upwind()) dens_adj(mu, r, vs, nullptr, cand, vt, ik, kr_of(0), stored_of(0));
     }
     // k of step i of the accepted AO trajectory (-1: unknown)
     int kr_of(int i) const { return (int)k_rho.size() == N ? k_rho[i] : -1; }
+    // the terms of step i of the accepted AO trajectory, when its forward sweep kept them
+    int up_hcur = 0;             // stored trajectory of rho (the other one takes the line search's trials)
+    const T* stored_of(int i) const { return kr_of(i) >= 0 ? up.hist_step(up_hcur, i, L[0].ncell) : nullptr; }
 
     // Alg:Passive with blending; vt must hold v + lambda/K.  Result in vstar, rho.
     void ao(const T* rho0, int nk, const int* ks, const T* keys, double* hist) {
         const long C = L[0].ncell, F = L[0].nface;
         copy(vstar, vt, N * F);
-        forward_sweep(rho0, vstar, rho, &k_rho);
+        forward_sweep(rho0, vstar, rho, &k_rho, up_hcur);
         double phi = ao_objective(rho, vstar, nk, ks, keys);
         if (hist) hist[0] = phi;
         for (int it = 0; it < P.ao_iters; ++it) {
@@ -1255,12 +1261,13 @@ public:
             double alpha = 1.0;
             for (int hv = 0; hv <= 10; ++hv) {
                 blend(vstar, cand, (T)alpha, trial, N * F);
-                forward_sweep(rho0, trial, rho_t, &k_rho_t);
+                forward_sweep(rho0, trial, rho_t, &k_rho_t, up_hcur ^ 1);
                 const double pt = ao_objective(rho_t, trial, nk, ks, keys);
                 if (pt <= phi) {
                     std::swap(vstar, trial);
                     std::swap(rho, rho_t);
                     std::swap(k_rho, k_rho_t);
+                    up_hcur ^= 1;
                     phi = pt;
                     break;
                 }
