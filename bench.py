@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--al-tol", type=float, default=0.05,
                     help="relative objective decrease below which the fallback updates the multipliers")
     ap.add_argument("--no-3d", action="store_true", help="skip the 64^3 x 60 precision-form comparison")
+    ap.add_argument("--no-rotational", action="store_true",
+                    help="skip the solves with the paper's rotational velocity operator")
     ap.add_argument("--serve-requests", type=int, default=64, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
@@ -165,6 +167,9 @@ def main():
     if args.al_admm > 0:
         out["al_fallback"] = al_run(S, w, args.density, args.al_admm, args.al_tol)
         progress("augmented-Lagrangian solves done")
+    if not args.no_rotational:
+        out["rotational_velocity"] = rotational_run(S, w, args.density, kw)
+        progress("rotational-operator solves done")
     if not args.no_3d:
         out["precision_3d"] = precision_3d_run(S)
         progress("3D solves done")
@@ -287,6 +292,27 @@ def al_run(S, w, density, max_admm, al_tol):
     return res
 
 
+def rotational_run(S, w, density, kw):
+    """The same workload with the paper's own velocity operator (eq:NSA: the
+    implicit rotational form, 2D), outside the step clock: the mixed solve
+    (after a warm-up solve) and the FP64 solve to the ADMM stop, their
+    iterations, seconds and objective, and the mixed form's keyframe error
+    against the FP64 run."""
+    solve_once(S, w, "mixed", density, velocity="rotational", **kw)
+    res, us, conv = {}, {}, []
+    for prec in ("mixed", "fp64"):
+        st, us[prec] = solve_once(S, w, prec, density, velocity="rotational", **kw)
+        res[prec] = {"admm_iters": st["admm_iters"], "vcycles": st["vcycles"], "converged": bool(st["converged"]),
+                     "seconds": st["seconds"], "objective": st["objective"], "visual_diff": st["visual_diff"]}
+        conv.append(bool(st["converged"]))
+    kf = keyframe_error(S, w, density, us["mixed"], us["fp64"], velocity="rotational")
+    res["kf_err_mixed_vs_fp64"] = kf
+    res["meets_1e-4_kf_err"] = bool(kf <= 1e-4 and all(conv))
+    res["cell_updates_per_s"] = (w["n"][0] * w["n"][1] * w["num_steps"] * res["mixed"]["vcycles"]
+                                 / res["mixed"]["seconds"])
+    return res
+
+
 def precision_3d_run(S):
     """The 3D precision form (outside the step clock): the 64^3, 60-step
     workload (sphere to ellipsoid unions at t = 30 and 60, SL density) solved
@@ -319,14 +345,15 @@ def precision_3d_run(S):
     return res
 
 
-def keyframe_error(S, w, density, u_a, u_b):
+def keyframe_error(S, w, density, u_a, u_b, velocity="sl"):
     """max over keyframes of |rho_a - rho_b| / |rho_b| after re-simulating both
-    control sequences with the FP64 step of the library."""
+    control sequences with the FP64 step of the library (with the velocity
+    operator the controls were solved for)."""
     import numpy as np
     import torch
     dev = torch.device("cuda:0")
     N = w["num_steps"]
-    p64 = S.make_problem(w["n"], 1, w["r"], dt=w["dt"], precision="fp64", density=density)
+    p64 = S.make_problem(w["n"], 1, w["r"], dt=w["dt"], precision="fp64", density=density, velocity=velocity)
     cells, faces = S.counts(p64)
     work = torch.empty(S.stfas_step_work_bytes(p64), dtype=torch.uint8, device=dev)
 

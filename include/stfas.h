@@ -68,6 +68,17 @@ typedef enum { STFAS_FP64 = 0, STFAS_MIXED = 1 } stfas_precision;
  * in rho and v exist. */
 typedef enum { STFAS_DENSITY_SL = 0, STFAS_DENSITY_UPWIND = 1 } stfas_density;
 
+/* Velocity operator of the dynamics (Sec. 3.1 eq:NSA).  Semi-Lagrangian:
+ * v_{i+1} = Q(S(v_i) + dt u_i) with the self-advection S.  Rotational
+ * (2D only): the paper's implicit update (v_{i+1} - v_i)/dt + Adv[v_{i+1}] =
+ * u_i - G p_{i+1} with Adv the vorticity form (curl v) x v, discretised with
+ * the node vorticity and node-paired face products so that it does no work;
+ * the KKT residual is eq:KKTAO as printed (du_{i-1}/dv_i = I/dt + dAdv/dv_i)
+ * and the re-simulation of the outputs (and stfas_step_forward) takes 4
+ * fixed-point steps per time step.  stfas_lbfgs and stfas_step_backward
+ * accept only the semi-Lagrangian operator (STFAS_E_INVALID otherwise). */
+typedef enum { STFAS_VELOCITY_SL = 0, STFAS_VELOCITY_ROTATIONAL = 1 } stfas_velocity;
+
 /* Problem description (Sec. 3.2 eq:opt and the parameter table of Sec. 5).
  * A field <= 0 selects the documented default. */
 typedef struct {
@@ -97,6 +108,7 @@ typedef struct {
                              * (Sec. 5, convergence analysis; eq:HESS): K/r on every v block becomes
                              * K/r + scgs_lm / dt^2 (the residual is unchanged, so is the solution);
                              * 0 selects 1; < 0 turns it off */
+    int32_t velocity_op;    /* stfas_velocity; 0 = semi-Lagrangian; 1 (rotational) needs dim = 2 */
 } stfas_problem;
 
 typedef struct {

@@ -60,6 +60,7 @@ class Problem:
     density: str = "sl"               # density operator: "sl" or "upwind" (eq:Adv)
     al_tol: float = 0.0               # augmented-Lagrangian fallback threshold (0: plain ADMM)
     scgs_lm: float = 1.0              # smoother's Levenberg-Marquardt perturbation times dt^2 (< 0: off)
+    velocity: str = "sl"              # velocity operator: "sl" or "vorticity" (eq:NSA's Adv, 2D)
 
     def resolved(self, rho0):
         p = Problem(**self.__dict__)
@@ -92,13 +93,13 @@ class Result:
     history: dict = field(default_factory=dict)
 
 
-def resimulate(g: Grid, rho0, u, dt, kind="sl"):
+def resimulate(g: Grid, rho0, u, dt, kind="sl", velocity="sl"):
     N = u.shape[0]
     rho = np.zeros((N + 1, g.ncell))
     v = np.zeros((N + 1, g.nface))
     rho[0] = rho0
     for i in range(N):
-        rho[i + 1], v[i + 1], _ = step_forward(g, rho[i], v[i], u[i], dt, kind=kind)
+        rho[i + 1], v[i + 1], _ = step_forward(g, rho[i], v[i], u[i], dt, kind=kind, velocity=velocity)
     return rho, v
 
 
@@ -119,7 +120,7 @@ def solve(prob: Problem, rho0, keys):
     g = Grid(p.n)
     N = p.num_steps
     kr = p.K / p.r
-    H = stfas.Hierarchy(g, N, p.dt, kr, omega=p.scgs_omega, lm=max(p.scgs_lm, 0.0))
+    H = stfas.Hierarchy(g, N, p.dt, kr, omega=p.scgs_omega, lm=max(p.scgs_lm, 0.0), velocity=p.velocity)
     F = g.nface
     v_all = np.zeros((N, F))          # v_i, i = 0..N-1 as seen by AO (v_0 = 0)
     lam = np.zeros((N, F))
@@ -161,7 +162,7 @@ def solve(prob: Problem, rho0, keys):
             lam = lam + p.K * p.beta * (v_all - vstar)
             hist["updates"] += 1
     u = x[2].copy()
-    rho_sim, _ = resimulate(g, rho0, u, p.dt, p.density)
+    rho_sim, _ = resimulate(g, rho0, u, p.dt, p.density, p.velocity)
     J, Jl2, reg = objectives(g, rho_sim, keys, u, p.r, p.metric_levels)
     return Result(u=u, v=x[0].copy(), vstar=vstar, rho_ao=rho, rho_sim=rho_sim, objective=J,
                   objective_l2=Jl2, reg_term=reg, admm_iters=it, vcycles=total_vc,

@@ -6,16 +6,31 @@ exponential of eq:Adv, `kind`) and its exact adjoint.
   w    = S(v) + dt u          (advect, then add the control force)
   v'   = Q(w),  p' = phi / dt (projection; the pressure is the multiplier of
                                the divergence constraint, eq:NSB)
+
+With the paper's rotational operator (velocity = "vorticity", 2D) the
+velocity update of eq:NSA is implicit, (v' - v)/dt + Adv[v'] = u - G p'.
+Reading: it is solved by a fixed number of fixed-point (Picard) steps from
+v'_0 = Q(v + dt u):  v'_{m+1} = Q(v + dt u - dt Adv[v'_m]), m < PICARD;
+the density is carried by the old velocity as before.  The step's adjoint is
+not built for this form.
 """
 import numpy as np
 
 from .grid import Grid
-from . import advect, density
+from . import advect, density, vorticity
 from .poisson import project
 
+PICARD = 4
 
-def step_forward(g: Grid, rho, v, u, dt, rtol=1e-14, kind="sl"):
+
+def step_forward(g: Grid, rho, v, u, dt, rtol=1e-14, kind="sl", velocity="sl"):
     rho_n = density.fwd(g, rho, v, dt, kind)
+    if velocity == "vorticity":
+        base = (v + dt * u) * g.interior_mask()
+        v_n, phi = project(g, base, rtol=rtol)
+        for _ in range(PICARD):
+            v_n, phi = project(g, base - dt * vorticity.adv(g, v_n), rtol=rtol)
+        return rho_n, v_n, phi / dt
     w = advect.self_advect(g, v, dt) + dt * u * g.interior_mask()
     v_n, phi = project(g, w, rtol=rtol)
     return rho_n, v_n, phi / dt

@@ -28,6 +28,7 @@ class StfasProblem(ctypes.Structure):
         ("density_op", c_int32),
         ("al_tol", c_double),
         ("scgs_lm", c_double),
+        ("velocity_op", c_int32),
     ]
 
 

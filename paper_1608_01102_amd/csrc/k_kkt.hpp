@@ -11,9 +11,16 @@
 //   F4_i = D u_i
 // Kernels compute out = res + sgn f (sgn = -1: residual res - f; sgn = +1:
 // the FAS right-hand side f(R x) + R r).
+//
+// With the rotational operator of eq:NSA (2D, k_rot.hpp) the rows are those
+// of eq:KKTAO as printed:
+//   F1_i = (K/r)[i<N](v_i - w_i) - [i<N] u_i/dt + u_{i-1}/dt + J_Adv(v_i)^T u_{i-1} + G pbar_i
+//   F3_i = (v_{i+1} - v_i)/dt + Adv[v_{i+1}] - u_i + G p_{i+1}
+// all local stencils (no transpose part).
 #pragma once
 #include "common.hpp"
 #include "k_advect.hpp"
+#include "k_rot.hpp"
 
 namespace stfas {
 
@@ -23,7 +30,7 @@ template <typename T, int D>
 __device__ inline void kkt_face(const Grid& g, int N, T dt, T kr, T cfl, T sgn, const T* __restrict__ v,
                                 const T* __restrict__ pb, const T* __restrict__ u, const T* __restrict__ p,
                                 const T* __restrict__ w, const T* res1, const T* res3, T* out1, T* out3, int f,
-                                int j) {
+                                int j, int vort = 0) {
     const long F = g.nface, C = g.ncell;
     int a, i, jj, k;
     face_decode(g, f, a, i, jj, k);
@@ -36,6 +43,19 @@ __device__ inline void kkt_face(const Grid& g, int N, T dt, T kr, T cfl, T sgn, 
     const int c = cell_index(g, i, jj, k);
     const int cm = cell_index(g, i - (a == 0), jj - (a == 1), k - (a == 2));
     const T ih = (T)(1.0 / g.h);
+    if (D == 2 && vort) {
+        // F1_{j+1} = u_j/dt + G pbar + J_Adv(v_{j+1})^T u_j [+ (K/r)(v - w) - u_{j+1}/dt]
+        T f1 = u[e] / dt + (pb[j * C + c] - pb[j * C + cm]) * ih;
+        f1 += rot_adv_T<T>(g, v + j * F, u + j * F, a, i, jj, ih);
+        if (j < N - 1) f1 += kr * (v[e] - w[(j + 1) * F + f]) - u[e + F] / dt;
+        // F3_j = (v_{j+1} - v_j)/dt + Adv[v_{j+1}] - u_j + G p_{j+1}
+        const T vprev = j >= 1 ? v[e - F] : (T)0;
+        const T f3 = (v[e] - vprev) / dt + rot_adv<T>(g, v + j * F, a, i, jj, ih) - u[e] +
+                     (p[j * C + c] - p[j * C + cm]) * ih;
+        out1[e] = (res1 ? res1[e] : (T)0) + sgn * f1;
+        out3[e] = (res3 ? res3[e] : (T)0) + sgn * f3;
+        return;
+    }
     // F1_{j+1}
     T f1 = u[e] / dt + (pb[j * C + c] - pb[j * C + cm]) * ih;
     if (j < N - 1) f1 += kr * (v[e] - w[(j + 1) * F + f]);
@@ -96,6 +116,7 @@ struct KktSplit {
     int cnt[3];     // cells of the colour along each axis
     int nfc;        // faces of the colour's cells (per slice), with rows set
     void* gq;       // tiled transpose: where the quarters for the other axes go (k_quarter_gather adds them)
+    int vort;       // 1: face rows of the rotational operator (2D; no transpose part)
 };
 
 // Face e (0 <= e < nfc) of the colour's cells: a-faces whose coordinates
@@ -131,7 +152,7 @@ __global__ void __launch_bounds__(256) k_kkt_split(Grid g, int N, T dt, T kr, T 
         const int e = (int)(b % ks.nbf) * 256 + threadIdx.x;
         if (e >= (ks.rows ? ks.nfc : g.nface)) return;
         const int f = ks.rows ? colour_face(g, ks, e) : e;
-        kkt_face<T, D>(g, N, dt, kr, cfl, sgn, v, pb, u, p, w, res1, res3, out1, out3, f, (int)(b / ks.nbf));
+        kkt_face<T, D>(g, N, dt, kr, cfl, sgn, v, pb, u, p, w, res1, res3, out1, out3, f, (int)(b / ks.nbf), ks.vort);
         return;
     }
     b -= bf;

@@ -29,6 +29,7 @@ constexpr int RED_BLOCKS = 512;
 constexpr int MAX_COARSE_CELLS = 4096;
 constexpr int MAX_PROJECT_CYCLES = 60;
 constexpr long DIRECT_T_SLOTS = 131072;   // face slots up to which the residual's transpose runs untiled
+constexpr int ROT_PICARD = 4;             // fixed-point steps of the rotational operator's implicit update
 
 
 // Bump allocator with a planning pass: plan() sizes every buffer, carve()
@@ -50,6 +51,7 @@ struct Params {
     int dim, n[3], N;
     double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol, omega, al_tol, lm;
     int ao_iters, max_admm, max_vcycles, metric_levels, fixed_counts, precision, density;
+    int vort;   // 1: the rotational velocity operator (eq:NSA's Adv, 2D)
 };
 
 inline int default_metric_levels(const int* n, int dim) {
@@ -94,6 +96,9 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     o.al_tol = p->al_tol;
     if (std::isnan(p->scgs_lm) || std::isinf(p->scgs_lm)) return false;
     o.lm = (p->scgs_lm < 0 ? 0.0 : (p->scgs_lm > 0 ? p->scgs_lm : 1.0)) / (o.dt * o.dt);
+    if (p->velocity_op != STFAS_VELOCITY_SL && p->velocity_op != STFAS_VELOCITY_ROTATIONAL) return false;
+    if (p->velocity_op == STFAS_VELOCITY_ROTATIONAL && o.dim != 2) return false;
+    o.vort = p->velocity_op == STFAS_VELOCITY_ROTATIONAL ? 1 : 0;
     const double total = (double)o.n[0] * o.n[1] * o.n[2];
     if (total > 2.0e9 / (o.dim + 1)) return false;
     return true;
@@ -866,6 +871,7 @@ public:
         KktSplit ks{};
         ks.nbf = blocks_for(g.nface, 256);
         ks.nbc = blocks_for(g.ncell, 256);
+        ks.vort = P.vort;
         const long blocks = (long)(ks.nbf + ks.nbc) * N;
         traced(tr, st, l == 0 ? TR_KKT_FACES : TR_NONE,
                sz * (fslots * (5 + (s1 ? 2 : 0)) + cslots * (4 + (s2 ? 2 : 0))), [&] {
@@ -873,7 +879,7 @@ public:
                                                                       pb, u, p, w, s1, s2, s3, s4, o1, o2, o3, o4,
                                                                       nullptr, nullptr);
                });
-        if (N > 1) {
+        if (N > 1 && !P.vort) {
             // v, y read, out read-modify-write, per face
             traced(tr, st, l == 0 ? TR_SELF_ADVECT_T : TR_NONE, sz * (double)g.nface * (N - 1) * 4,
                    [&] { self_advect_T(l, v, u + g.nface, (T)(-sgn / dt), o1, N - 1); });
@@ -949,6 +955,8 @@ public:
         const long nfr = ks.nfc, ncr = cs.total;     // face and cell rows per slice
         ks.nbf = blocks_for(nfr, 256);
         ks.nbc = blocks_for(ncr, 256);
+        ks.vort = P.vort;
+        if (P.vort) t1 = t1z = nullptr;    // the rotational rows have no transpose part
         if (t1 && N > 1) {
             ks.direct = (long)N * g.nface <= DIRECT_T_SLOTS ? 1 : 0;
             if (ks.direct) {
@@ -1026,6 +1034,9 @@ public:
             const double sz = sizeof(T), M2 = 2.0 * N;
             int G = 1, Lc = 0, CH = 0;
             if (D == 3) {
+                kkt_rows(l, colour);
+            } else if (P.vort) {
+                t1 = t1_zero;                       // stays zero: the rows carry every term of F1
                 kkt_rows(l, colour);
             } else {
                 t1 = t1_zero;
@@ -1380,6 +1391,7 @@ public:
     }
     int lbfgs(const void* rho0v, int nk, const int* ks, const void* keysv, void* uv, int iters, double eps_stop,
               double* hist) override {
+        if (P.vort) return -3;   // the baseline runs the semi-Lagrangian step chain only
         const T* rho0 = (const T*)rho0v;
         const T* keys = (const T*)keysv;
         T* u = (T*)uv;
@@ -1530,8 +1542,20 @@ public:
         int cur = 0;
         for (int i = 0; i < N; ++i) {
             dens_fwd(rs_rho[cur], rs_v[cur], rs_rho[cur ^ 1]);
-            self_advect(0, rs_v[cur], q.u + i * F, rs_w, 1);
-            project(rs_w, rs_v[cur ^ 1], nullptr, 1);
+            if (P.vort) {
+                // the implicit update by ROT_PICARD fixed-point steps from Q(v + dt u)
+                const Grid& g = L[0];
+                k_rot_rhs<T><<<blocks_for(F, BS), BS, 0, st>>>(g, (T)P.dt, rs_v[cur], q.u + i * F, nullptr, rs_w);
+                project(rs_w, rs_v[cur ^ 1], nullptr, 1);
+                for (int m = 0; m < ROT_PICARD; ++m) {
+                    k_rot_rhs<T><<<blocks_for(F, BS), BS, 0, st>>>(g, (T)P.dt, rs_v[cur], q.u + i * F,
+                                                                    rs_v[cur ^ 1], rs_w);
+                    project(rs_w, rs_v[cur ^ 1], nullptr, 1);
+                }
+            } else {
+                self_advect(0, rs_v[cur], q.u + i * F, rs_w, 1);
+                project(rs_w, rs_v[cur ^ 1], nullptr, 1);
+            }
             cur ^= 1;
             for (int kq = 0; kq < nk; ++kq)
                 if (ks[kq] == i + 1) {

@@ -91,8 +91,18 @@ struct Step {
             up.forward(g, p.dt, rho, v, rho_o, st);
         else
             k_advect<T, D><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g, cfl, rho, v, rho_o, g.ncell, g.nface);
-        k_self_advect<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, (T)p.dt, v, u, w, g.nface);
-        pois.project(w, v_o, p_o, 1, p.poisson_rtol, step_cycles(p), nullptr);
+        if (p.vort) {
+            // the implicit rotational update: ROT_PICARD fixed-point steps from Q(v + dt u)
+            k_rot_rhs<T><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, (T)p.dt, v, u, nullptr, w);
+            pois.project(w, v_o, p_o, 1, p.poisson_rtol, step_cycles(p), nullptr);
+            for (int m = 0; m < ROT_PICARD; ++m) {
+                k_rot_rhs<T><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, (T)p.dt, v, u, v_o, w);
+                pois.project(w, v_o, p_o, 1, p.poisson_rtol, step_cycles(p), nullptr);
+            }
+        } else {
+            k_self_advect<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, cfl, (T)p.dt, v, u, w, g.nface);
+            pois.project(w, v_o, p_o, 1, p.poisson_rtol, step_cycles(p), nullptr);
+        }
         if (p_o) k_axpby<T><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g.ncell, (T)(1.0 / p.dt), p_o, (T)0, nullptr, p_o);
     }
 
@@ -325,6 +335,7 @@ stfas_status stfas_lbfgs(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
         HCK(hipPeekAtLastError());
         HCK(hipStreamSynchronize(ctx->s->st));
         if (done == -1) return STFAS_E_NOMEM;
+        if (done == -3) return STFAS_E_INVALID;
         if (iters_done) *iters_done = done < 0 ? 0 : done;
         return done == -2 ? STFAS_E_NONFINITE : STFAS_OK;
     });
@@ -367,7 +378,7 @@ stfas_status stfas_step_backward(const stfas_problem* prob, void* hip_stream, co
                                  const void* g_rho_out, const void* g_v_out, void* g_rho, void* g_v, void* g_u,
                                  void* work) {
     Params p;
-    if (!resolve(prob, p)) return STFAS_E_INVALID;
+    if (!resolve(prob, p) || p.vort) return STFAS_E_INVALID;
     if (!rho || !v || !g_rho_out || !g_v_out || !g_rho || !g_v || !g_u || !work) return STFAS_E_INVALID;
     return guard([&]() {
         return dispatch_step(p, (hipStream_t)hip_stream, work, false, rho, v, g_rho_out, g_v_out, g_rho, g_v, g_u);

@@ -73,6 +73,21 @@ def test_density_operator_selection():
     assert 50 * cells * 8 <= extra_step <= 50 * cells * 8 + 4096
 
 
+def test_velocity_operator_selection():
+    """The rotational velocity operator is 2D only; an unknown value, or the
+    operator on a 3D grid, is rejected before any allocation; the forward
+    step takes it with the same scratch as the semi-Lagrangian one."""
+    from paper_1608_01102_amd import stfas as S
+    ok = S.make_problem((32, 32), 10, 1e-3, velocity="rotational")
+    assert S.stfas_workspace_bytes(ok) > 0
+    assert S.stfas_step_work_bytes(ok) == S.stfas_step_work_bytes(S.make_problem((32, 32), 10, 1e-3))
+    bad3d = S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational")
+    assert S.stfas_workspace_bytes(bad3d) == 0
+    bad = S.make_problem((32, 32), 10, 1e-3)
+    bad.velocity_op = 2
+    assert S.stfas_workspace_bytes(bad) == 0
+
+
 def test_status_strings():
     from paper_1608_01102_amd import _lib
     lib = _lib.load()

@@ -1,0 +1,135 @@
+"""Pins of the oracle's rotational velocity operator (Sec. 3.1 eq:NSA, the
+vorticity form (curl v) x v) and of the KKT residual of eq:KKTAO built on it
+(CPU): the operator does no work, its Jacobian transpose passes the
+dot-product test, an irrotational field has none, solid-body rotation gives
+the closed form, and F1 is the gradient of the reduced objective."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import kkt, poisson, step, vorticity
+from oracle.grid import Grid, grad
+
+
+@pytest.fixture
+def rng():
+    return np.random.default_rng(61)
+
+
+def _faces(g, rng, s=1.0):
+    return rng.standard_normal(g.nface) * s * g.interior_mask()
+
+
+@pytest.mark.parametrize("n", [(8, 6), (13, 9), (16, 16)])
+def test_rotational_operator_does_no_work(n, rng):
+    g = Grid(n)
+    for _ in range(3):
+        v = _faces(g, rng)
+        a = vorticity.adv(g, v)
+        assert abs(v @ a) <= 1e-13 * np.linalg.norm(v) * np.linalg.norm(a)
+        assert np.all(a[g.interior_mask() == 0] == 0)
+
+
+@pytest.mark.parametrize("n", [(8, 6), (13, 9)])
+def test_rotational_operator_is_quadratic_and_its_transpose_is_exact(n, rng):
+    g = Grid(n)
+    v, y, d = _faces(g, rng), _faces(g, rng), _faces(g, rng)
+    assert np.allclose(vorticity.adv(g, 2.5 * v), 6.25 * vorticity.adv(g, v), rtol=1e-13, atol=0)
+    # central differences are exact for a quadratic map (up to rounding)
+    e = 1e-3
+    jd = (vorticity.adv(g, v + e * d) - vorticity.adv(g, v - e * d)) / (2 * e)
+    assert abs(y @ jd - vorticity.adv_T(g, v, y) @ d) <= 1e-11 * abs(y @ jd)
+    # the gradient of <y, Adv[v]> by central differences of the scalar
+    f = lambda x: y @ vorticity.adv(g, x)
+    fd = (f(v + e * d) - f(v - e * d)) / (2 * e)
+    assert abs(fd - vorticity.adv_T(g, v, y) @ d) <= 1e-11 * abs(fd)
+
+
+def test_irrotational_field_has_no_rotational_term(rng):
+    g = Grid((12, 10))
+    v = grad(g, rng.standard_normal(g.ncell), g.h) * g.interior_mask()
+    assert np.max(np.abs(vorticity.node_vorticity(g, v))) <= 1e-12 * np.max(np.abs(v)) / g.h
+    assert np.max(np.abs(vorticity.adv(g, v))) <= 1e-12 * np.max(np.abs(v)) ** 2 / g.h
+
+
+def test_solid_rotation_closed_form():
+    """v = (y - 1/2, -(x - 1/2)) on the unit square: vorticity -2 at every
+    interior node and Adv_x = -2 (x - 1/2), Adv_y = -2 (y - 1/2) (that is
+    (curl v) x v) at faces whose end nodes are interior."""
+    n = 16
+    g = Grid((n, n))
+    h = g.h
+    vx = np.tile(((np.arange(n) + 0.5) * h - 0.5)[:, None], (1, n + 1))
+    vy = np.tile(-((np.arange(n) + 0.5) * h - 0.5)[None, :], (n + 1, 1))
+    v = g.join([vx, vy]) * g.interior_mask()
+    w = vorticity.node_vorticity(g, v)
+    assert np.allclose(w[1:n, 1:n], -2.0, rtol=0, atol=1e-12)
+    ax, ay = g.split(vorticity.adv(g, v))
+    nodes = np.arange(n + 1) * h
+    assert np.allclose(ax[1:n - 1, 1:n], -2 * (nodes[None, 1:n] - 0.5), rtol=0, atol=1e-12)
+    assert np.allclose(ay[1:n, 1:n - 1], -2 * (nodes[1:n, None] - 0.5), rtol=0, atol=1e-12)
+
+
+def test_implicit_step_satisfies_its_update():
+    """The re-simulation step (fixed-point steps from Q(v + dt u)) leaves a
+    residual of the implicit update far below its terms on a slow flow, and
+    that residual shrinks with every extra step."""
+    g = Grid((16, 16))
+    rng = np.random.default_rng(62)
+    dt = 0.5 * g.h
+    v = synthetic.curl_noise_velocity(g.n, rng, 2.0, 0.5, dt / g.h)
+    u = poisson.project(g, _faces(g, rng, 0.5))[0]
+    rho = np.zeros(g.ncell)
+    res = []
+    for m in (1, 2, 4):
+        old = step.PICARD
+        step.PICARD = m
+        try:
+            _, vn, p = step.step_forward(g, rho, v, u, dt, velocity="vorticity")
+        finally:
+            step.PICARD = old
+        r = ((vn - v) / dt + vorticity.adv(g, vn) - u + grad(g, p, g.h)) * g.interior_mask()
+        # the projection absorbs the gradient part; what is left is the fixed-point error
+        res.append(np.linalg.norm(poisson.project(g, r)[0]))
+    assert res[2] < res[1] < res[0]
+    assert res[2] <= 1e-3 * np.linalg.norm(vorticity.adv(g, v))
+
+
+def test_kkt_rotational_f1_is_the_reduced_gradient(rng):
+    """For a state whose u and p satisfy F3 = F4 = 0 given v (u the solenoidal
+    part of (v_{i+1} - v_i)/dt + Adv[v_{i+1}]), F2 = F4 = 0 and <F1, dv>
+    equals the directional derivative of 1/2 sum |u_i|^2 + (K/r)/2 sum |v_i - w_i|^2
+    for solenoidal dv (eq:KKTAO as printed)."""
+    g = Grid((8, 8))
+    N, dt, kr = 4, 0.5 * g.h, 3.0
+    L = kkt.Level(g, N, dt, kr, velocity="vorticity")
+    vs = [np.zeros(g.nface)] + [poisson.project(g, _faces(g, rng, 0.8))[0] for _ in range(N)]
+    w = np.stack([_faces(g, rng, 0.5) for _ in range(N)])
+
+    def build(vlist):
+        u = np.zeros((N, g.nface))
+        p = np.zeros((N, g.ncell))
+        for i in range(N):
+            q = (vlist[i + 1] - vlist[i]) / dt + vorticity.adv(g, vlist[i + 1])
+            u[i], phi = poisson.project(g, q)
+            p[i] = -phi
+        return [np.stack(vlist[1:]), np.zeros((N, g.ncell)), u, p]
+
+    x = build(vs)
+    f = kkt.residual_f(L, x, w)
+    scale = np.max(np.abs(x[2]))
+    assert np.max(np.abs(f[1])) < 1e-11 * scale and np.max(np.abs(f[3])) < 1e-11 * scale
+    assert np.max(np.abs(f[2])) < 1e-10 * scale
+
+    def jred(vlist):
+        xx = build(vlist)
+        val = 0.5 * np.sum(xx[2] ** 2)
+        for i in range(1, N):
+            val += 0.5 * kr * np.sum((vlist[i] - w[i]) ** 2)
+        return val
+    for _ in range(3):
+        dvs = [np.zeros(g.nface)] + [synthetic.curl_noise_velocity(g.n, rng, 1.0) for _ in range(N)]
+        e = 1e-6
+        fd = (jred([a + e * b for a, b in zip(vs, dvs)]) - jred([a - e * b for a, b in zip(vs, dvs)])) / (2 * e)
+        ad = sum(f[0][j] @ dvs[j + 1] for j in range(N))
+        assert abs(fd - ad) <= 1e-5 * max(abs(fd), 1.0)
