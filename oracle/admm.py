@@ -61,6 +61,7 @@ class Problem:
     al_tol: float = 0.0               # augmented-Lagrangian fallback threshold (0: plain ADMM)
     scgs_lm: float = 1.0              # smoother's Levenberg-Marquardt perturbation times dt^2 (< 0: off)
     velocity: str = "sl"              # velocity operator: "sl" or "vorticity" (eq:NSA's Adv, 2D)
+    local_adv: bool = True            # vorticity: dAdv/dv in the smoother's local matrix (eq:HESS)
 
     def resolved(self, rho0):
         p = Problem(**self.__dict__)
@@ -120,7 +121,8 @@ def solve(prob: Problem, rho0, keys):
     g = Grid(p.n)
     N = p.num_steps
     kr = p.K / p.r
-    H = stfas.Hierarchy(g, N, p.dt, kr, omega=p.scgs_omega, lm=max(p.scgs_lm, 0.0), velocity=p.velocity)
+    H = stfas.Hierarchy(g, N, p.dt, kr, omega=p.scgs_omega, lm=max(p.scgs_lm, 0.0), velocity=p.velocity,
+                          local_adv=p.local_adv)
     F = g.nface
     v_all = np.zeros((N, F))          # v_i, i = 0..N-1 as seen by AO (v_0 = 0)
     lam = np.zeros((N, F))

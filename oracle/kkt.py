@@ -40,7 +40,8 @@ class Level:
     advect=False replaces S by the identity (the linear-quadratic special
     case used by the brute-force checks)."""
 
-    def __init__(self, g: Grid, N, dt, K_over_r, advect=True, omega=1.0, lm=0.0, velocity="sl"):
+    def __init__(self, g: Grid, N, dt, K_over_r, advect=True, omega=1.0, lm=0.0, velocity="sl",
+                 local_adv=True):
         self.g, self.N, self.dt, self.kr = g, N, dt, K_over_r
         self.mask = g.interior_mask()
         self.advect = advect
@@ -48,6 +49,9 @@ class Level:
         self.velocity = velocity    # "sl": v_{i+1} = Q(S(v_i) + dt u_i); "vorticity": eq:NSA with Adv
         self.omega = omega          # relaxation weight of the smoother
         self.lm = lm                # Levenberg-Marquardt perturbation of the smoother's K/r, times dt^2
+        # rotational operator: the smoother's local matrix holds the cell's block of dAdv/dv (eq:HESS);
+        # False leaves it out (du_{i-1}/dv_i = I/dt, the collapsed form of the SL operator)
+        self.local_adv = local_adv and velocity == "vorticity"
 
     def S(self, v):
         return advect.self_advect(self.g, v, self.dt, self.g.h) if self.advect else v * self.mask

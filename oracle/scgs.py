@@ -46,11 +46,22 @@ du_i/dv_i = -I/dt exactly as eq:KKTAO states; the residual stays exact):
   T_kk  = -1 (u blocks),  K/r (v_i, i<N),  0 (v_N)   [+ lm/dt^2 on v blocks]
   T(u_{i-1}, v_i) = +1/dt,   T(v_i, u_i) = -1/dt   (symmetric)
   g = divergence coefficients of the cell's faces (-1/h low, +1/h high).
+
+With the rotational operator (level.local_adv) the local matrix is eq:HESS
+itself: the coupling of u_i and v_{i+1} is the cell's block of
+du_i/dv_{i+1} = I/dt + dAdv/dv at v_{i+1} (rows: F3_i at the cell's faces,
+columns: v_{i+1} at the cell's faces), and its transpose couples v_{i+1}
+and u_i in F1_{i+1}.  The v blocks keep K/r (+ the perturbation) as printed:
+the second derivative of Adv, which F1_{i+1} carries through
+J_Adv(v_{i+1})^T u_i, is not in eq:HESS.  The blocks are no longer scalar
+multiples of the identity, so the elimination below takes them as full
+(2d+1)x(2d+1) matrices.
 """
 import numpy as np
 
 from .grid import Grid
 from .kkt import Level, residual, transpose_term
+from . import vorticity
 
 
 def colour_cells(g: Grid, colour):
@@ -96,6 +107,32 @@ def _tmatrix(N, dt, kr, mu=0.0):
         if k + 1 < 2 * N:
             off[k] = (1.0 / dt) if k % 2 == 0 else (-1.0 / dt)
     return diag, off
+
+
+def adv_local_blocks(L: Level, v, fidx, inner):
+    """Per slot i (v[i] = v_{i+1}) and cell of the colour, the block of
+    I/dt + dAdv/dv at v_{i+1} on the cell's face slots: out[i, c, t, s] =
+    d(F3_i at slot t) / d(v_{i+1} at slot s), zero where a slot is a wall.
+
+    Adv is a homogeneous quadratic, so (Adv(v + d) - Adv(v - d)) / 2 is its
+    Jacobian times d exactly (up to rounding).  d is taken as the indicator
+    of slot s of every cell of the colour at once: Adv at a face reads only
+    the faces that share one of its end nodes, and two cells of one colour
+    differ by an even, nonzero offset, so no face of one of them shares a
+    node with a face of the other: each cell's slots see only its own d."""
+    g, N, dt = L.g, L.N, L.dt
+    nc, ns = fidx.shape
+    out = np.zeros((N, nc, ns, ns))
+    for s in range(ns):
+        d = np.zeros(g.nface)
+        sel = inner[:, s]
+        d[fidx[sel, s]] = 1.0
+        for i in range(N):
+            jd = 0.5 * (vorticity.adv(g, v[i] + d) - vorticity.adv(g, v[i] - d))
+            out[i, :, :, s] = jd[fidx] * inner * inner[:, s:s + 1]
+    for s in range(ns):
+        out[:, :, s, s] += inner[:, s] / dt
+    return out
 
 
 def smooth_colour(L: Level, x, w, res, colour, jst=None):
@@ -147,13 +184,24 @@ def smooth_colour(L: Level, x, w, res, colour, jst=None):
         dk[:, B - 1] = cr[j][cidx]
         return dk
 
-    # block elimination forward
+    Bl = adv_local_blocks(L, v, fidx, inner) if L.local_adv else None
+
+    def upper(k):
+        """Coupling of block k (rows) with block k + 1 (columns)."""
+        if Bl is not None and k % 2 == 0:
+            A = np.zeros((nc, B, B))
+            A[:, :2 * d, :2 * d] = Bl[k // 2]          # dF3_i / dv_{i+1}, i = k / 2
+            return A
+        return off[k] * E
+
+    # block elimination forward (the matrix is symmetric: the coupling of
+    # block k with block k - 1 is upper(k - 1) transposed)
     Ahat = [None] * (2 * N)
     dhat = [None] * (2 * N)
     Ahat[0], dhat[0] = block(0), rhs(0)
     for k in range(1, 2 * N):
-        Lk = off[k - 1] * E
-        Uk1 = off[k - 1] * E
+        Uk1 = upper(k - 1)
+        Lk = np.transpose(Uk1, (0, 2, 1))
         M = np.linalg.solve(np.transpose(Ahat[k - 1], (0, 2, 1)), np.transpose(Lk, (0, 2, 1)))
         M = np.transpose(M, (0, 2, 1))                      # M = Lk Ahat_{k-1}^{-1}
         Ahat[k] = block(k) - M @ Uk1
@@ -162,7 +210,7 @@ def smooth_colour(L: Level, x, w, res, colour, jst=None):
     xs = [None] * (2 * N)
     xs[2 * N - 1] = np.linalg.solve(Ahat[2 * N - 1], dhat[2 * N - 1][..., None])[..., 0]
     for k in range(2 * N - 2, -1, -1):
-        Uk = off[k] * E
+        Uk = upper(k)
         t = dhat[k] - np.einsum("cij,cj->ci", Uk, xs[k + 1])
         xs[k] = np.linalg.solve(Ahat[k], t[..., None])[..., 0]
     # apply the corrections (disjoint unknowns within a colour), relaxed by omega

@@ -13,6 +13,8 @@ from oracle.grid import Grid
 
 pytestmark = pytest.mark.gpu
 
+# whether the library's smoother holds the cell's block of dAdv/dv (eq:HESS)
+LOCAL_ADV = False
 CASES = [((16, 12), 4), ((20, 12), 5), ((16, 16), 3), ((9, 7), 2)]
 PRECS = ["fp64", "mixed"]
 
@@ -52,7 +54,7 @@ def test_rotational_kkt_residual_all_levels(n, N, prec):
     rng = np.random.default_rng(71)
     for level in range(ctx.num_levels()):
         gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
-        L = kkt.Level(gl, N, dt, K / 1e-2, velocity="vorticity")
+        L = kkt.Level(gl, N, dt, K / 1e-2, velocity="vorticity", local_adv=LOCAL_ADV)
         x = _state(gl, N, rng, 0.5, prec)
         w = _q(_faces(gl, rng, N), prec)
         res = _state(gl, N, rng, 1.0, prec)
@@ -73,7 +75,7 @@ def test_rotational_scgs_sweep(n, N, prec, omega, lm):
     rng = np.random.default_rng(72)
     for level in (0, ctx.num_levels() - 1):
         gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
-        L = kkt.Level(gl, N, dt, K / 1e-2, omega=omega, lm=max(lm, 0.0), velocity="vorticity")
+        L = kkt.Level(gl, N, dt, K / 1e-2, omega=omega, lm=max(lm, 0.0), velocity="vorticity", local_adv=LOCAL_ADV)
         x = _state(gl, N, rng, 0.3, prec)
         w = _q(_faces(gl, rng, N), prec)
         res = _state(gl, N, rng, 1.0, prec) if level > 0 else None
@@ -103,7 +105,7 @@ def test_rotational_vcycles(n, N, prec):
     xd = _dev(x, prec)
     flag(f"rotational nso n={n} N={N} {prec}")
     nv, hist = S.stfas_op_nso(ctx, xd, to_dev(w, prec))
-    H = stfas.Hierarchy(g, N, dt, K / r, omega=0.7, lm=1.0, velocity="vorticity")
+    H = stfas.Hierarchy(g, N, dt, K / r, omega=0.7, lm=1.0, velocity="vorticity", local_adv=LOCAL_ADV)
     nv_ref, hist_ref = stfas.nso(H, x, w, max_vcycles=3, fixed_counts=True)
     assert nv == nv_ref == 3
     for k in range(4):
@@ -125,7 +127,7 @@ def _solve_pair(w, prec, **kw):
     flag(f"rotational solve n={w['n']} N={N} {prec} {kw}")
     st = S.stfas_solve(ctx, to_dev(rho0, prec), ks, to_dev(np.stack([keys[k] for k in ks]), prec), u)
     ctx.destroy()
-    ref = admm.solve(admm.Problem(velocity="vorticity", **args), rho0, keys)
+    ref = admm.solve(admm.Problem(velocity="vorticity", local_adv=LOCAL_ADV, **args), rho0, keys)
     return to_np(u).reshape(N, -1), st, ref
 
 

@@ -133,3 +133,48 @@ def test_kkt_rotational_f1_is_the_reduced_gradient(rng):
         fd = (jred([a + e * b for a, b in zip(vs, dvs)]) - jred([a - e * b for a, b in zip(vs, dvs)])) / (2 * e)
         ad = sum(f[0][j] @ dvs[j + 1] for j in range(N))
         assert abs(fd - ad) <= 1e-5 * max(abs(fd), 1.0)
+
+
+def _colour_rows(g, colour):
+    from oracle import scgs
+    cells = scgs.colour_cells(g, colour)
+    faces = set()
+    for a in range(g.dim):
+        for off in (0, 1):
+            idx = cells.copy()
+            idx[:, a] += off
+            faces.update(scgs._face_flat(g, a, idx).tolist())
+    faces = np.array(sorted(faces))
+    return faces[g.interior_mask()[faces] > 0], scgs._cell_flat(g, cells)
+
+
+@pytest.mark.parametrize("n", [(8, 8), (9, 6)])
+def test_local_block_is_the_exact_jacobian_at_zero_u(n, rng):
+    """eq:HESS with the cell's block of dAdv/dv: at u = 0 (where the second
+    derivative of Adv that eq:HESS leaves out is multiplied by zero) it is
+    the exact Jacobian of the colour's rows in the colour's unknowns, so one
+    pass with omega = 1 is a Newton step on those rows: what is left there
+    falls with the square of the right-hand side's defect.  Without the
+    block (the collapsed local matrix) it falls only linearly."""
+    from oracle import scgs
+    g = Grid(n)
+    N, dt, kr = 4, 0.6 * g.h, 5.0
+    x0 = [np.stack([_faces(g, rng, 0.8) for _ in range(N)]), rng.standard_normal((N, g.ncell)) * 0.3,
+          np.zeros((N, g.nface)), rng.standard_normal((N, g.ncell)) * 0.3]
+    w = np.stack([_faces(g, rng, 0.5) for _ in range(N)])
+    z = [np.stack([_faces(g, rng) for _ in range(N)]), rng.standard_normal((N, g.ncell)),
+         np.stack([_faces(g, rng) for _ in range(N)]), rng.standard_normal((N, g.ncell))]
+    for colour in range(4):
+        fr, cr = _colour_rows(g, colour)
+        for local_adv, order in ((True, 2.0), (False, 1.0)):
+            L = kkt.Level(g, N, dt, kr, velocity="vorticity", local_adv=local_adv)
+            f0 = kkt.residual_f(L, x0, w)
+            left = []
+            for eps in (1e-3, 1e-4):
+                x = [a.copy() for a in x0]
+                res = [a + eps * b for a, b in zip(f0, z)]
+                scgs.smooth_colour(L, x, w, res, colour)
+                r = kkt.residual(L, x, w, res)
+                left.append(max(np.max(np.abs(r[0][:, fr])), np.max(np.abs(r[2][:, fr])),
+                                np.max(np.abs(r[1][:, cr])), np.max(np.abs(r[3][:, cr]))))
+            assert 10 ** (order - 0.15) <= left[0] / left[1] <= 10 ** (order + 0.15), (colour, local_adv, left)
