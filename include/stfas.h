@@ -73,8 +73,9 @@ typedef enum { STFAS_DENSITY_SL = 0, STFAS_DENSITY_UPWIND = 1 } stfas_density;
  * (2D only): the paper's implicit update (v_{i+1} - v_i)/dt + Adv[v_{i+1}] =
  * u_i - G p_{i+1} with Adv the vorticity form (curl v) x v, discretised with
  * the node vorticity and node-paired face products so that it does no work;
- * the KKT residual is eq:KKTAO as printed (du_{i-1}/dv_i = I/dt + dAdv/dv_i)
- * and the re-simulation of the outputs (and stfas_step_forward) takes 4
+ * the KKT residual is eq:KKTAO as printed (du_{i-1}/dv_i = I/dt + dAdv/dv_i),
+ * the smoother's local matrix is eq:HESS with the cell's block of dAdv/dv
+ * (Sec. 4.3, solved by block elimination in time), and the re-simulation of the outputs (and stfas_step_forward) takes 4
  * fixed-point steps per time step.  stfas_lbfgs and stfas_step_backward
  * accept only the semi-Lagrangian operator (STFAS_E_INVALID otherwise). */
 typedef enum { STFAS_VELOCITY_SL = 0, STFAS_VELOCITY_ROTATIONAL = 1 } stfas_velocity;
@@ -98,7 +99,8 @@ typedef struct {
     double poisson_rtol;    /* projection relative residual; default 1e-13 (FP64) / 1e-6 (MIXED) */
     int32_t fixed_counts;   /* 1: ignore eps_*, run exactly max_admm and max_vcycles (parity mode) */
     int32_t precision;      /* stfas_precision */
-    double scgs_omega;      /* relaxation weight of the SCGS smoother (Sec. 4.3), in (0, 2]; <= 0 selects 0.7 */
+    double scgs_omega;      /* relaxation weight of the SCGS smoother (Sec. 4.3), in (0, 2]; <= 0 selects 0.7
+                             * (1 with the rotational velocity operator) */
     int32_t density_op;     /* stfas_density; 0 = semi-Lagrangian */
     double al_tol;          /* augmented-Lagrangian fallback of the ADMM loop (Sec. 5, convergence
                              * analysis): > 0 makes the multiplier update of an iteration t > 1 only
@@ -107,7 +109,7 @@ typedef struct {
     double scgs_lm;         /* Levenberg-Marquardt perturbation of K in the smoother's local matrix
                              * (Sec. 5, convergence analysis; eq:HESS): K/r on every v block becomes
                              * K/r + scgs_lm / dt^2 (the residual is unchanged, so is the solution);
-                             * 0 selects 1; < 0 turns it off */
+                             * 0 selects 1 (off with the rotational velocity operator); < 0 turns it off */
     int32_t velocity_op;    /* stfas_velocity; 0 = semi-Lagrangian; 1 (rotational) needs dim = 2 */
 } stfas_problem;
 

@@ -56,10 +56,11 @@ class Problem:
     max_vcycles: int = 30
     metric_levels: int = -1
     fixed_counts: bool = False
-    scgs_omega: float = 0.7
+    scgs_omega: float = 0.0           # relaxation weight of the smoother (<= 0: 0.7, 1 with "vorticity")
     density: str = "sl"               # density operator: "sl" or "upwind" (eq:Adv)
     al_tol: float = 0.0               # augmented-Lagrangian fallback threshold (0: plain ADMM)
-    scgs_lm: float = 1.0              # smoother's Levenberg-Marquardt perturbation times dt^2 (< 0: off)
+    scgs_lm: float = 0.0              # smoother's Levenberg-Marquardt perturbation times dt^2
+                                      # (< 0: off; 0: 1, off with "vorticity")
     velocity: str = "sl"              # velocity operator: "sl" or "vorticity" (eq:NSA's Adv, 2D)
     local_adv: bool = True            # vorticity: dAdv/dv in the smoother's local matrix (eq:HESS)
 
@@ -71,8 +72,13 @@ class Problem:
             p.K = p.r / (p.dt * p.dt)
         if p.metric_levels < 0:
             p.metric_levels = metric.default_levels(p.n)
+        # with the rotational operator the smoother solves eq:HESS with its exact
+        # local block: no relaxation and no perturbation unless asked for
+        rot = p.velocity == "vorticity"
+        if p.scgs_omega <= 0:
+            p.scgs_omega = 1.0 if rot else 0.7
         if p.scgs_lm == 0:
-            p.scgs_lm = 1.0
+            p.scgs_lm = -1.0 if rot else 1.0
         if p.eps_admm <= 0:
             p.eps_admm = float(np.max(rho0)) / 100.0
         return p

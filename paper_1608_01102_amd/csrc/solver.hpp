@@ -20,6 +20,7 @@
 #include "k_kkt.hpp"
 #include "k_misc.hpp"
 #include "k_poisson.hpp"
+#include "k_rot_scgs.hpp"
 #include "k_upwind.hpp"
 
 namespace stfas {
@@ -88,17 +89,19 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     o.precision = p->precision;
     o.poisson_rtol = p->poisson_rtol > 0 ? p->poisson_rtol : (o.precision == STFAS_FP64 ? 1e-13 : 1e-6);
     o.fixed_counts = p->fixed_counts ? 1 : 0;
-    o.omega = p->scgs_omega > 0 ? p->scgs_omega : 0.7;
+    if (p->velocity_op != STFAS_VELOCITY_SL && p->velocity_op != STFAS_VELOCITY_ROTATIONAL) return false;
+    if (p->velocity_op == STFAS_VELOCITY_ROTATIONAL && o.dim != 2) return false;
+    o.vort = p->velocity_op == STFAS_VELOCITY_ROTATIONAL ? 1 : 0;
+    // the rotational operator's smoother solves eq:HESS with its exact local
+    // block: no relaxation and no perturbation unless asked for
+    o.omega = p->scgs_omega > 0 ? p->scgs_omega : (o.vort ? 1.0 : 0.7);
     if (!(o.omega <= 2.0)) return false;
     if (p->density_op != STFAS_DENSITY_SL && p->density_op != STFAS_DENSITY_UPWIND) return false;
     o.density = p->density_op;
     if (!(p->al_tol >= 0) || !std::isfinite(p->al_tol)) return false;
     o.al_tol = p->al_tol;
     if (std::isnan(p->scgs_lm) || std::isinf(p->scgs_lm)) return false;
-    o.lm = (p->scgs_lm < 0 ? 0.0 : (p->scgs_lm > 0 ? p->scgs_lm : 1.0)) / (o.dt * o.dt);
-    if (p->velocity_op != STFAS_VELOCITY_SL && p->velocity_op != STFAS_VELOCITY_ROTATIONAL) return false;
-    if (p->velocity_op == STFAS_VELOCITY_ROTATIONAL && o.dim != 2) return false;
-    o.vort = p->velocity_op == STFAS_VELOCITY_ROTATIONAL ? 1 : 0;
+    o.lm = (p->scgs_lm < 0 ? 0.0 : (p->scgs_lm > 0 ? p->scgs_lm : (o.vort ? 0.0 : 1.0))) / (o.dt * o.dt);
     const double total = (double)o.n[0] * o.n[1] * o.n[2];
     if (total > 2.0e9 / (o.dim + 1)) return false;
     return true;
@@ -590,6 +593,7 @@ public:
     };
     std::vector<Lev> lev;
     T* scgs_scratch = nullptr;   // two-kernel SCGS path only (horizons too long for the fused kernel)
+    T* rot_scratch = nullptr;    // rotational operator: the local blocks of one colour (ROT_BLK_WORDS per cell-slot)
     T *t1a = nullptr, *t1b = nullptr;   // J_S^T part of F1 for the SCGS colour passes (any level)
     T *t1_zero = nullptr, *t1_used = nullptr;   // t1a / t1b: the one that is all zero, the other
     T* tq = nullptr;                            // quarters of the 3D sweep transpose (k_quarter_gather)
@@ -669,6 +673,11 @@ public:
             long maxcol = 0;
             for (int c = 0; c < (1 << D); ++c) maxcol = std::max<long>(maxcol, colour_set(L[0], c).total);
             scgs_scratch = A.take<T>((size_t)maxcol * 2 * D * 2 * N);
+        }
+        if (P.vort) {
+            long maxcol = 0;
+            for (int c = 0; c < (1 << D); ++c) maxcol = std::max<long>(maxcol, colour_set(L[0], c).total);
+            rot_scratch = A.take<T>((size_t)maxcol * N * ROT_BLK_WORDS);
         }
         t_diag = A.take<T>(2 * N);
         t_sub = A.take<T>(2 * N);
@@ -1014,6 +1023,21 @@ public:
         return tot;
     }
 
+    // Local solves of one colour with the rotational operator: eq:HESS with the
+    // cell's block of dAdv/dv, reduced to 3x3 blocks and eliminated in time.
+    void rot_local_solve(int l, int colour) {
+        const Grid& g = L[l];
+        Lev& q = lev[l];
+        const ColourSet cs = colour_set(g, colour);
+        const long n = (long)cs.total * N;
+        const T dt = (T)P.dt, kr = (T)(P.K / P.r), lm = (T)P.lm;
+        k_rot_blk_setup<T><<<blocks_for(n, 256), 256, 0, st>>>(g, N, cs, dt, kr, lm, q.v, q.r1, q.r2, q.r3, q.r4,
+                                                              rot_scratch);
+        k_rot_blk_thomas<T><<<blocks_for(cs.total, 64), 64, 0, st>>>(N, cs.total, dt, rot_scratch);
+        k_rot_blk_apply<T><<<blocks_for(n, 256), 256, 0, st>>>(g, N, cs, dt, kr, lm, (T)P.omega, q.v, q.pb, q.u,
+                                                              q.p, q.r1, q.r2, q.r3, q.r4, rot_scratch);
+    }
+
     // One SCGS sweep on level l.  3D: the J_S^T part of F1 once from the state
     // at the sweep's start, held for every colour, then per colour its rows
     // and its local solves.  2D: per colour, its rows and the J_S^T part from
@@ -1036,8 +1060,9 @@ public:
             if (D == 3) {
                 kkt_rows(l, colour);
             } else if (P.vort) {
-                t1 = t1_zero;                       // stays zero: the rows carry every term of F1
-                kkt_rows(l, colour);
+                kkt_rows(l, colour);                // the rows carry every term of F1
+                rot_local_solve(l, colour);
+                continue;
             } else {
                 t1 = t1_zero;
                 kkt_rows(l, colour, t1, t1_used);   // t1_used is cleared for the next colour

@@ -13,8 +13,8 @@ from oracle.grid import Grid
 
 pytestmark = pytest.mark.gpu
 
-# whether the library's smoother holds the cell's block of dAdv/dv (eq:HESS)
-LOCAL_ADV = False
+# the library's smoother holds the cell's block of dAdv/dv (eq:HESS)
+LOCAL_ADV = True
 CASES = [((16, 12), 4), ((20, 12), 5), ((16, 16), 3), ((9, 7), 2)]
 PRECS = ["fp64", "mixed"]
 
@@ -89,15 +89,17 @@ def test_rotational_scgs_sweep(n, N, prec, omega, lm):
     ctx.destroy()
 
 
+@pytest.mark.parametrize("omega,lm", [(0.0, 0.0), (0.7, 1.0)])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,N", [((16, 16), 6), ((32, 32), 10)])
-def test_rotational_vcycles(n, N, prec):
+def test_rotational_vcycles(n, N, prec, omega, lm):
+    """(0, 0): the operator's defaults (omega = 1, no perturbation)."""
     from paper_1608_01102_amd import stfas as S
     g = Grid(n)
     dt, r = g.h, 1e-2
     K = r / dt ** 2
-    prob = S.make_problem(n, N, r, dt=dt, K=K, max_vcycles=3, fixed_counts=True, precision=prec, scgs_omega=0.7,
-                          velocity="rotational")
+    prob = S.make_problem(n, N, r, dt=dt, K=K, max_vcycles=3, fixed_counts=True, precision=prec, scgs_omega=omega,
+                          scgs_lm=lm, velocity="rotational")
     ctx = S.stfas_create(prob)
     rng = np.random.default_rng(73)
     w = _q(np.stack([synthetic.curl_noise_velocity(n, rng, 1.0, 0.8) for _ in range(N)]), prec)
@@ -105,12 +107,16 @@ def test_rotational_vcycles(n, N, prec):
     xd = _dev(x, prec)
     flag(f"rotational nso n={n} N={N} {prec}")
     nv, hist = S.stfas_op_nso(ctx, xd, to_dev(w, prec))
-    H = stfas.Hierarchy(g, N, dt, K / r, omega=0.7, lm=1.0, velocity="vorticity", local_adv=LOCAL_ADV)
+    H = stfas.Hierarchy(g, N, dt, K / r, omega=omega or 1.0, lm=lm, velocity="vorticity", local_adv=LOCAL_ADV)
     nv_ref, hist_ref = stfas.nso(H, x, w, max_vcycles=3, fixed_counts=True)
     assert nv == nv_ref == 3
     for k in range(4):
         assert rel(to_np(xd[k]), x[k]) <= TOL[prec], k
-    assert np.allclose(hist, hist_ref, rtol=1e-8 if prec == "fp64" else 1e-3)
+    # the mixed form evaluates the residual in FP32 from terms of the size of
+    # the first residual: once the cycles have cut it by 1e5 its FP32 rounding
+    # (about 1e-7 of those terms) is a visible fraction of it
+    atol = 0.0 if prec == "fp64" else 1e-6 * hist_ref[0]
+    assert np.allclose(hist, hist_ref, rtol=1e-8 if prec == "fp64" else 1e-3, atol=atol)
     ctx.destroy()
 
 

@@ -80,6 +80,12 @@ def test_velocity_operator_selection():
     from paper_1608_01102_amd import stfas as S
     ok = S.make_problem((32, 32), 10, 1e-3, velocity="rotational")
     assert S.stfas_workspace_bytes(ok) > 0
+    # its smoother keeps 21 words per (cell of the largest colour, slot): the
+    # reduced local blocks, their factors and the corrections (256-byte rounded)
+    for prec, word in (("fp64", 8), ("mixed", 4)):
+        extra = (S.stfas_workspace_bytes(S.make_problem((32, 32), 10, 1e-3, velocity="rotational", precision=prec)) -
+                 S.stfas_workspace_bytes(S.make_problem((32, 32), 10, 1e-3, precision=prec)))
+        assert extra == (16 * 16 * 10 * 21 * word + 255) // 256 * 256
     assert S.stfas_step_work_bytes(ok) == S.stfas_step_work_bytes(S.make_problem((32, 32), 10, 1e-3))
     bad3d = S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational")
     assert S.stfas_workspace_bytes(bad3d) == 0
