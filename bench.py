@@ -310,6 +310,14 @@ def rotational_run(S, w, density, kw):
     res["meets_1e-4_kf_err"] = bool(kf <= 1e-4 and all(conv))
     res["cell_updates_per_s"] = (w["n"][0] * w["n"][1] * w["num_steps"] * res["mixed"]["vcycles"]
                                  / res["mixed"]["seconds"])
+    # the smoother's other local matrices (mixed): eq:HESS's block on every
+    # level, and on none (which needs the perturbation mu dt^2 = 1 to stay finite)
+    res["smoother"] = {"default": "local block of dAdv/dv on the finest level, omega 1, no perturbation"}
+    for name, extra in (("block_every_level", dict(scgs_local="exact")),
+                        ("no_block_mu1", dict(scgs_local="collapsed", scgs_lm=1.0))):
+        st, _ = solve_once(S, w, "mixed", density, velocity="rotational", **extra, **kw)
+        res["smoother"][name] = {"admm_iters": st["admm_iters"], "vcycles": st["vcycles"],
+                                 "converged": bool(st["converged"]), "seconds": st["seconds"]}
     return res
 
 

@@ -111,6 +111,12 @@ typedef struct {
                              * K/r + scgs_lm / dt^2 (the residual is unchanged, so is the solution);
                              * 0 selects 1 (off with the rotational velocity operator); < 0 turns it off */
     int32_t velocity_op;    /* stfas_velocity; 0 = semi-Lagrangian; 1 (rotational) needs dim = 2 */
+    int32_t scgs_local;     /* local matrix of the SCGS smoother with the rotational operator (Sec. 4.3
+                             * eq:HESS): 0 = with the cell's block of dAdv/dv (block elimination in
+                             * time) on the finest level and without it below (default); 1 = without
+                             * it on every level (du_{i-1}/dv_i = I/dt, the scalar temporal solve of
+                             * the semi-Lagrangian operator); 2 = with it on every level; other
+                             * values invalid; must be 0 with the semi-Lagrangian operator */
 } stfas_problem;
 
 typedef struct {

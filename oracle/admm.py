@@ -62,7 +62,8 @@ class Problem:
     scgs_lm: float = 0.0              # smoother's Levenberg-Marquardt perturbation times dt^2
                                       # (< 0: off; 0: 1, off with "vorticity")
     velocity: str = "sl"              # velocity operator: "sl" or "vorticity" (eq:NSA's Adv, 2D)
-    local_adv: bool = True            # vorticity: dAdv/dv in the smoother's local matrix (eq:HESS)
+    local_adv: object = "finest"      # vorticity: dAdv/dv in the smoother's local matrix (eq:HESS):
+                                      # "finest" (level 0 only), True (every level), False (none)
 
     def resolved(self, rho0):
         p = Problem(**self.__dict__)

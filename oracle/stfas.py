@@ -36,7 +36,9 @@ def level_grids(g: Grid):
 class Hierarchy:
     def __init__(self, g: Grid, N, dt, K_over_r, advect=True, omega=1.0, lm=0.0, velocity="sl", local_adv=True):
         self.grids = level_grids(g)
-        self.levels = [Level(gl, N, dt, K_over_r, advect, omega, lm, velocity, local_adv) for gl in self.grids]
+        # local_adv: True on every level, False on none, "finest" on level 0 only
+        self.levels = [Level(gl, N, dt, K_over_r, advect, omega, lm, velocity,
+                             local_adv if local_adv != "finest" else l == 0) for l, gl in enumerate(self.grids)]
         self.transfers = [Transfer(gl) for gl in self.grids[:-1]]
 
     def targets(self, w):

@@ -29,6 +29,7 @@ class StfasProblem(ctypes.Structure):
         ("al_tol", c_double),
         ("scgs_lm", c_double),
         ("velocity_op", c_int32),
+        ("scgs_local", c_int32),
     ]
 
 

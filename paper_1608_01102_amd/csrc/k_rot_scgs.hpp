@@ -40,10 +40,12 @@
 
 namespace stfas {
 
-// Scratch per (cell of the colour, slot), structure of arrays:
-// [0, 9) beta_s (row-major), [9, 18) D_s, then W_s after the elimination,
-// [18, 21) reduced right-hand side, then t_s, then y_s.
-constexpr int ROT_BLK_WORDS = 21;
+// Scratch per (cell of the colour, slot), one record of ROT_BLK_WORDS words
+// (21 used, padded to a multiple of 16 bytes so the elimination reads it
+// with 16-byte loads): [0, 9) F_s = -beta_s/dt (row-major), the coupling of
+// y_{s-1} and y_s, [9, 18) D_s, [18, 21) the reduced right-hand side, which
+// the elimination replaces by y_s.
+constexpr int ROT_BLK_WORDS = 24;
 
 // The cell's block of dAdv/dv at v (rows: Adv at the face slots, columns: v
 // at the face slots).  With the node quantities of k_rot.hpp, for an x-face
@@ -220,16 +222,26 @@ __device__ inline void rot_slot_rhs(const Grid& g, const RotCell<T>& rc, const T
 
 template <typename P>
 __device__ inline P* rot_sc(P* sc, int w, int s, int total, int q, int N) {
-    return sc + ((long)w * N + s) * total + q;
+    (void)N;
+    return sc + ((long)s * total + q) * ROT_BLK_WORDS + w;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_rot_blk_setup(Grid g, int N, ColourSet cs, T dt, T kr, T lm, const T* __restrict__ v,
-                                const T* __restrict__ r1, const T* __restrict__ r2, const T* __restrict__ r3,
-                                const T* __restrict__ r4, T* __restrict__ sc) {
-    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= (long)cs.total * N) return;
-    const int q = (int)(tid % cs.total), s = (int)(tid / cs.total);
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+};
+
+// The record of (colour cell q, slot s): beta_s, D_s and the reduced right-hand side.
+template <typename T>
+__device__ inline void rot_setup_item(const Grid& g, int N, const ColourSet& cs, int q, int s, T dt, T kr, T lm,
+                                      const T* __restrict__ v, const T* __restrict__ r1, const T* __restrict__ r2,
+                                      const T* __restrict__ r3, const T* __restrict__ r4, T* rec) {
     int i, j, k;
     colour_cell(cs, q, i, j, k);
     RotCell<T> rc;
@@ -256,8 +268,8 @@ __global__ void __launch_bounds__(256) k_rot_blk_setup(Grid g, int N, ColourSet 
         for (int b = 0; b < 3; ++b) {
             T d = beta[0][a] * beta[0][b] + beta[1][a] * beta[1][b] + beta[2][a] * beta[2][b];
             if (a == b) d += rc.act[a] > 0 ? kap : (T)1;
-            *rot_sc(sc, a * 3 + b, s, cs.total, q, N) = beta[a][b];
-            *rot_sc(sc, 9 + a * 3 + b, s, cs.total, q, N) = d;
+            rec[a * 3 + b] = -beta[a][b] / dt;
+            rec[9 + a * 3 + b] = d;
         }
     // w4 = c_s + B_s^T ahat_s - B_s^T P B_s vbar_s  [- ahat_{s+1}/dt + P B_{s+1} vbar_{s+1}/dt]
     T ahat[4], vbar[4], w4[4], t4[4], p4[4];
@@ -281,42 +293,78 @@ __global__ void __launch_bounds__(256) k_rot_blk_setup(Grid g, int N, ColourSet 
     T rr[3];
     rc.zt(w4, rr);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) *rot_sc(sc, 18 + a, s, cs.total, q, N) = rr[a];
+    for (int a = 0; a < 3; ++a) rec[18 + a] = rr[a];
 }
 
-// Inverse of a symmetric positive definite 3x3 matrix (adjugate over determinant).
+
 template <typename T>
-__device__ inline void inv3(const T (&S)[3][3], T (&o)[3][3]) {
-    o[0][0] = S[1][1] * S[2][2] - S[1][2] * S[2][1];
-    o[0][1] = S[0][2] * S[2][1] - S[0][1] * S[2][2];
-    o[0][2] = S[0][1] * S[1][2] - S[0][2] * S[1][1];
-    o[1][0] = S[1][2] * S[2][0] - S[1][0] * S[2][2];
-    o[1][1] = S[0][0] * S[2][2] - S[0][2] * S[2][0];
-    o[1][2] = S[0][2] * S[1][0] - S[0][0] * S[1][2];
-    o[2][0] = S[1][0] * S[2][1] - S[1][1] * S[2][0];
-    o[2][1] = S[0][1] * S[2][0] - S[0][0] * S[2][1];
-    o[2][2] = S[0][0] * S[1][1] - S[0][1] * S[1][0];
-    const T det = S[0][0] * o[0][0] + S[0][1] * o[1][0] + S[0][2] * o[2][0];
-    const T id = (T)1 / det;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) o[a][b] *= id;
+__global__ void __launch_bounds__(256) k_rot_blk_setup(Grid g, int N, ColourSet cs, T dt, T kr, T lm, const T* __restrict__ v,
+                                const T* __restrict__ r1, const T* __restrict__ r2, const T* __restrict__ r3,
+                                const T* __restrict__ r4, T* __restrict__ sc) {
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (long)cs.total * N) return;
+    const int q = (int)(tid % cs.total), s = (int)(tid / cs.total);
+    rot_setup_item(g, N, cs, q, s, dt, kr, lm, v, r1, r2, r3, r4, rot_sc(sc, 0, s, cs.total, q, N));
 }
 
-// Elimination in time, one thread per cell of the colour; the next steps'
-// blocks are loaded RB steps ahead of their use (they do not depend on the
-// recurrence).
+__device__ inline float rot_rsq(float x) { return __builtin_amdgcn_rsqf(x); }   // x >= 1/dt^2 here
+__device__ inline double rot_rsq(double x) { return 1.0 / sqrt(x); }
+
+// Cholesky factor of a symmetric positive definite 3x3 matrix S = L L^T:
+// the three off-diagonal entries and the reciprocals of the diagonal.
 template <typename T>
-__global__ void __launch_bounds__(64) k_rot_blk_thomas(int N, int total, T dt, T* __restrict__ sc) {
+struct Chol3 {
+    T i0, i1, i2, l10, l20, l21;
+    __device__ void factor(const T (&S)[3][3]) {
+        i0 = rot_rsq(S[0][0]);
+        l10 = S[1][0] * i0;
+        l20 = S[2][0] * i0;
+        i1 = rot_rsq(S[1][1] - l10 * l10);
+        l21 = (S[2][1] - l20 * l10) * i1;
+        i2 = rot_rsq(S[2][2] - l20 * l20 - l21 * l21);
+    }
+    __device__ void lower(const T (&f)[3], T (&o)[3]) const {     // L o = f
+        o[0] = f[0] * i0;
+        o[1] = (f[1] - l10 * o[0]) * i1;
+        o[2] = (f[2] - l20 * o[0] - l21 * o[1]) * i2;
+    }
+    __device__ void upper(const T (&f)[3], T (&o)[3]) const {     // L^T o = f
+        o[2] = f[2] * i2;
+        o[1] = (f[1] - l21 * o[2]) * i1;
+        o[0] = (f[0] - l10 * o[1] - l20 * o[2]) * i0;
+    }
+};
+
+// Words of LDS per (thread, slot) in the elimination: W_s (9) and t_s (3).
+constexpr int ROT_BLK_LDS = 12;
+
+// Elimination in time, one thread per cell of the colour.  Step s factors
+// the running Schur complement S = L L^T, forms G = L^-1 F and L^-1 z for the
+// coupling F = -beta_s/dt, updates S <- D_s - G^T G and z <- rhs_s - G^T L^-1 z,
+// and keeps W = S^-1 F, t = S^-1 z for the back substitution
+// y_s = t_s - W_s y_{s+1} in LDS (blockDim.x threads x N slots x 12 words);
+// the next steps' blocks are loaded RB steps ahead of their use (they do not
+// depend on the recurrence), and no global store sits between those loads.
+template <typename T>
+__global__ void __launch_bounds__(64) k_rot_blk_thomas(int N, int total, T* __restrict__ sc) {
+    extern __shared__ __align__(16) unsigned char rot_lds_raw[];
+    T* lds = reinterpret_cast<T*>(rot_lds_raw);
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total) return;
-    constexpr int RB = 4;
+    if (q >= total) return;          // no barrier below: every thread works alone
+    const int TB = blockDim.x;
+    auto lw = [&](int s, int w) -> T& { return lds[((long)s * ROT_BLK_LDS + w) * TB + threadIdx.x]; };
+    constexpr int RB = sizeof(T) == 4 ? 8 : 4;
     T buf[RB][ROT_BLK_WORDS];
+    using V = typename Vec16<T>::type;
+    constexpr int NV = 16 / sizeof(T);
     auto load = [&](int s, T (&o)[ROT_BLK_WORDS]) {
         if (s < N) {
+            const V* src = reinterpret_cast<const V*>(rot_sc(sc, 0, s, total, q, N));
 #pragma unroll
-            for (int w = 0; w < ROT_BLK_WORDS; ++w) o[w] = *rot_sc(sc, w, s, total, q, N);
+            for (int k = 0; k < ROT_BLK_WORDS / NV; ++k) {
+                const V x = src[k];
+                __builtin_memcpy(&o[k * NV], &x, sizeof(V));
+            }
         }
     };
 #pragma unroll
@@ -329,84 +377,91 @@ __global__ void __launch_bounds__(64) k_rot_blk_thomas(int N, int total, T dt, T
         for (int b = 0; b < 3; ++b) S[a][b] = buf[0][9 + a * 3 + b];
     }
     load(RB, buf[0]);
-    const T idt = (T)1 / dt;
     for (int s0 = 1; s0 < N; s0 += RB) {
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
             const int s = s0 + u;
             if (s >= N) break;
             T(&cur)[ROT_BLK_WORDS] = buf[(1 + u) % RB];
-            // F = -beta_s/dt couples row s-1 with column s; W = S^-1 F, t = S^-1 z
-            T Si[3][3], W[3][3], t[3];
-            inv3(S, Si);
+            Chol3<T> ch;
+            ch.factor(S);
+            // G = L^-1 F column by column (F = -beta_s/dt), zz = L^-1 z
+            T G[3][3], zz[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                t[a] = Si[a][0] * z[0] + Si[a][1] * z[1] + Si[a][2] * z[2];
+            for (int b = 0; b < 3; ++b) {
+                const T f[3] = {cur[b], cur[3 + b], cur[6 + b]};
+                T gcol[3];
+                ch.lower(f, gcol);
 #pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    W[a][b] = -idt * (Si[a][0] * cur[b] + Si[a][1] * cur[3 + b] + Si[a][2] * cur[6 + b]);
+                for (int a = 0; a < 3; ++a) G[a][b] = gcol[a];
             }
+            ch.lower(z, zz);
+            // W = L^-T G, t = L^-T zz, kept for the back substitution
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                *rot_sc(sc, 18 + a, s - 1, total, q, N) = t[a];
+            for (int b = 0; b < 3; ++b) {
+                const T gcol[3] = {G[0][b], G[1][b], G[2][b]};
+                T wcol[3];
+                ch.upper(gcol, wcol);
 #pragma unroll
-                for (int b = 0; b < 3; ++b) *rot_sc(sc, 9 + a * 3 + b, s - 1, total, q, N) = W[a][b];
+                for (int a = 0; a < 3; ++a) lw(s - 1, a * 3 + b) = wcol[a];
             }
-            // S = D_s - F^T W, z = rhs_s - F^T t  (F^T = -beta_s^T/dt)
+            T t[3];
+            ch.upper(zz, t);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) lw(s - 1, 9 + a) = t[a];
+            // S = D_s - G^T G, z = rhs_s - G^T zz
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                z[a] = cur[18 + a] + idt * (cur[a] * t[0] + cur[3 + a] * t[1] + cur[6 + a] * t[2]);
+                z[a] = cur[18 + a] - (G[0][a] * zz[0] + G[1][a] * zz[1] + G[2][a] * zz[2]);
 #pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    S[a][b] = cur[9 + a * 3 + b] + idt * (cur[a] * W[0][b] + cur[3 + a] * W[1][b] + cur[6 + a] * W[2][b]);
+                for (int b = 0; b <= a; ++b) {
+                    S[a][b] = cur[9 + a * 3 + b] - (G[0][a] * G[0][b] + G[1][a] * G[1][b] + G[2][a] * G[2][b]);
+                    S[b][a] = S[a][b];
+                }
             }
             load(s + RB, cur);
         }
     }
-    T Si[3][3], y[3];
-    inv3(S, Si);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) y[a] = Si[a][0] * z[0] + Si[a][1] * z[1] + Si[a][2] * z[2];
+    T y[3];
+    {
+        Chol3<T> ch;
+        ch.factor(S);
+        T zz[3];
+        ch.lower(z, zz);
+        ch.upper(zz, y);
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) *rot_sc(sc, 18 + a, N - 1, total, q, N) = y[a];
-    // y_s = t_s - W_s y_{s+1}, the factors again loaded RB steps ahead
-    constexpr int BW = 12;
-    T bb[RB][BW];
-    auto loadb = [&](int s, T (&o)[BW]) {
-        if (s >= 0) {
+    for (int s = N - 2; s >= 0; --s) {
+        T yn[3];
 #pragma unroll
-            for (int w = 0; w < BW; ++w) o[w] = *rot_sc(sc, 9 + w, s, total, q, N);
-        }
-    };
+        for (int a = 0; a < 3; ++a)
+            yn[a] = lw(s, 9 + a) - (lw(s, a * 3) * y[0] + lw(s, a * 3 + 1) * y[1] + lw(s, a * 3 + 2) * y[2]);
 #pragma unroll
-    for (int b = 0; b < RB; ++b) loadb(N - 2 - b, bb[b]);
-    for (int s0 = N - 2; s0 >= 0; s0 -= RB) {
-#pragma unroll
-        for (int u = 0; u < RB; ++u) {
-            const int s = s0 - u;
-            if (s < 0) break;
-            T(&cur)[BW] = bb[u];
-            T yn[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) yn[a] = cur[9 + a] - (cur[a * 3] * y[0] + cur[a * 3 + 1] * y[1] + cur[a * 3 + 2] * y[2]);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                y[a] = yn[a];
-                *rot_sc(sc, 18 + a, s, total, q, N) = y[a];
-            }
-            loadb(s - RB, cur);
+        for (int a = 0; a < 3; ++a) {
+            y[a] = yn[a];
+            *rot_sc(sc, 18 + a, s, total, q, N) = y[a];
         }
     }
 }
 
+// Threads per block of the elimination: LDS holds 12 words per (thread,
+// slot), within 64 KB; at least one thread (N <= 1024 fits even in FP64).
 template <typename T>
-__global__ void __launch_bounds__(256) k_rot_blk_apply(Grid g, int N, ColourSet cs, T dt, T kr, T lm, T omega, T* __restrict__ v,
-                                T* __restrict__ pb, T* __restrict__ u, T* __restrict__ p, const T* __restrict__ r1,
-                                const T* __restrict__ r2, const T* __restrict__ r3, const T* __restrict__ r4,
-                                const T* __restrict__ sc) {
-    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= (long)cs.total * N) return;
-    const int q = (int)(tid % cs.total), s = (int)(tid / cs.total);
+inline int rot_blk_threads(int N) {
+    int tb = 64;
+    while (tb > 1 && (long)tb * N * ROT_BLK_LDS * sizeof(T) > 65536) tb >>= 1;
+    return tb;
+}
+
+// The corrections of (colour cell q, slot s) from y_s (in rec) and y_{s-1}
+// (in prev, used when s > 0), relaxed by omega and added to the state.
+template <typename T>
+__device__ inline void rot_apply_item(const Grid& g, int N, const ColourSet& cs, int q, int s, T dt, T kr, T lm,
+                                      T omega, T* __restrict__ v, T* __restrict__ pb, T* __restrict__ u,
+                                      T* __restrict__ p, const T* __restrict__ r1, const T* __restrict__ r2,
+                                      const T* __restrict__ r3, const T* __restrict__ r4, const T* rec,
+                                      const T* prev) {
     int i, j, k;
     colour_cell(cs, q, i, j, k);
     RotCell<T> rc;
@@ -416,14 +471,14 @@ __global__ void __launch_bounds__(256) k_rot_blk_apply(Grid g, int N, ColourSet 
     rot_cell_B<T>(g, rc, vs, i, j, dt, B);       // before this thread changes v_s
     T y[3], dv[4], dvp[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) y[a] = *rot_sc(sc, 18 + a, s, cs.total, q, N);
+    for (int a = 0; a < 3; ++a) y[a] = rec[18 + a];
     rc.zy(y, dv);
     const T e = r2[(long)s * g.ncell + rc.cell];
 #pragma unroll
     for (int r = 0; r < 4; ++r) dv[r] += rc.gv[r] * e / rc.gg;
     if (s > 0) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) y[a] = *rot_sc(sc, 18 + a, s - 1, cs.total, q, N);
+        for (int a = 0; a < 3; ++a) y[a] = prev[18 + a];
         rc.zy(y, dvp);
         const T ep = r2[(long)(s - 1) * g.ncell + rc.cell];
 #pragma unroll
@@ -459,6 +514,165 @@ __global__ void __launch_bounds__(256) k_rot_blk_apply(Grid g, int N, ColourSet 
         }
     p[(long)s * g.ncell + rc.cell] += omega * dp;
     pb[(long)s * g.ncell + rc.cell] += omega * dpb;
+}
+
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_rot_blk_apply(Grid g, int N, ColourSet cs, T dt, T kr, T lm, T omega, T* __restrict__ v,
+                                T* __restrict__ pb, T* __restrict__ u, T* __restrict__ p, const T* __restrict__ r1,
+                                const T* __restrict__ r2, const T* __restrict__ r3, const T* __restrict__ r4,
+                                const T* __restrict__ sc) {
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (long)cs.total * N) return;
+    const int q = (int)(tid % cs.total), s = (int)(tid / cs.total);
+    rot_apply_item(g, N, cs, q, s, dt, kr, lm, omega, v, pb, u, p, r1, r2, r3, r4, rot_sc(sc, 0, s, cs.total, q, N),
+                   s > 0 ? rot_sc(sc, 0, s - 1, cs.total, q, N) : (const T*)nullptr);
+}
+
+// Elimination of one cell whose records (slot s at rec + s * stride) are in
+// LDS: the same steps as k_rot_blk_thomas; W_{s-1}, t_{s-1} replace D_{s-1}
+// and the right-hand side of slot s - 1, y_s replaces t_s.  Each step reads
+// the next step's record before it writes its own results, so the reads
+// need not wait for the writes (the compiler cannot tell the two apart).
+template <typename T>
+__device__ inline void rot_eliminate_local(T* rec, int stride, int N) {
+    T S[3][3], z[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        z[a] = rec[18 + a];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) S[a][b] = rec[9 + a * 3 + b];
+    }
+    auto load = [&](int s, T (&o)[21]) {
+        const T* x = rec + (long)s * stride;
+#pragma unroll
+        for (int w = 0; w < 21; ++w) o[w] = x[w];
+    };
+    // one step: S = L L^T, G = L^-1 F_s, zz = L^-1 z; S <- D_s - G^T G,
+    // z <- rhs_s - G^T zz; slot s - 1 keeps W = L^-T G and t = L^-T zz
+    auto step = [&](int s, const T (&cur)[21]) {
+        T* prv = rec + (long)(s - 1) * stride;
+        Chol3<T> ch;
+        ch.factor(S);
+        T G[3][3], zz[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const T f[3] = {cur[b], cur[3 + b], cur[6 + b]};
+            T gcol[3];
+            ch.lower(f, gcol);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) G[a][b] = gcol[a];
+        }
+        ch.lower(z, zz);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            z[a] = cur[18 + a] - (G[0][a] * zz[0] + G[1][a] * zz[1] + G[2][a] * zz[2]);
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                S[a][b] = cur[9 + a * 3 + b] - (G[0][a] * G[0][b] + G[1][a] * G[1][b] + G[2][a] * G[2][b]);
+                S[b][a] = S[a][b];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const T gcol[3] = {G[0][b], G[1][b], G[2][b]};
+            T wcol[3];
+            ch.upper(gcol, wcol);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) prv[9 + a * 3 + b] = wcol[a];
+        }
+        T t[3];
+        ch.upper(zz, t);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) prv[18 + a] = t[a];
+    };
+    // two buffers in turn: the next record is read before a step writes
+    T ba[21], bb[21];
+    if (N > 1) load(1, ba);
+    for (int s = 1; s < N; s += 2) {
+        if (s + 1 < N) load(s + 1, bb);
+        step(s, ba);
+        if (s + 1 >= N) break;
+        if (s + 2 < N) load(s + 2, ba);
+        step(s + 1, bb);
+    }
+    T y[3];
+    {
+        Chol3<T> ch;
+        ch.factor(S);
+        T zz[3];
+        ch.lower(z, zz);
+        ch.upper(zz, y);
+    }
+    T* last = rec + (long)(N - 1) * stride;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) last[18 + a] = y[a];
+    auto loadb = [&](int s, T (&o)[12]) {
+        const T* x = rec + (long)s * stride + 9;
+#pragma unroll
+        for (int w = 0; w < 12; ++w) o[w] = x[w];
+    };
+    auto back = [&](int s, const T (&r)[12]) {
+        T yn[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) yn[a] = r[9 + a] - (r[a * 3] * y[0] + r[a * 3 + 1] * y[1] + r[a * 3 + 2] * y[2]);
+        T* o = rec + (long)s * stride + 18;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            y[a] = yn[a];
+            o[a] = y[a];
+        }
+    };
+    T ca[12], cb[12];
+    if (N > 1) loadb(N - 2, ca);
+    for (int s = N - 2; s >= 0; s -= 2) {
+        if (s > 0) loadb(s - 1, cb);
+        back(s, ca);
+        if (s == 0) break;
+        if (s > 1) loadb(s - 2, ca);
+        back(s - 1, cb);
+    }
+}
+
+// One launch per colour for horizons whose records fit in LDS: a block takes
+// TB cells of the colour; its threads form the records of every (cell, slot)
+// in LDS, one thread per cell eliminates in time, and the threads add the
+// corrections per (cell, slot).  Cells of one colour share nothing the
+// others write, so blocks need no ordering among themselves.
+template <typename T>
+__global__ void __launch_bounds__(512) k_rot_blk_fused(Grid g, int N, ColourSet cs, int TB, T dt, T kr, T lm, T omega,
+                                                       T* __restrict__ v, T* __restrict__ pb, T* __restrict__ u,
+                                                       T* __restrict__ p, const T* __restrict__ r1,
+                                                       const T* __restrict__ r2, const T* __restrict__ r3,
+                                                       const T* __restrict__ r4) {
+    extern __shared__ __align__(16) unsigned char rot_lds_raw[];
+    T* lds = reinterpret_cast<T*>(rot_lds_raw);
+    const int stride = ROT_BLK_WORDS;
+    const int cstride = N * ROT_BLK_WORDS + 16 / (int)sizeof(T);     // per cell, padded off the bank stride
+    const int c0 = blockIdx.x * TB;
+    const int nc = min(TB, cs.total - c0);
+    const int items = nc * N;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int cl = it % nc, s = it / nc;
+        rot_setup_item(g, N, cs, c0 + cl, s, dt, kr, lm, v, r1, r2, r3, r4, lds + (long)cl * cstride + s * stride);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) rot_eliminate_local(lds + (long)threadIdx.x * cstride, stride, N);
+    __syncthreads();
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int cl = it % nc, s = it / nc;
+        const T* rec = lds + (long)cl * cstride + s * stride;
+        rot_apply_item(g, N, cs, c0 + cl, s, dt, kr, lm, omega, v, pb, u, p, r1, r2, r3, r4, rec,
+                       s > 0 ? rec - stride : (const T*)nullptr);
+    }
+}
+
+// Cells per block of the fused launch (records within 64 KB of LDS), 0 when
+// one cell's records do not fit (the three-launch form then runs).
+template <typename T>
+inline int rot_fused_cells(int N) {
+    const long per = ((long)N * ROT_BLK_WORDS + 16 / (long)sizeof(T)) * (long)sizeof(T);
+    return (int)std::min<long>(8, 65536 / per);
 }
 
 }  // namespace stfas

@@ -53,6 +53,7 @@ struct Params {
     double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol, omega, al_tol, lm;
     int ao_iters, max_admm, max_vcycles, metric_levels, fixed_counts, precision, density;
     int vort;   // 1: the rotational velocity operator (eq:NSA's Adv, 2D)
+    int rot_exact;   // levels (from the finest) whose smoother's local matrix holds the cell's block of dAdv/dv
 };
 
 inline int default_metric_levels(const int* n, int dim) {
@@ -92,6 +93,8 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     if (p->velocity_op != STFAS_VELOCITY_SL && p->velocity_op != STFAS_VELOCITY_ROTATIONAL) return false;
     if (p->velocity_op == STFAS_VELOCITY_ROTATIONAL && o.dim != 2) return false;
     o.vort = p->velocity_op == STFAS_VELOCITY_ROTATIONAL ? 1 : 0;
+    if (p->scgs_local != 0 && !(o.vort && (p->scgs_local == 1 || p->scgs_local == 2))) return false;
+    o.rot_exact = !o.vort ? 0 : (p->scgs_local == 0 ? 1 : (p->scgs_local == 2 ? 1 << 20 : 0));
     // the rotational operator's smoother solves eq:HESS with its exact local
     // block: no relaxation and no perturbation unless asked for
     o.omega = p->scgs_omega > 0 ? p->scgs_omega : (o.vort ? 1.0 : 0.7);
@@ -593,7 +596,7 @@ public:
     };
     std::vector<Lev> lev;
     T* scgs_scratch = nullptr;   // two-kernel SCGS path only (horizons too long for the fused kernel)
-    T* rot_scratch = nullptr;    // rotational operator: the local blocks of one colour (ROT_BLK_WORDS per cell-slot)
+    T* rot_scratch = nullptr;    // rotational operator, long horizons: the local blocks of one colour (ROT_BLK_WORDS per cell-slot)
     T *t1a = nullptr, *t1b = nullptr;   // J_S^T part of F1 for the SCGS colour passes (any level)
     T *t1_zero = nullptr, *t1_used = nullptr;   // t1a / t1b: the one that is all zero, the other
     T* tq = nullptr;                            // quarters of the 3D sweep transpose (k_quarter_gather)
@@ -674,7 +677,7 @@ public:
             for (int c = 0; c < (1 << D); ++c) maxcol = std::max<long>(maxcol, colour_set(L[0], c).total);
             scgs_scratch = A.take<T>((size_t)maxcol * 2 * D * 2 * N);
         }
-        if (P.vort) {
+        if (P.rot_exact && rot_fused_cells<T>(N) < 1) {
             long maxcol = 0;
             for (int c = 0; c < (1 << D); ++c) maxcol = std::max<long>(maxcol, colour_set(L[0], c).total);
             rot_scratch = A.take<T>((size_t)maxcol * N * ROT_BLK_WORDS);
@@ -1024,16 +1027,26 @@ public:
     }
 
     // Local solves of one colour with the rotational operator: eq:HESS with the
-    // cell's block of dAdv/dv, reduced to 3x3 blocks and eliminated in time.
+    // cell's block of dAdv/dv, reduced to 3x3 blocks and eliminated in time;
+    // one launch while a cell's records fit in LDS, else three through rot_scratch.
     void rot_local_solve(int l, int colour) {
         const Grid& g = L[l];
         Lev& q = lev[l];
         const ColourSet cs = colour_set(g, colour);
         const long n = (long)cs.total * N;
         const T dt = (T)P.dt, kr = (T)(P.K / P.r), lm = (T)P.lm;
+        const int tbc = rot_fused_cells<T>(N);
+        if (tbc >= 1) {
+            const size_t lds = (size_t)tbc * ((size_t)N * ROT_BLK_WORDS + 16 / sizeof(T)) * sizeof(T);
+            k_rot_blk_fused<T><<<blocks_for(cs.total, tbc), 512, lds, st>>>(g, N, cs, tbc, dt, kr, lm, (T)P.omega, q.v,
+                                                                          q.pb, q.u, q.p, q.r1, q.r2, q.r3, q.r4);
+            return;
+        }
         k_rot_blk_setup<T><<<blocks_for(n, 256), 256, 0, st>>>(g, N, cs, dt, kr, lm, q.v, q.r1, q.r2, q.r3, q.r4,
                                                               rot_scratch);
-        k_rot_blk_thomas<T><<<blocks_for(cs.total, 64), 64, 0, st>>>(N, cs.total, dt, rot_scratch);
+        const int tb = rot_blk_threads<T>(N);
+        k_rot_blk_thomas<T><<<blocks_for(cs.total, tb), tb, (size_t)tb * N * ROT_BLK_LDS * sizeof(T), st>>>(
+            N, cs.total, rot_scratch);
         k_rot_blk_apply<T><<<blocks_for(n, 256), 256, 0, st>>>(g, N, cs, dt, kr, lm, (T)P.omega, q.v, q.pb, q.u,
                                                               q.p, q.r1, q.r2, q.r3, q.r4, rot_scratch);
     }
@@ -1059,10 +1072,13 @@ public:
             int G = 1, Lc = 0, CH = 0;
             if (D == 3) {
                 kkt_rows(l, colour);
-            } else if (P.vort) {
+            } else if (l < P.rot_exact) {
                 kkt_rows(l, colour);                // the rows carry every term of F1
                 rot_local_solve(l, colour);
                 continue;
+            } else if (P.vort) {
+                t1 = t1_zero;                       // stays zero: the rows carry every term of F1
+                kkt_rows(l, colour);
             } else {
                 t1 = t1_zero;
                 kkt_rows(l, colour, t1, t1_used);   // t1_used is cleared for the next colour

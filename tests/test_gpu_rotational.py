@@ -13,8 +13,11 @@ from oracle.grid import Grid
 
 pytestmark = pytest.mark.gpu
 
-# the library's smoother holds the cell's block of dAdv/dv (eq:HESS)
-LOCAL_ADV = True
+# the smoother's local matrix: eq:HESS with the cell's block of dAdv/dv on the
+# finest level only ("finest", the default), on every level ("exact"), or on
+# none ("collapsed")
+LOCALS = ["finest", "exact", "collapsed"]
+ORACLE_LOCAL = {"exact": True, "collapsed": False, "finest": "finest"}
 CASES = [((16, 12), 4), ((20, 12), 5), ((16, 16), 3), ((9, 7), 2)]
 PRECS = ["fp64", "mixed"]
 
@@ -36,14 +39,14 @@ def _dev(x, prec):
     return tuple(to_dev(a, prec) for a in x)
 
 
-def _ctx(n, N, prec, r=1e-2, **kw):
+def _ctx(n, N, prec, r=1e-2, local="finest", **kw):
     from paper_1608_01102_amd import stfas as S
     g = Grid(n)
     dt = 0.7 * g.h
     K = 3.0 * r / dt ** 2
     kw.setdefault("scgs_omega", 1.0)
     kw.setdefault("scgs_lm", -1.0)
-    prob = S.make_problem(n, N, r, dt=dt, K=K, precision=prec, velocity="rotational", **kw)
+    prob = S.make_problem(n, N, r, dt=dt, K=K, precision=prec, velocity="rotational", scgs_local=local, **kw)
     return S, S.stfas_create(prob), g, dt, K
 
 
@@ -54,7 +57,7 @@ def test_rotational_kkt_residual_all_levels(n, N, prec):
     rng = np.random.default_rng(71)
     for level in range(ctx.num_levels()):
         gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
-        L = kkt.Level(gl, N, dt, K / 1e-2, velocity="vorticity", local_adv=LOCAL_ADV)
+        L = kkt.Level(gl, N, dt, K / 1e-2, velocity="vorticity")
         x = _state(gl, N, rng, 0.5, prec)
         w = _q(_faces(gl, rng, N), prec)
         res = _state(gl, N, rng, 1.0, prec)
@@ -67,15 +70,17 @@ def test_rotational_kkt_residual_all_levels(n, N, prec):
     ctx.destroy()
 
 
+@pytest.mark.parametrize("local", LOCALS)
 @pytest.mark.parametrize("omega,lm", [(1.0, -1.0), (0.7, 1.0)])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,N", CASES)
-def test_rotational_scgs_sweep(n, N, prec, omega, lm):
-    S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=omega, scgs_lm=lm)
+def test_rotational_scgs_sweep(n, N, prec, omega, lm, local):
+    S, ctx, g, dt, K = _ctx(n, N, prec, local=local, scgs_omega=omega, scgs_lm=lm)
     rng = np.random.default_rng(72)
     for level in (0, ctx.num_levels() - 1):
         gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
-        L = kkt.Level(gl, N, dt, K / 1e-2, omega=omega, lm=max(lm, 0.0), velocity="vorticity", local_adv=LOCAL_ADV)
+        L = kkt.Level(gl, N, dt, K / 1e-2, omega=omega, lm=max(lm, 0.0), velocity="vorticity",
+                      local_adv=local == "exact" or (local == "finest" and level == 0))
         x = _state(gl, N, rng, 0.3, prec)
         w = _q(_faces(gl, rng, N), prec)
         res = _state(gl, N, rng, 1.0, prec) if level > 0 else None
@@ -89,17 +94,38 @@ def test_rotational_scgs_sweep(n, N, prec, omega, lm):
     ctx.destroy()
 
 
+@pytest.mark.parametrize("prec,N", [("fp64", 342), ("mixed", 683)])
+def test_rotational_scgs_sweep_long_horizon(prec, N):
+    """Horizons whose local records (24 words per slot) pass 64 KB per cell
+    take the three-launch form of the local solve (records in the workspace)."""
+    n = (8, 8)
+    S, ctx, g, dt, K = _ctx(n, N, prec)
+    rng = np.random.default_rng(75)
+    L = kkt.Level(g, N, dt, K / 1e-2, velocity="vorticity")
+    x = _state(g, N, rng, 0.3, prec)
+    w = _q(_faces(g, rng, N), prec)
+    xd = _dev(x, prec)
+    flag(f"rotational scgs long horizon N={N} {prec}")
+    S.stfas_op_scgs_sweep(ctx, 0, xd, to_dev(w, prec), None)
+    ref = [a.copy() for a in x]
+    scgs.sweep(L, ref, w, [np.zeros_like(a) for a in x])
+    for k in range(4):
+        assert rel(to_np(xd[k]), ref[k]) <= TOL[prec], k
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("local", LOCALS)
 @pytest.mark.parametrize("omega,lm", [(0.0, 0.0), (0.7, 1.0)])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,N", [((16, 16), 6), ((32, 32), 10)])
-def test_rotational_vcycles(n, N, prec, omega, lm):
+def test_rotational_vcycles(n, N, prec, omega, lm, local):
     """(0, 0): the operator's defaults (omega = 1, no perturbation)."""
     from paper_1608_01102_amd import stfas as S
     g = Grid(n)
     dt, r = g.h, 1e-2
     K = r / dt ** 2
     prob = S.make_problem(n, N, r, dt=dt, K=K, max_vcycles=3, fixed_counts=True, precision=prec, scgs_omega=omega,
-                          scgs_lm=lm, velocity="rotational")
+                          scgs_lm=lm, velocity="rotational", scgs_local=local)
     ctx = S.stfas_create(prob)
     rng = np.random.default_rng(73)
     w = _q(np.stack([synthetic.curl_noise_velocity(n, rng, 1.0, 0.8) for _ in range(N)]), prec)
@@ -107,7 +133,7 @@ def test_rotational_vcycles(n, N, prec, omega, lm):
     xd = _dev(x, prec)
     flag(f"rotational nso n={n} N={N} {prec}")
     nv, hist = S.stfas_op_nso(ctx, xd, to_dev(w, prec))
-    H = stfas.Hierarchy(g, N, dt, K / r, omega=omega or 1.0, lm=lm, velocity="vorticity", local_adv=LOCAL_ADV)
+    H = stfas.Hierarchy(g, N, dt, K / r, omega=omega or 1.0, lm=lm, velocity="vorticity", local_adv=ORACLE_LOCAL[local])
     nv_ref, hist_ref = stfas.nso(H, x, w, max_vcycles=3, fixed_counts=True)
     assert nv == nv_ref == 3
     for k in range(4):
@@ -120,12 +146,12 @@ def test_rotational_vcycles(n, N, prec, omega, lm):
     ctx.destroy()
 
 
-def _solve_pair(w, prec, **kw):
+def _solve_pair(w, prec, local="finest", **kw):
     from paper_1608_01102_amd import stfas as S
     g = Grid(w["n"])
     N = w["num_steps"]
     args = dict(n=w["n"], num_steps=N, r=w["r"], dt=w["dt"], **kw)
-    ctx = S.stfas_create(S.make_problem(precision=prec, velocity="rotational", **args))
+    ctx = S.stfas_create(S.make_problem(precision=prec, velocity="rotational", scgs_local=local, **args))
     rho0 = _q(w["rho0"], prec)
     keys = {t: _q(v, prec) for t, v in w["keys"].items()}
     ks = sorted(keys)
@@ -133,14 +159,15 @@ def _solve_pair(w, prec, **kw):
     flag(f"rotational solve n={w['n']} N={N} {prec} {kw}")
     st = S.stfas_solve(ctx, to_dev(rho0, prec), ks, to_dev(np.stack([keys[k] for k in ks]), prec), u)
     ctx.destroy()
-    ref = admm.solve(admm.Problem(velocity="vorticity", local_adv=LOCAL_ADV, **args), rho0, keys)
+    ref = admm.solve(admm.Problem(velocity="vorticity", local_adv=ORACLE_LOCAL[local], **args), rho0, keys)
     return to_np(u).reshape(N, -1), st, ref
 
 
+@pytest.mark.parametrize("local", LOCALS)
 @pytest.mark.parametrize("prec", PRECS)
-def test_rotational_solve_fixed_counts(prec):
+def test_rotational_solve_fixed_counts(prec, local):
     w = synthetic.small_problem((16, 16), 6, seed=2, r=1e-2)
-    u, st, ref = _solve_pair(w, prec, max_admm=3, max_vcycles=3, fixed_counts=True)
+    u, st, ref = _solve_pair(w, prec, local, max_admm=3, max_vcycles=3, fixed_counts=True)
     assert rel(u, ref.u) <= TOL[prec]
     assert abs(st["objective"] - ref.objective) <= TOL[prec] * ref.objective
     assert st["admm_iters"] == ref.admm_iters == 3 and st["vcycles"] == ref.vcycles

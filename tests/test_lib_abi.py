@@ -80,18 +80,27 @@ def test_velocity_operator_selection():
     from paper_1608_01102_amd import stfas as S
     ok = S.make_problem((32, 32), 10, 1e-3, velocity="rotational")
     assert S.stfas_workspace_bytes(ok) > 0
-    # its smoother keeps 21 words per (cell of the largest colour, slot): the
-    # reduced local blocks, their factors and the corrections (256-byte rounded)
+    # its smoother keeps a record of 24 words (21 used) per (cell, slot) in
+    # LDS while one cell's N records fit in 64 KB (no workspace); beyond, per
+    # (cell of the largest colour, slot) in the workspace (256-byte rounded)
     for prec, word in (("fp64", 8), ("mixed", 4)):
-        extra = (S.stfas_workspace_bytes(S.make_problem((32, 32), 10, 1e-3, velocity="rotational", precision=prec)) -
-                 S.stfas_workspace_bytes(S.make_problem((32, 32), 10, 1e-3, precision=prec)))
-        assert extra == (16 * 16 * 10 * 21 * word + 255) // 256 * 256
+        for N in (10, 65536 // (24 * word) + 1):
+            extra = (S.stfas_workspace_bytes(S.make_problem((32, 32), N, 1e-3, velocity="rotational", precision=prec)) -
+                     S.stfas_workspace_bytes(S.make_problem((32, 32), N, 1e-3, precision=prec)))
+            assert extra == (0 if N == 10 else (16 * 16 * N * 24 * word + 255) // 256 * 256), (prec, N)
     assert S.stfas_step_work_bytes(ok) == S.stfas_step_work_bytes(S.make_problem((32, 32), 10, 1e-3))
     bad3d = S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational")
     assert S.stfas_workspace_bytes(bad3d) == 0
     bad = S.make_problem((32, 32), 10, 1e-3)
     bad.velocity_op = 2
     assert S.stfas_workspace_bytes(bad) == 0
+    # the smoother's local matrix: the collapsed form keeps no block scratch; the
+    # switch is the rotational operator's only, and 0, 1 or 2
+    for loc in ("collapsed", "finest"):
+        col = S.make_problem((32, 32), 10, 1e-3, velocity="rotational", scgs_local=loc)
+        assert S.stfas_workspace_bytes(col) == S.stfas_workspace_bytes(S.make_problem((32, 32), 10, 1e-3))
+    for vel, loc in (("sl", 1), ("sl", 2), ("rotational", 3), ("rotational", -1)):
+        assert S.stfas_workspace_bytes(S.make_problem((32, 32), 10, 1e-3, velocity=vel, scgs_local=loc)) == 0
 
 
 def test_status_strings():
