@@ -69,15 +69,17 @@ typedef enum { STFAS_FP64 = 0, STFAS_MIXED = 1 } stfas_precision;
 typedef enum { STFAS_DENSITY_SL = 0, STFAS_DENSITY_UPWIND = 1 } stfas_density;
 
 /* Velocity operator of the dynamics (Sec. 3.1 eq:NSA).  Semi-Lagrangian:
- * v_{i+1} = Q(S(v_i) + dt u_i) with the self-advection S.  Rotational
- * (2D only): the paper's implicit update (v_{i+1} - v_i)/dt + Adv[v_{i+1}] =
- * u_i - G p_{i+1} with Adv the vorticity form (curl v) x v, discretised with
- * the node vorticity and node-paired face products so that it does no work;
- * the KKT residual is eq:KKTAO as printed (du_{i-1}/dv_i = I/dt + dAdv/dv_i),
- * the smoother's local matrix is eq:HESS with the cell's block of dAdv/dv
- * (Sec. 4.3, solved by block elimination in time), and the re-simulation of the outputs (and stfas_step_forward) takes 4
- * fixed-point steps per time step.  stfas_lbfgs and stfas_step_backward
- * accept only the semi-Lagrangian operator (STFAS_E_INVALID otherwise). */
+ * v_{i+1} = Q(S(v_i) + dt u_i) with the self-advection S.  Rotational: the
+ * paper's implicit update (v_{i+1} - v_i)/dt + Adv[v_{i+1}] = u_i - G p_{i+1}
+ * with Adv the vorticity form (curl v) x v, discretised with the vorticity
+ * on the grid's edges (the nodes in 2D) and edge-paired face products so
+ * that it does no work; the KKT residual is eq:KKTAO as printed
+ * (du_{i-1}/dv_i = I/dt + dAdv/dv_i); in 2D the smoother's local matrix is
+ * eq:HESS with the cell's block of dAdv/dv (Sec. 4.3, solved by block
+ * elimination in time; scgs_local), in 3D it leaves the block out; the
+ * re-simulation of the outputs (and stfas_step_forward) takes 4 fixed-point
+ * steps per time step.  stfas_lbfgs and stfas_step_backward accept only the
+ * semi-Lagrangian operator (STFAS_E_INVALID otherwise). */
 typedef enum { STFAS_VELOCITY_SL = 0, STFAS_VELOCITY_ROTATIONAL = 1 } stfas_velocity;
 
 /* Problem description (Sec. 3.2 eq:opt and the parameter table of Sec. 5).
@@ -109,14 +111,16 @@ typedef struct {
     double scgs_lm;         /* Levenberg-Marquardt perturbation of K in the smoother's local matrix
                              * (Sec. 5, convergence analysis; eq:HESS): K/r on every v block becomes
                              * K/r + scgs_lm / dt^2 (the residual is unchanged, so is the solution);
-                             * 0 selects 1 (off with the rotational velocity operator); < 0 turns it off */
-    int32_t velocity_op;    /* stfas_velocity; 0 = semi-Lagrangian; 1 (rotational) needs dim = 2 */
+                             * 0 selects 1 (off with the rotational velocity operator in 2D); < 0
+                             * turns it off */
+    int32_t velocity_op;    /* stfas_velocity; 0 = semi-Lagrangian, 1 = rotational */
     int32_t scgs_local;     /* local matrix of the SCGS smoother with the rotational operator (Sec. 4.3
                              * eq:HESS): 0 = with the cell's block of dAdv/dv (block elimination in
                              * time) on the finest level and without it below (default); 1 = without
                              * it on every level (du_{i-1}/dv_i = I/dt, the scalar temporal solve of
                              * the semi-Lagrangian operator); 2 = with it on every level; other
-                             * values invalid; must be 0 with the semi-Lagrangian operator */
+                             * values invalid; must be 0 with the semi-Lagrangian operator.  The
+                             * block is built for 2D: in 3D 0 and 1 both leave it out, 2 is invalid */
 } stfas_problem;
 
 typedef struct {

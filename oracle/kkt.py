@@ -19,7 +19,7 @@ operator) to the u_i coupling (explicit operator).  As in App. A, Q is
 dropped from these partials because u_i is solenoidal at the optimum.
 F1 and F3 are zero on wall faces.
 
-With the paper's own velocity operator (velocity = "vorticity", 2D; Adv of
+With the paper's own velocity operator (velocity = "vorticity", 2D or 3D; Adv of
 eq:NSA in the rotational form of vorticity.py, implicit in v_{i+1}):
 
   F1_i = (K/r)[i<N](v_i - w_i) - [i<N] u_i / dt + u_{i-1} / dt + J_Adv(v_i)^T u_{i-1} + G pbar_i
@@ -50,8 +50,8 @@ class Level:
         self.omega = omega          # relaxation weight of the smoother
         self.lm = lm                # Levenberg-Marquardt perturbation of the smoother's K/r, times dt^2
         # rotational operator: the smoother's local matrix holds the cell's block of dAdv/dv (eq:HESS);
-        # False leaves it out (du_{i-1}/dv_i = I/dt, the collapsed form of the SL operator)
-        self.local_adv = local_adv and velocity == "vorticity"
+        # False leaves it out (du_{i-1}/dv_i = I/dt, the collapsed form of the SL operator), as 3D does
+        self.local_adv = bool(local_adv) and velocity == "vorticity" and g.dim == 2
 
     def S(self, v):
         return advect.self_advect(self.g, v, self.dt, self.g.h) if self.advect else v * self.mask

@@ -7,7 +7,7 @@ exponential of eq:Adv, `kind`) and its exact adjoint.
   v'   = Q(w),  p' = phi / dt (projection; the pressure is the multiplier of
                                the divergence constraint, eq:NSB)
 
-With the paper's rotational operator (velocity = "vorticity", 2D) the
+With the paper's rotational operator (velocity = "vorticity", 2D or 3D) the
 velocity update of eq:NSA is implicit, (v' - v)/dt + Adv[v'] = u - G p'.
 Reading: it is solved by a fixed number of fixed-point (Picard) steps from
 v'_0 = Q(v + dt u):  v'_{m+1} = Q(v + dt u - dt Adv[v'_m]), m < PICARD;

@@ -43,14 +43,14 @@ __device__ inline void kkt_face(const Grid& g, int N, T dt, T kr, T cfl, T sgn, 
     const int c = cell_index(g, i, jj, k);
     const int cm = cell_index(g, i - (a == 0), jj - (a == 1), k - (a == 2));
     const T ih = (T)(1.0 / g.h);
-    if (D == 2 && vort) {
+    if (vort) {
         // F1_{j+1} = u_j/dt + G pbar + J_Adv(v_{j+1})^T u_j [+ (K/r)(v - w) - u_{j+1}/dt]
         T f1 = u[e] / dt + (pb[j * C + c] - pb[j * C + cm]) * ih;
-        f1 += rot_adv_T<T>(g, v + j * F, u + j * F, a, i, jj, ih);
+        f1 += rot_adv_T<T, D>(g, v + j * F, u + j * F, a, i, jj, k, ih);
         if (j < N - 1) f1 += kr * (v[e] - w[(j + 1) * F + f]) - u[e + F] / dt;
         // F3_j = (v_{j+1} - v_j)/dt + Adv[v_{j+1}] - u_j + G p_{j+1}
         const T vprev = j >= 1 ? v[e - F] : (T)0;
-        const T f3 = (v[e] - vprev) / dt + rot_adv<T>(g, v + j * F, a, i, jj, ih) - u[e] +
+        const T f3 = (v[e] - vprev) / dt + rot_adv<T, D>(g, v + j * F, a, i, jj, k, ih) - u[e] +
                      (p[j * C + c] - p[j * C + cm]) * ih;
         out1[e] = (res1 ? res1[e] : (T)0) + sgn * f1;
         out3[e] = (res3 ? res3[e] : (T)0) + sgn * f3;
@@ -116,7 +116,7 @@ struct KktSplit {
     int cnt[3];     // cells of the colour along each axis
     int nfc;        // faces of the colour's cells (per slice), with rows set
     void* gq;       // tiled transpose: where the quarters for the other axes go (k_quarter_gather adds them)
-    int vort;       // 1: face rows of the rotational operator (2D; no transpose part)
+    int vort;       // 1: face rows of the rotational operator (no transpose part)
 };
 
 // Face e (0 <= e < nfc) of the colour's cells: a-faces whose coordinates

@@ -1,6 +1,6 @@
-// The rotational velocity operator of Sec. 3.1 eq:NSA on the 2D MAC grid:
+// The rotational velocity operator of Sec. 3.1 eq:NSA on the MAC grid:
 // Adv[v] discretises (curl v) x v (the gradient part of (v . grad) v goes
-// into the kinetic pressure).
+// into the kinetic pressure).  In 2D:
 //
 //   node vorticity (cell corners, the circulation around the node's dual
 //   cell; zero on the walls):  w_n = (v_y right - v_y left - v_x above + v_x below)/h
@@ -14,7 +14,9 @@
 // (w(v), v); the transpose of its Jacobian, J_Adv(v)^T y, is the gradient in
 // v of <y, Adv[v]> = 1/4 sum_n w_n (Sx_n Yy_n - Sy_n Yx_n), again a stencil
 // of node quantities.  Everything is evaluated per face from its two end
-// nodes; wall faces carry nothing.
+// nodes; wall faces carry nothing.  In 3D the vorticity sits on the edges
+// (rot_adv, rot_adv_T below take either dimension); the node helpers serve
+// the 2D local block of the smoother.
 #pragma once
 #include "common.hpp"
 
@@ -54,56 +56,112 @@ __device__ inline T rot_vorticity(const Grid& g, const T* v, int I, int J, T ih)
     return (rot_vy(g, v, I, J) - rot_vy(g, v, I - 1, J) - rot_vx(g, v, I, J) + rot_vx(g, v, I, J - 1)) * ih;
 }
 
-// The two end nodes of interior face (a, i, j): x-face (i, j) ends at nodes
-// (i, j) and (i, j + 1); y-face (i, j) at nodes (i, j) and (i + 1, j).
-__device__ inline void rot_ends(int a, int i, int j, int (&n)[2][2]) {
-    n[0][0] = i;
-    n[0][1] = j;
-    n[1][0] = a == 0 ? i : i + 1;
-    n[1][1] = a == 0 ? j + 1 : j;
+// The same operator on the edges of a 2D or 3D grid.  For each cyclic triple
+// of axes (c, p, q) = (z, x, y), (x, y, z), (y, z, x) (2D: the first only, the
+// z-edges being the nodes) a c-edge sits at a p-node, a q-node and a c-cell
+// (lattice coordinates e[3]) and carries the circulation
+//   w_c = (D_p v_q - D_q v_p)/h (zero on walls) and the sums S_p, S_q of its
+// two incident p-faces and q-faces; each incident p-face gains -1/4 w_c S_q and
+// each incident q-face +1/4 w_c S_p: (curl v) x v, with every pair of faces
+// meeting at an edge entering both components with opposite signs (no work).
+// For (c, p, q) = (z, x, y) this is the node form above.
+template <int D>
+struct RotTriples;
+template <>
+struct RotTriples<2> {
+    static constexpr int n = 1;
+    static constexpr int t[1][3] = {{2, 0, 1}};
+};
+template <>
+struct RotTriples<3> {
+    static constexpr int n = 3;
+    static constexpr int t[3][3] = {{2, 0, 1}, {0, 1, 2}, {1, 2, 0}};
+};
+
+// Face value of axis a at lattice coordinates x; 0 outside the lattice (and,
+// masked, on wall faces).
+template <typename T>
+__device__ inline T rot_face(const Grid& g, const T* f, int a, const int (&x)[3], bool masked) {
+    if (x[0] < 0 || x[1] < 0 || x[2] < 0 || x[0] >= face_ext(g, a, 0) || x[1] >= face_ext(g, a, 1) ||
+        x[2] >= face_ext(g, a, 2))
+        return (T)0;
+    if (masked && !face_interior(g, a, x[0], x[1], x[2])) return (T)0;
+    return f[face_index(g, a, x[0], x[1], x[2])];
 }
 
-// Adv[v] at interior face (a, i, j) (a 2D face; wall faces are the caller's).
+// w (0 off the interior edges), S_p and S_q of face field f at the c-edge e of triple (c, p, q).
 template <typename T>
-__device__ inline T rot_adv(const Grid& g, const T* v, int a, int i, int j, T ih) {
-    int n[2][2];
-    rot_ends(a, i, j, n);
-    T acc[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        T sx, sy;
-        rot_sums(g, v, n[e][0], n[e][1], false, sx, sy);
-        acc[e] = rot_vorticity(g, v, n[e][0], n[e][1], ih) * (a == 0 ? sy : sx);
-    }
-    return a == 0 ? (T)-0.25 * (acc[0] + acc[1]) : (T)0.25 * (acc[0] + acc[1]);
+__device__ inline bool rot_edge(const Grid& g, const T* f, int p, int q, const int (&e)[3], T ih, bool masked, T& w,
+                                T& sp, T& sq) {
+    int m[3] = {e[0], e[1], e[2]};
+    const T vq1 = rot_face(g, f, q, m, masked), vp1 = rot_face(g, f, p, m, masked);
+    m[p] -= 1;
+    const T vq0 = rot_face(g, f, q, m, masked);
+    m[p] += 1;
+    m[q] -= 1;
+    const T vp0 = rot_face(g, f, p, m, masked);
+    sp = vp0 + vp1;
+    sq = vq0 + vq1;
+    const bool in = e[p] > 0 && e[p] < g.n[p] && e[q] > 0 && e[q] < g.n[q];
+    w = in ? ((vq1 - vq0) - (vp1 - vp0)) * ih : (T)0;
+    return in;
 }
 
-// J_Adv(v)^T y at interior face (a, i, j); y is read with its wall faces as 0.
-template <typename T>
-__device__ inline T rot_adv_T(const Grid& g, const T* v, const T* y, int a, int i, int j, T ih) {
-    int n[2][2];
-    rot_ends(a, i, j, n);
-    T P[2], wy[2];
+// Adv[v] at interior face (a, i, j, k) (wall faces are the caller's).
+template <typename T, int D>
+__device__ inline T rot_adv(const Grid& g, const T* v, int a, int i, int j, int k, T ih) {
+    const int fx[3] = {i, j, k};
+    T acc = 0;
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int I = n[e][0], J = n[e][1];
-        T sx, sy, yx, yy;
-        rot_sums(g, v, I, J, false, sx, sy);
-        rot_sums(g, y, I, J, true, yx, yy);
-        const bool interior = I > 0 && I < g.n[0] && J > 0 && J < g.n[1];
-        P[e] = interior ? (T)0.25 * (sx * yy - sy * yx) : (T)0;
-        wy[e] = rot_vorticity(g, v, I, J, ih) * (a == 0 ? yy : yx);
+    for (int t = 0; t < RotTriples<D>::n; ++t) {
+        const int p = RotTriples<D>::t[t][1], q = RotTriples<D>::t[t][2];
+        if (a != p && a != q) continue;
+#pragma unroll
+        for (int e2 = 0; e2 < 2; ++e2) {
+            int e[3] = {fx[0], fx[1], fx[2]};
+            e[a == p ? q : p] += e2;          // the two c-edges at the face's ends across the other axis
+            T w, sp, sq;
+            rot_edge(g, v, p, q, e, ih, false, w, sp, sq);
+            acc += a == p ? (T)-0.25 * w * sq : (T)0.25 * w * sp;
+        }
     }
-    // through the vorticity: an x-face enters w at its lower end node with -1/h and at its
-    // upper one with +1/h; a y-face at its left end node with +1/h and at its right one with -1/h
-    const T gw = a == 0 ? (P[1] - P[0]) * ih : (P[0] - P[1]) * ih;
-    return a == 0 ? gw + (T)0.25 * (wy[0] + wy[1]) : gw - (T)0.25 * (wy[0] + wy[1]);
+    return acc;
+}
+
+// J_Adv(v)^T y at interior face (a, i, j, k): the gradient in v of
+// <y, Adv[v]> = sum over interior edges of w_c (S_p Y_q - S_q Y_p)/4 (y read
+// with its wall faces as 0).  A p-face enters w_c at the edges of its q-ends
+// with -1/h (lower) and +1/h (upper) and S_p at both; a q-face enters w_c at
+// the edges of its p-ends with +1/h (lower) and -1/h (upper) and S_q at both.
+template <typename T, int D>
+__device__ inline T rot_adv_T(const Grid& g, const T* v, const T* y, int a, int i, int j, int k, T ih) {
+    const int fx[3] = {i, j, k};
+    T acc = 0;
+#pragma unroll
+    for (int t = 0; t < RotTriples<D>::n; ++t) {
+        const int p = RotTriples<D>::t[t][1], q = RotTriples<D>::t[t][2];
+        if (a != p && a != q) continue;
+        T P[2], ws[2];
+#pragma unroll
+        for (int e2 = 0; e2 < 2; ++e2) {
+            int e[3] = {fx[0], fx[1], fx[2]};
+            e[a == p ? q : p] += e2;
+            T w, sp, sq, wy, yp, yq;
+            const bool in = rot_edge(g, v, p, q, e, ih, false, w, sp, sq);
+            rot_edge(g, y, p, q, e, ih, true, wy, yp, yq);
+            P[e2] = in ? (T)0.25 * (sp * yq - sq * yp) : (T)0;
+            ws[e2] = a == p ? w * yq : w * yp;
+        }
+        acc += a == p ? (P[1] - P[0]) * ih + (T)0.25 * (ws[0] + ws[1])
+                      : (P[0] - P[1]) * ih - (T)0.25 * (ws[0] + ws[1]);
+    }
+    return acc;
 }
 
 // One fixed-point step of the implicit update (v' - v)/dt + Adv[v'] = u - G p'
 // before its projection: out = v + dt u - dt Adv[vk] on interior faces, 0 on
 // walls (vk = null: without the Adv term, the first iterate).
-template <typename T>
+template <typename T, int D>
 __global__ void k_rot_rhs(Grid g, T dt, const T* __restrict__ v, const T* __restrict__ u, const T* __restrict__ vk,
                           T* __restrict__ out) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
@@ -115,7 +173,7 @@ __global__ void k_rot_rhs(Grid g, T dt, const T* __restrict__ v, const T* __rest
         return;
     }
     T w = v[f] + dt * u[f];
-    if (vk) w -= dt * rot_adv<T>(g, vk, a, i, j, (T)(1.0 / g.h));
+    if (vk) w -= dt * rot_adv<T, D>(g, vk, a, i, j, k, (T)(1.0 / g.h));
     out[f] = w;
 }
 

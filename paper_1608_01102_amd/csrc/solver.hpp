@@ -52,7 +52,7 @@ struct Params {
     int dim, n[3], N;
     double dt, r, K, beta, eps_stfas, eps_admm, poisson_rtol, omega, al_tol, lm;
     int ao_iters, max_admm, max_vcycles, metric_levels, fixed_counts, precision, density;
-    int vort;   // 1: the rotational velocity operator (eq:NSA's Adv, 2D)
+    int vort;   // 1: the rotational velocity operator (eq:NSA's Adv)
     int rot_exact;   // levels (from the finest) whose smoother's local matrix holds the cell's block of dAdv/dv
 };
 
@@ -91,12 +91,13 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     o.poisson_rtol = p->poisson_rtol > 0 ? p->poisson_rtol : (o.precision == STFAS_FP64 ? 1e-13 : 1e-6);
     o.fixed_counts = p->fixed_counts ? 1 : 0;
     if (p->velocity_op != STFAS_VELOCITY_SL && p->velocity_op != STFAS_VELOCITY_ROTATIONAL) return false;
-    if (p->velocity_op == STFAS_VELOCITY_ROTATIONAL && o.dim != 2) return false;
     o.vort = p->velocity_op == STFAS_VELOCITY_ROTATIONAL ? 1 : 0;
-    if (p->scgs_local != 0 && !(o.vort && (p->scgs_local == 1 || p->scgs_local == 2))) return false;
-    o.rot_exact = !o.vort ? 0 : (p->scgs_local == 0 ? 1 : (p->scgs_local == 2 ? 1 << 20 : 0));
-    // the rotational operator's smoother solves eq:HESS with its exact local
-    // block: no relaxation and no perturbation unless asked for
+    // the local block of dAdv/dv is built for 2D; a 3D rotational smoother leaves it out
+    if (p->scgs_local != 0 && !(o.vort && (p->scgs_local == 1 || (p->scgs_local == 2 && o.dim == 2))))
+        return false;
+    o.rot_exact = !o.vort || o.dim == 3 ? 0 : (p->scgs_local == 0 ? 1 : (p->scgs_local == 2 ? 1 << 20 : 0));
+    // the rotational operator's smoother solves eq:HESS with its local block
+    // (2D): no relaxation and, in 2D, no perturbation unless asked for
     o.omega = p->scgs_omega > 0 ? p->scgs_omega : (o.vort ? 1.0 : 0.7);
     if (!(o.omega <= 2.0)) return false;
     if (p->density_op != STFAS_DENSITY_SL && p->density_op != STFAS_DENSITY_UPWIND) return false;
@@ -104,7 +105,7 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     if (!(p->al_tol >= 0) || !std::isfinite(p->al_tol)) return false;
     o.al_tol = p->al_tol;
     if (std::isnan(p->scgs_lm) || std::isinf(p->scgs_lm)) return false;
-    o.lm = (p->scgs_lm < 0 ? 0.0 : (p->scgs_lm > 0 ? p->scgs_lm : (o.vort ? 0.0 : 1.0))) / (o.dt * o.dt);
+    o.lm = (p->scgs_lm < 0 ? 0.0 : (p->scgs_lm > 0 ? p->scgs_lm : (o.vort && o.dim == 2 ? 0.0 : 1.0))) / (o.dt * o.dt);
     const double total = (double)o.n[0] * o.n[1] * o.n[2];
     if (total > 2.0e9 / (o.dim + 1)) return false;
     return true;
@@ -1061,8 +1062,10 @@ public:
         T* t1 = nullptr;
         if (D == 3) {
             t1 = t1_zero;
-            kkt_transpose(l, t1, t1_used);          // t1_used is cleared for the next sweep
-            std::swap(t1_zero, t1_used);
+            if (!P.vort) {                          // the rotational rows have no transpose part
+                kkt_transpose(l, t1, t1_used);      // t1_used is cleared for the next sweep
+                std::swap(t1_zero, t1_used);
+            }
         }
         for (int colour = 0; colour < (1 << D); ++colour) {
             const ColourSet cs = colour_set(g, colour);
@@ -1586,10 +1589,10 @@ public:
             if (P.vort) {
                 // the implicit update by ROT_PICARD fixed-point steps from Q(v + dt u)
                 const Grid& g = L[0];
-                k_rot_rhs<T><<<blocks_for(F, BS), BS, 0, st>>>(g, (T)P.dt, rs_v[cur], q.u + i * F, nullptr, rs_w);
+                k_rot_rhs<T, D><<<blocks_for(F, BS), BS, 0, st>>>(g, (T)P.dt, rs_v[cur], q.u + i * F, nullptr, rs_w);
                 project(rs_w, rs_v[cur ^ 1], nullptr, 1);
                 for (int m = 0; m < ROT_PICARD; ++m) {
-                    k_rot_rhs<T><<<blocks_for(F, BS), BS, 0, st>>>(g, (T)P.dt, rs_v[cur], q.u + i * F,
+                    k_rot_rhs<T, D><<<blocks_for(F, BS), BS, 0, st>>>(g, (T)P.dt, rs_v[cur], q.u + i * F,
                                                                     rs_v[cur ^ 1], rs_w);
                     project(rs_w, rs_v[cur ^ 1], nullptr, 1);
                 }

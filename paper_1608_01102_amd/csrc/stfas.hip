@@ -93,10 +93,10 @@ struct Step {
             k_advect<T, D><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g, cfl, rho, v, rho_o, g.ncell, g.nface);
         if (p.vort) {
             // the implicit rotational update: ROT_PICARD fixed-point steps from Q(v + dt u)
-            k_rot_rhs<T><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, (T)p.dt, v, u, nullptr, w);
+            k_rot_rhs<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, (T)p.dt, v, u, nullptr, w);
             pois.project(w, v_o, p_o, 1, p.poisson_rtol, step_cycles(p), nullptr);
             for (int m = 0; m < ROT_PICARD; ++m) {
-                k_rot_rhs<T><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, (T)p.dt, v, u, v_o, w);
+                k_rot_rhs<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, (T)p.dt, v, u, v_o, w);
                 pois.project(w, v_o, p_o, 1, p.poisson_rtol, step_cycles(p), nullptr);
             }
         } else {

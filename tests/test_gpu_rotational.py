@@ -226,3 +226,80 @@ def test_rotational_rejected_where_not_built():
         S.stfas_lbfgs(ctx, rho0, [4], keys, u, 2)
     assert e.value.status == STFAS_E_INVALID
     ctx.destroy()
+
+
+# ---------------------------------------------------------------- 3D (vorticity on edges)
+CASES_3D = [((8, 8, 8), 3), ((12, 8, 8), 2)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", CASES_3D)
+def test_rotational_3d_kkt_residual_all_levels(n, N, prec):
+    S, ctx, g, dt, K = _ctx(n, N, prec)
+    rng = np.random.default_rng(81)
+    for level in range(ctx.num_levels()):
+        gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
+        L = kkt.Level(gl, N, dt, K / 1e-2, velocity="vorticity")
+        x = _state(gl, N, rng, 0.5, prec)
+        w = _q(_faces(gl, rng, N), prec)
+        res = _state(gl, N, rng, 1.0, prec)
+        out = tuple(empty(a.size, prec) for a in res)
+        flag(f"rotational 3d kkt n={n} level={level} {prec}")
+        S.stfas_op_kkt_residual(ctx, level, _dev(x, prec), to_dev(w, prec), _dev(res, prec), out)
+        ref = kkt.residual(L, x, w, res)
+        for k in range(4):
+            assert rel(to_np(out[k]), ref[k]) <= TOL[prec], (level, k)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("omega,lm", [(0.0, 0.0), (0.7, 2.0)])
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,N", CASES_3D)
+def test_rotational_3d_scgs_sweep(n, N, prec, omega, lm):
+    """3D takes the smoother without the local block; (0, 0) are the defaults
+    there (omega 1, the perturbation mu dt^2 = 1)."""
+    S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=omega, scgs_lm=lm)
+    rng = np.random.default_rng(82)
+    for level in (0, ctx.num_levels() - 1):
+        gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
+        L = kkt.Level(gl, N, dt, K / 1e-2, omega=omega or 1.0, lm=lm or 1.0, velocity="vorticity")
+        x = _state(gl, N, rng, 0.3, prec)
+        w = _q(_faces(gl, rng, N), prec)
+        res = _state(gl, N, rng, 1.0, prec) if level > 0 else None
+        xd = _dev(x, prec)
+        flag(f"rotational 3d scgs n={n} level={level} {prec}")
+        S.stfas_op_scgs_sweep(ctx, level, xd, to_dev(w, prec), _dev(res, prec) if res else None)
+        ref = [a.copy() for a in x]
+        scgs.sweep(L, ref, w, res if res else [np.zeros_like(a) for a in x])
+        for k in range(4):
+            assert rel(to_np(xd[k]), ref[k]) <= TOL[prec], (level, k)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_rotational_3d_solve_fixed_counts(prec):
+    w = synthetic.small_problem((8, 8, 8), 3, seed=3, r=1e-2)
+    u, st, ref = _solve_pair(w, prec, max_admm=2, max_vcycles=2, fixed_counts=True)
+    assert rel(u, ref.u) <= TOL[prec]
+    assert abs(st["objective"] - ref.objective) <= TOL[prec] * ref.objective
+    assert st["admm_iters"] == ref.admm_iters == 2 and st["vcycles"] == ref.vcycles
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_rotational_3d_step_forward(prec):
+    from paper_1608_01102_amd import stfas as S
+    from oracle import step
+    n = (12, 10, 8)
+    g = Grid(n)
+    dt = 0.9 * g.h
+    prob = S.make_problem(n, 1, 1.0, dt=dt, precision=prec, velocity="rotational")
+    rng = np.random.default_rng(84)
+    rho = _q(synthetic.smooth_noise_density(n, rng, 1.0), prec)
+    v = _q(synthetic.curl_noise_velocity(n, rng, 1.0, 1.0, dt / g.h), prec)
+    u = _q(synthetic.random_faces(n, rng, 2.0), prec)
+    ro, vo, po = empty(g.ncell, prec), empty(g.nface, prec), empty(g.ncell, prec)
+    flag(f"rotational 3d step n={n} {prec}")
+    S.stfas_step_forward(prob, to_dev(rho, prec), to_dev(v, prec), to_dev(u, prec), ro, vo, po)
+    rr, vr, pr = step.step_forward(g, rho, v, u, dt, velocity="vorticity")
+    tol = TOL[prec] if prec == "fp64" else 2e-5
+    assert rel(to_np(ro), rr) <= tol and rel(to_np(vo), vr) <= tol and rel(to_np(po), pr) <= 10 * tol

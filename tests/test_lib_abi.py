@@ -74,9 +74,9 @@ def test_density_operator_selection():
 
 
 def test_velocity_operator_selection():
-    """The rotational velocity operator is 2D only; an unknown value, or the
-    operator on a 3D grid, is rejected before any allocation; the forward
-    step takes it with the same scratch as the semi-Lagrangian one."""
+    """The rotational velocity operator: an unknown value is rejected before
+    any allocation; the forward step takes it with the same scratch as the
+    semi-Lagrangian one."""
     from paper_1608_01102_amd import stfas as S
     ok = S.make_problem((32, 32), 10, 1e-3, velocity="rotational")
     assert S.stfas_workspace_bytes(ok) > 0
@@ -89,8 +89,14 @@ def test_velocity_operator_selection():
                      S.stfas_workspace_bytes(S.make_problem((32, 32), N, 1e-3, precision=prec)))
             assert extra == (0 if N == 10 else (16 * 16 * N * 24 * word + 255) // 256 * 256), (prec, N)
     assert S.stfas_step_work_bytes(ok) == S.stfas_step_work_bytes(S.make_problem((32, 32), 10, 1e-3))
-    bad3d = S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational")
-    assert S.stfas_workspace_bytes(bad3d) == 0
+    # 3D: the operator is taken without the smoother's local block (no block scratch); asking for the
+    # block on every level is invalid there
+    ok3d = S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational")
+    assert S.stfas_workspace_bytes(ok3d) == S.stfas_workspace_bytes(S.make_problem((16, 16, 16), 10, 1e-3))
+    assert S.stfas_workspace_bytes(S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational",
+                                                  scgs_local="collapsed")) > 0
+    assert S.stfas_workspace_bytes(S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational",
+                                                  scgs_local="exact")) == 0
     bad = S.make_problem((32, 32), 10, 1e-3)
     bad.velocity_op = 2
     assert S.stfas_workspace_bytes(bad) == 0

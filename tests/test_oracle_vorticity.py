@@ -178,3 +178,70 @@ def test_local_block_is_the_exact_jacobian_at_zero_u(n, rng):
                 left.append(max(np.max(np.abs(r[0][:, fr])), np.max(np.abs(r[2][:, fr])),
                                 np.max(np.abs(r[1][:, cr])), np.max(np.abs(r[3][:, cr]))))
             assert 10 ** (order - 0.15) <= left[0] / left[1] <= 10 ** (order + 0.15), (colour, local_adv, left)
+
+
+# ---------------------------------------------------------------- 3D (vorticity on edges)
+def test_edge_form_equals_node_form_in_2d(rng):
+    """The any-dimension form (edges) and the 2D form (nodes) are two
+    separate codes for the same 2D operator."""
+    for n in ((9, 7), (8, 8)):
+        g = Grid(n)
+        v, y = _faces(g, rng), rng.standard_normal(g.nface)
+        assert np.max(np.abs(vorticity.adv_nd(g, v) - vorticity._adv_2d(g, v))) <= 1e-13 * np.max(np.abs(v)) ** 2 / g.h
+        assert np.max(np.abs(vorticity.adv_nd_T(g, v, y) - vorticity._adv_T_2d(g, v, y))) <= 1e-12 / g.h
+
+
+@pytest.mark.parametrize("n", [(6, 5, 4), (8, 8, 8)])
+def test_3d_operator_does_no_work_and_its_transpose_is_exact(n, rng):
+    g = Grid(n)
+    for _ in range(2):
+        v, y, d = _faces(g, rng), _faces(g, rng), _faces(g, rng)
+        a = vorticity.adv(g, v)
+        assert abs(v @ a) <= 1e-13 * np.linalg.norm(v) * np.linalg.norm(a)
+        assert np.all(a[g.interior_mask() == 0] == 0)
+        assert np.allclose(vorticity.adv(g, -1.5 * v), 2.25 * a, rtol=1e-13, atol=1e-13 * np.max(np.abs(a)))
+        e = 1e-3
+        jd = (vorticity.adv(g, v + e * d) - vorticity.adv(g, v - e * d)) / (2 * e)
+        assert abs(y @ jd - vorticity.adv_T(g, v, y) @ d) <= 1e-11 * abs(y @ jd)
+
+
+def _embed(g3, c, v2x, v2y):
+    """A 3D face field invariant along axis c whose components in the plane
+    (p, q) of the triple (c, p, q) are the 2D field (x-role p, y-role q); the
+    c component is zero."""
+    n0, n1, n2 = g3.n
+    parts = [np.zeros(s) for s in g3.face_shapes]
+    if c == 2:                                   # p = x, q = y
+        parts[0][:] = v2x[None, :, :]
+        parts[1][:] = v2y[None, :, :]
+    elif c == 0:                                 # p = y, q = z
+        parts[1][:] = v2x[:, :, None]
+        parts[2][:] = v2y[:, :, None]
+    else:                                        # c = y: p = z, q = x
+        parts[2][:] = v2x.T[:, None, :]
+        parts[0][:] = v2y.T[:, None, :]
+    return g3.join(parts)
+
+
+@pytest.mark.parametrize("c", [2, 0, 1])
+def test_3d_operator_on_planar_fields_is_the_2d_operator(c, rng):
+    """A field that does not vary along axis c and has no c component is a 2D
+    flow in every layer: the 3D operator (vorticity on edges, all three
+    pairings) returns the 2D operator of each layer and nothing along c.
+    Run for the three axes, this fixes the sign and orientation of every
+    pairing against the 2D form and its closed forms."""
+    n = (6, 5, 7)
+    g3 = Grid(n)
+    p, q = {2: (0, 1), 0: (1, 2), 1: (2, 0)}[c]
+    g2 = Grid((n[p], n[q]), g3.h)
+    v2 = _faces(g2, rng)
+    v2x, v2y = g2.split(v2)
+    v3 = _embed(g3, c, v2x, v2y)
+    a2x, a2y = g2.split(vorticity._adv_2d(g2, v2))
+    assert np.max(np.abs(vorticity.adv(g3, v3) - _embed(g3, c, a2x, a2y))) <= 1e-12 * np.max(np.abs(a2x))
+    y2 = rng.standard_normal(g2.nface) * g2.interior_mask()
+    y3 = _embed(g3, c, *g2.split(y2))
+    t2x, t2y = g2.split(vorticity._adv_T_2d(g2, v2, y2))
+    got = vorticity.adv_T(g3, v3, y3)
+    # the transpose also has no c part: the c faces enter no pairing with a nonzero partner here
+    assert np.max(np.abs(got - _embed(g3, c, t2x, t2y))) <= 1e-12 * np.max(np.abs(t2x))
