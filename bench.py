@@ -173,6 +173,9 @@ def main():
     if not args.no_3d:
         out["precision_3d"] = precision_3d_run(S)
         progress("3D solves done")
+        if not args.no_rotational:
+            out["rotational_velocity_3d"] = precision_3d_run(S, velocity="rotational")
+            progress("3D rotational-operator solves done")
     if args.serve_requests > 0:
         out["serving"] = serving_run(args)
         progress("serving done")
@@ -321,7 +324,7 @@ def rotational_run(S, w, density, kw):
     return res
 
 
-def precision_3d_run(S):
+def precision_3d_run(S, velocity="sl"):
     """The 3D precision form (outside the step clock): the 64^3, 60-step
     workload (sphere to ellipsoid unions at t = 30 and 60, SL density) solved
     to the ADMM stop in the mixed form and in FP64 on the GPU, with
@@ -331,25 +334,28 @@ def precision_3d_run(S):
     100 iterations from run to run), cap 150; iterations, seconds, seconds
     per V-cycle, final visual difference, and the mixed
     form's keyframe error against the FP64 run after re-simulating both
-    controls with the FP64 step."""
+    controls with the FP64 step.  velocity="rotational" runs the same with
+    the paper's rotational operator (vorticity on edges; its smoother without
+    the local block in 3D)."""
     import torch
     import synthetic
     w = synthetic.c3_precision_3d(0)
     opts = dict(K=4.0 * w["r"] / w["dt"] ** 2, ao_iters=4, max_admm=150)
     res, us, conv = {}, {}, []
     for prec in ("mixed", "fp64"):
-        st, us[prec] = solve_once(S, w, prec, "sl", **opts)
+        st, us[prec] = solve_once(S, w, prec, "sl", velocity=velocity, **opts)
         res[prec] = {"seconds": st["seconds"], "admm_iters": st["admm_iters"], "vcycles": st["vcycles"],
                      "converged": bool(st["converged"]),
                      "ms_per_vcycle_incl_ao": st["seconds"] * 1e3 / max(st["vcycles"], 1),
                      "objective": st["objective"], "visual_diff": st["visual_diff"]}
         conv.append(bool(st["converged"]))
         torch.cuda.empty_cache()
-    kf = keyframe_error(S, w, "sl", us["mixed"], us["fp64"])
+    kf = keyframe_error(S, w, "sl", us["mixed"], us["fp64"], velocity=velocity)
     res["kf_err_mixed_vs_fp64"] = kf
     res["meets_1e-4_kf_err"] = bool(kf <= 1e-4 and all(conv))
     res["workload"] = ("3D 64^3 MAC grid, 60 steps, r=1e-3, SL density, K dt^2/r = 4, 4 density-subproblem "
-                       "iterations, ADMM to the visual-difference stop max(rho0)/100")
+                       "iterations, ADMM to the visual-difference stop max(rho0)/100"
+                       + (", rotational velocity operator" if velocity != "sl" else ""))
     return res
 
 
