@@ -74,9 +74,9 @@ typedef enum { STFAS_DENSITY_SL = 0, STFAS_DENSITY_UPWIND = 1 } stfas_density;
  * with Adv the vorticity form (curl v) x v, discretised with the vorticity
  * on the grid's edges (the nodes in 2D) and edge-paired face products so
  * that it does no work; the KKT residual is eq:KKTAO as printed
- * (du_{i-1}/dv_i = I/dt + dAdv/dv_i); in 2D the smoother's local matrix is
+ * (du_{i-1}/dv_i = I/dt + dAdv/dv_i); the smoother's local matrix is
  * eq:HESS with the cell's block of dAdv/dv (Sec. 4.3, solved by block
- * elimination in time; scgs_local), in 3D it leaves the block out; the
+ * elimination in time), by default on the finest level in 2D (scgs_local); the
  * re-simulation of the outputs (and stfas_step_forward) takes 4 fixed-point
  * steps per time step.  stfas_lbfgs and stfas_step_backward accept only the
  * semi-Lagrangian operator (STFAS_E_INVALID otherwise). */
@@ -111,16 +111,15 @@ typedef struct {
     double scgs_lm;         /* Levenberg-Marquardt perturbation of K in the smoother's local matrix
                              * (Sec. 5, convergence analysis; eq:HESS): K/r on every v block becomes
                              * K/r + scgs_lm / dt^2 (the residual is unchanged, so is the solution);
-                             * 0 selects 1 (off with the rotational velocity operator in 2D); < 0
-                             * turns it off */
+                             * 0 selects 1 (off where the rotational operator's smoother holds the
+                             * local block, see scgs_local); < 0 turns it off */
     int32_t velocity_op;    /* stfas_velocity; 0 = semi-Lagrangian, 1 = rotational */
     int32_t scgs_local;     /* local matrix of the SCGS smoother with the rotational operator (Sec. 4.3
-                             * eq:HESS): 0 = with the cell's block of dAdv/dv (block elimination in
-                             * time) on the finest level and without it below (default); 1 = without
-                             * it on every level (du_{i-1}/dv_i = I/dt, the scalar temporal solve of
-                             * the semi-Lagrangian operator); 2 = with it on every level; other
-                             * values invalid; must be 0 with the semi-Lagrangian operator.  The
-                             * block is built for 2D: in 3D 0 and 1 both leave it out, 2 is invalid */
+                             * eq:HESS): 1 = without the cell's block of dAdv/dv on every level
+                             * (du_{i-1}/dv_i = I/dt, the scalar temporal solve of the semi-Lagrangian
+                             * operator); 2 = with it on every level (block elimination in time);
+                             * 3 = with it on the finest level only; 0 = 3 in 2D, 1 in 3D; other
+                             * values invalid; must be 0 with the semi-Lagrangian operator */
 } stfas_problem;
 
 typedef struct {

@@ -62,8 +62,9 @@ class Problem:
     scgs_lm: float = 0.0              # smoother's Levenberg-Marquardt perturbation times dt^2
                                       # (< 0: off; 0: 1, off with "vorticity")
     velocity: str = "sl"              # velocity operator: "sl" or "vorticity" (eq:NSA's Adv)
-    local_adv: object = "finest"      # vorticity: dAdv/dv in the smoother's local matrix (eq:HESS):
-                                      # "finest" (level 0 only), True (every level), False (none)
+    local_adv: object = "default"     # vorticity: dAdv/dv in the smoother's local matrix (eq:HESS):
+                                      # "finest" (level 0 only), True (every level), False (none);
+                                      # "default": "finest" in 2D, False in 3D
 
     def resolved(self, rho0):
         p = Problem(**self.__dict__)
@@ -73,14 +74,16 @@ class Problem:
             p.K = p.r / (p.dt * p.dt)
         if p.metric_levels < 0:
             p.metric_levels = metric.default_levels(p.n)
-        # with the rotational operator the smoother solves eq:HESS with its exact
-        # local block (2D): no relaxation and no perturbation unless asked for;
-        # in 3D (no block) the perturbation stays
+        # with the rotational operator the smoother solves eq:HESS with its local
+        # block: no relaxation and no perturbation unless asked for (without
+        # the block the perturbation stays)
         rot = p.velocity == "vorticity"
+        if p.local_adv == "default":
+            p.local_adv = "finest" if len(p.n) == 2 else False
         if p.scgs_omega <= 0:
             p.scgs_omega = 1.0 if rot else 0.7
         if p.scgs_lm == 0:
-            p.scgs_lm = -1.0 if rot and len(p.n) == 2 else 1.0
+            p.scgs_lm = -1.0 if rot and p.local_adv is not False else 1.0
         if p.eps_admm <= 0:
             p.eps_admm = float(np.max(rho0)) / 100.0
         return p

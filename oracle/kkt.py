@@ -50,8 +50,8 @@ class Level:
         self.omega = omega          # relaxation weight of the smoother
         self.lm = lm                # Levenberg-Marquardt perturbation of the smoother's K/r, times dt^2
         # rotational operator: the smoother's local matrix holds the cell's block of dAdv/dv (eq:HESS);
-        # False leaves it out (du_{i-1}/dv_i = I/dt, the collapsed form of the SL operator), as 3D does
-        self.local_adv = bool(local_adv) and velocity == "vorticity" and g.dim == 2
+        # False leaves it out (du_{i-1}/dv_i = I/dt, the collapsed form of the SL operator)
+        self.local_adv = bool(local_adv) and velocity == "vorticity"
 
     def S(self, v):
         return advect.self_advect(self.g, v, self.dt, self.g.h) if self.advect else v * self.mask

@@ -92,12 +92,15 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     o.fixed_counts = p->fixed_counts ? 1 : 0;
     if (p->velocity_op != STFAS_VELOCITY_SL && p->velocity_op != STFAS_VELOCITY_ROTATIONAL) return false;
     o.vort = p->velocity_op == STFAS_VELOCITY_ROTATIONAL ? 1 : 0;
-    // the local block of dAdv/dv is built for 2D; a 3D rotational smoother leaves it out
-    if (p->scgs_local != 0 && !(o.vort && (p->scgs_local == 1 || (p->scgs_local == 2 && o.dim == 2))))
-        return false;
-    o.rot_exact = !o.vort || o.dim == 3 ? 0 : (p->scgs_local == 0 ? 1 : (p->scgs_local == 2 ? 1 << 20 : 0));
-    // the rotational operator's smoother solves eq:HESS with its local block
-    // (2D): no relaxation and, in 2D, no perturbation unless asked for
+    // the local block of dAdv/dv: by default on the finest level in 2D and on
+    // none in 3D (where it saves no V-cycles and costs a serial elimination)
+    if (p->scgs_local != 0 && !(o.vort && p->scgs_local >= 1 && p->scgs_local <= 3)) return false;
+    o.rot_exact = !o.vort ? 0
+                          : p->scgs_local == 0 ? (o.dim == 2 ? 1 : 0)
+                                               : p->scgs_local == 1 ? 0 : (p->scgs_local == 2 ? 1 << 20 : 1);
+    // the rotational operator's smoother: no relaxation, and no perturbation
+    // where its finest level holds the local block (without it the
+    // perturbation stays)
     o.omega = p->scgs_omega > 0 ? p->scgs_omega : (o.vort ? 1.0 : 0.7);
     if (!(o.omega <= 2.0)) return false;
     if (p->density_op != STFAS_DENSITY_SL && p->density_op != STFAS_DENSITY_UPWIND) return false;
@@ -105,7 +108,7 @@ inline bool resolve(const stfas_problem* p, Params& o) {
     if (!(p->al_tol >= 0) || !std::isfinite(p->al_tol)) return false;
     o.al_tol = p->al_tol;
     if (std::isnan(p->scgs_lm) || std::isinf(p->scgs_lm)) return false;
-    o.lm = (p->scgs_lm < 0 ? 0.0 : (p->scgs_lm > 0 ? p->scgs_lm : (o.vort && o.dim == 2 ? 0.0 : 1.0))) / (o.dt * o.dt);
+    o.lm = (p->scgs_lm < 0 ? 0.0 : (p->scgs_lm > 0 ? p->scgs_lm : (o.rot_exact > 0 ? 0.0 : 1.0))) / (o.dt * o.dt);
     const double total = (double)o.n[0] * o.n[1] * o.n[2];
     if (total > 2.0e9 / (o.dim + 1)) return false;
     return true;
@@ -597,7 +600,7 @@ public:
     };
     std::vector<Lev> lev;
     T* scgs_scratch = nullptr;   // two-kernel SCGS path only (horizons too long for the fused kernel)
-    T* rot_scratch = nullptr;    // rotational operator, long horizons: the local blocks of one colour (ROT_BLK_WORDS per cell-slot)
+    T* rot_scratch = nullptr;    // rotational operator: the local records of one colour (three-launch form)
     T *t1a = nullptr, *t1b = nullptr;   // J_S^T part of F1 for the SCGS colour passes (any level)
     T *t1_zero = nullptr, *t1_used = nullptr;   // t1a / t1b: the one that is all zero, the other
     T* tq = nullptr;                            // quarters of the 3D sweep transpose (k_quarter_gather)
@@ -678,10 +681,10 @@ public:
             for (int c = 0; c < (1 << D); ++c) maxcol = std::max<long>(maxcol, colour_set(L[0], c).total);
             scgs_scratch = A.take<T>((size_t)maxcol * 2 * D * 2 * N);
         }
-        if (P.rot_exact && rot_fused_cells<T>(N) < 1) {
+        if (P.rot_exact && !rot_use_fused(colour_set(L[0], 0).total)) {
             long maxcol = 0;
             for (int c = 0; c < (1 << D); ++c) maxcol = std::max<long>(maxcol, colour_set(L[0], c).total);
-            rot_scratch = A.take<T>((size_t)maxcol * N * ROT_BLK_WORDS);
+            rot_scratch = A.take<T>((size_t)maxcol * N * RotDims<D>::REC);
         }
         t_diag = A.take<T>(2 * N);
         t_sub = A.take<T>(2 * N);
@@ -1036,20 +1039,27 @@ public:
         const ColourSet cs = colour_set(g, colour);
         const long n = (long)cs.total * N;
         const T dt = (T)P.dt, kr = (T)(P.K / P.r), lm = (T)P.lm;
-        const int tbc = rot_fused_cells<T>(N);
-        if (tbc >= 1) {
-            const size_t lds = (size_t)tbc * ((size_t)N * ROT_BLK_WORDS + 16 / sizeof(T)) * sizeof(T);
-            k_rot_blk_fused<T><<<blocks_for(cs.total, tbc), 512, lds, st>>>(g, N, cs, tbc, dt, kr, lm, (T)P.omega, q.v,
-                                                                          q.pb, q.u, q.p, q.r1, q.r2, q.r3, q.r4);
+        if (rot_use_fused(cs.total)) {
+            const int tbc = rot_fused_cells<T, D>(N);
+            const size_t lds = (size_t)tbc * ((size_t)N * RotDims<D>::REC + 16 / sizeof(T)) * sizeof(T);
+            k_rot_blk_fused<T, D><<<blocks_for(cs.total, tbc), 512, lds, st>>>(
+                g, N, cs, tbc, dt, kr, lm, (T)P.omega, q.v, q.pb, q.u, q.p, q.r1, q.r2, q.r3, q.r4);
             return;
         }
-        k_rot_blk_setup<T><<<blocks_for(n, 256), 256, 0, st>>>(g, N, cs, dt, kr, lm, q.v, q.r1, q.r2, q.r3, q.r4,
-                                                              rot_scratch);
-        const int tb = rot_blk_threads<T>(N);
-        k_rot_blk_thomas<T><<<blocks_for(cs.total, tb), tb, (size_t)tb * N * ROT_BLK_LDS * sizeof(T), st>>>(
-            N, cs.total, rot_scratch);
-        k_rot_blk_apply<T><<<blocks_for(n, 256), 256, 0, st>>>(g, N, cs, dt, kr, lm, (T)P.omega, q.v, q.pb, q.u,
-                                                              q.p, q.r1, q.r2, q.r3, q.r4, rot_scratch);
+        k_rot_blk_setup<T, D><<<blocks_for(n, 256), 256, 0, st>>>(g, N, cs, dt, kr, lm, q.v, q.r1, q.r2, q.r3,
+                                                                 q.r4, rot_scratch);
+        const int tb = rot_blk_threads<T, D>(N);
+        k_rot_blk_thomas<T, D><<<blocks_for(cs.total, tb), tb, (size_t)tb * N * rot_blk_lds_words<D>() * sizeof(T),
+                                 st>>>(N, cs.total, rot_scratch);
+        k_rot_blk_apply<T, D><<<blocks_for(n, 256), 256, 0, st>>>(g, N, cs, dt, kr, lm, (T)P.omega, q.v, q.pb,
+                                                                 q.u, q.p, q.r1, q.r2, q.r3, q.r4, rot_scratch);
+    }
+    // The fused launch while a cell's records fit in LDS and its blocks (a few
+    // cells each, one eliminating thread per cell) fill the chip about twice;
+    // beyond, the three launches, whose elimination runs 64 cells per wave.
+    bool rot_use_fused(long cells) const {
+        const int tbc = rot_fused_cells<T, D>(N);
+        return tbc >= 1 && blocks_for(cells, tbc) <= 512;
     }
 
     // One SCGS sweep on level l.  3D: the J_S^T part of F1 once from the state
@@ -1073,12 +1083,12 @@ public:
             const double inner = (double)colour_inner_faces(g, colour);
             const double sz = sizeof(T), M2 = 2.0 * N;
             int G = 1, Lc = 0, CH = 0;
-            if (D == 3) {
-                kkt_rows(l, colour);
-            } else if (l < P.rot_exact) {
+            if (l < P.rot_exact) {
                 kkt_rows(l, colour);                // the rows carry every term of F1
                 rot_local_solve(l, colour);
                 continue;
+            } else if (D == 3) {
+                kkt_rows(l, colour);
             } else if (P.vort) {
                 t1 = t1_zero;                       // stays zero: the rows carry every term of F1
                 kkt_rows(l, colour);

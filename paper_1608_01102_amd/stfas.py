@@ -15,12 +15,12 @@ from ._lib import StfasProblem, StfasState, StfasStats, check
 PRECISIONS = {"fp64": _lib.STFAS_FP64, "mixed": _lib.STFAS_MIXED}
 DENSITY_OPS = {"sl": 0, "upwind": 1}
 VELOCITY_OPS = {"sl": 0, "rotational": 1, "vorticity": 1}
-SCGS_LOCAL = {"finest": 0, "collapsed": 1, "exact": 2}
+SCGS_LOCAL = {"default": 0, "collapsed": 1, "exact": 2, "finest": 3}
 
 
 def make_problem(n, num_steps, r, dt=0.0, K=0.0, beta=0.0, ao_iters=0, eps_stfas=0.0, eps_admm=0.0, max_admm=0,
                  max_vcycles=0, metric_levels=-1, poisson_rtol=0.0, fixed_counts=False, precision="fp64",
-                 scgs_omega=0.0, density="sl", al_tol=0.0, scgs_lm=0.0, velocity="sl", scgs_local="finest"):
+                 scgs_omega=0.0, density="sl", al_tol=0.0, scgs_lm=0.0, velocity="sl", scgs_local="default"):
     """stfas_problem with the C defaults for every field left at 0 (-1 for metric_levels)."""
     p = StfasProblem()
     n = tuple(int(x) for x in n)

@@ -14,10 +14,17 @@ from oracle.grid import Grid
 pytestmark = pytest.mark.gpu
 
 # the smoother's local matrix: eq:HESS with the cell's block of dAdv/dv on the
-# finest level only ("finest", the default), on every level ("exact"), or on
-# none ("collapsed")
-LOCALS = ["finest", "exact", "collapsed"]
-ORACLE_LOCAL = {"exact": True, "collapsed": False, "finest": "finest"}
+# finest level only ("finest"; the 2D default), on every level ("exact"), or
+# on none ("collapsed"; the 3D default)
+LOCALS = ["default", "exact", "collapsed"]
+ORACLE_LOCAL = {"default": "default", "exact": True, "collapsed": False, "finest": "finest"}
+
+
+def _block_on(local, level, dim=2):
+    """Whether the smoother of this level holds the local block."""
+    if local == "default":
+        local = "finest" if dim == 2 else "collapsed"
+    return local == "exact" or (local == "finest" and level == 0)
 CASES = [((16, 12), 4), ((20, 12), 5), ((16, 16), 3), ((9, 7), 2)]
 PRECS = ["fp64", "mixed"]
 
@@ -39,7 +46,7 @@ def _dev(x, prec):
     return tuple(to_dev(a, prec) for a in x)
 
 
-def _ctx(n, N, prec, r=1e-2, local="finest", **kw):
+def _ctx(n, N, prec, r=1e-2, local="default", **kw):
     from paper_1608_01102_amd import stfas as S
     g = Grid(n)
     dt = 0.7 * g.h
@@ -80,7 +87,7 @@ def test_rotational_scgs_sweep(n, N, prec, omega, lm, local):
     for level in (0, ctx.num_levels() - 1):
         gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
         L = kkt.Level(gl, N, dt, K / 1e-2, omega=omega, lm=max(lm, 0.0), velocity="vorticity",
-                      local_adv=local == "exact" or (local == "finest" and level == 0))
+                      local_adv=_block_on(local, level))
         x = _state(gl, N, rng, 0.3, prec)
         w = _q(_faces(gl, rng, N), prec)
         res = _state(gl, N, rng, 1.0, prec) if level > 0 else None
@@ -133,7 +140,10 @@ def test_rotational_vcycles(n, N, prec, omega, lm, local):
     xd = _dev(x, prec)
     flag(f"rotational nso n={n} N={N} {prec}")
     nv, hist = S.stfas_op_nso(ctx, xd, to_dev(w, prec))
-    H = stfas.Hierarchy(g, N, dt, K / r, omega=omega or 1.0, lm=lm, velocity="vorticity", local_adv=ORACLE_LOCAL[local])
+    # defaults: omega 1; the perturbation off with the block, mu dt^2 = 1 without it
+    lm_ref = lm if lm else (1.0 if local == "collapsed" else 0.0)
+    H = stfas.Hierarchy(g, N, dt, K / r, omega=omega or 1.0, lm=lm_ref, velocity="vorticity",
+                        local_adv={"default": "finest", "exact": True, "collapsed": False}[local])
     nv_ref, hist_ref = stfas.nso(H, x, w, max_vcycles=3, fixed_counts=True)
     assert nv == nv_ref == 3
     for k in range(4):
@@ -146,7 +156,7 @@ def test_rotational_vcycles(n, N, prec, omega, lm, local):
     ctx.destroy()
 
 
-def _solve_pair(w, prec, local="finest", **kw):
+def _solve_pair(w, prec, local="default", **kw):
     from paper_1608_01102_amd import stfas as S
     g = Grid(w["n"])
     N = w["num_steps"]
@@ -252,27 +262,54 @@ def test_rotational_3d_kkt_residual_all_levels(n, N, prec):
     ctx.destroy()
 
 
-@pytest.mark.parametrize("omega,lm", [(0.0, 0.0), (0.7, 2.0)])
+@pytest.mark.parametrize("local,omega,lm", [("default", 0.0, 0.0), ("collapsed", 0.7, 2.0), ("finest", 1.0, 1.0),
+                                            ("exact", 0.7, 2.0)])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,N", CASES_3D)
-def test_rotational_3d_scgs_sweep(n, N, prec, omega, lm):
-    """3D takes the smoother without the local block; (0, 0) are the defaults
-    there (omega 1, the perturbation mu dt^2 = 1)."""
-    S, ctx, g, dt, K = _ctx(n, N, prec, scgs_omega=omega, scgs_lm=lm)
+def test_rotational_3d_scgs_sweep(n, N, prec, omega, lm, local):
+    """The 3D local solves: eq:HESS's 7x7 blocks with the cell's 6x6 block of
+    dAdv/dv (reduced to 5 divergence-free directions) or without it; the 3D
+    defaults leave it out (omega 1, mu dt^2 = 1).  Without a perturbation this
+    random state makes some cells' last Schur complement nearly singular after
+    a few colours (smallest to largest eigenvalue 7e-9), so the block runs
+    are checked with one."""
+    S, ctx, g, dt, K = _ctx(n, N, prec, local=local, scgs_omega=omega, scgs_lm=lm)
     rng = np.random.default_rng(82)
+    lm_ref = lm if lm else 1.0
     for level in (0, ctx.num_levels() - 1):
         gl = Grid(tuple(x >> level for x in n), g.h * 2 ** level)
-        L = kkt.Level(gl, N, dt, K / 1e-2, omega=omega or 1.0, lm=lm or 1.0, velocity="vorticity")
+        L = kkt.Level(gl, N, dt, K / 1e-2, omega=omega or 1.0, lm=lm_ref, velocity="vorticity",
+                      local_adv=_block_on(local, level, 3))
         x = _state(gl, N, rng, 0.3, prec)
         w = _q(_faces(gl, rng, N), prec)
         res = _state(gl, N, rng, 1.0, prec) if level > 0 else None
         xd = _dev(x, prec)
-        flag(f"rotational 3d scgs n={n} level={level} {prec}")
+        flag(f"rotational 3d scgs n={n} level={level} {prec} {local}")
         S.stfas_op_scgs_sweep(ctx, level, xd, to_dev(w, prec), _dev(res, prec) if res else None)
         ref = [a.copy() for a in x]
         scgs.sweep(L, ref, w, res if res else [np.zeros_like(a) for a in x])
         for k in range(4):
             assert rel(to_np(xd[k]), ref[k]) <= TOL[prec], (level, k)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec,N", [("fp64", 147), ("mixed", 293)])
+def test_rotational_3d_scgs_sweep_long_horizon(prec, N):
+    """3D horizons whose local records (56 words per slot) pass 64 KB per cell
+    take the three-launch form of the local solve (records in the workspace)."""
+    n = (8, 8, 8)
+    S, ctx, g, dt, K = _ctx(n, N, prec, local="finest", scgs_lm=1.0)
+    rng = np.random.default_rng(85)
+    L = kkt.Level(g, N, dt, K / 1e-2, lm=1.0, velocity="vorticity")
+    x = _state(g, N, rng, 0.3, prec)
+    w = _q(_faces(g, rng, N), prec)
+    xd = _dev(x, prec)
+    flag(f"rotational 3d scgs long horizon N={N} {prec}")
+    S.stfas_op_scgs_sweep(ctx, 0, xd, to_dev(w, prec), None)
+    ref = [a.copy() for a in x]
+    scgs.sweep(L, ref, w, [np.zeros_like(a) for a in x])
+    for k in range(4):
+        assert rel(to_np(xd[k]), ref[k]) <= TOL[prec], k
     ctx.destroy()
 
 

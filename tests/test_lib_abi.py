@@ -89,23 +89,24 @@ def test_velocity_operator_selection():
                      S.stfas_workspace_bytes(S.make_problem((32, 32), N, 1e-3, precision=prec)))
             assert extra == (0 if N == 10 else (16 * 16 * N * 24 * word + 255) // 256 * 256), (prec, N)
     assert S.stfas_step_work_bytes(ok) == S.stfas_step_work_bytes(S.make_problem((32, 32), 10, 1e-3))
-    # 3D: the operator is taken without the smoother's local block (no block scratch); asking for the
-    # block on every level is invalid there
-    ok3d = S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational")
-    assert S.stfas_workspace_bytes(ok3d) == S.stfas_workspace_bytes(S.make_problem((16, 16, 16), 10, 1e-3))
-    assert S.stfas_workspace_bytes(S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational",
-                                                  scgs_local="collapsed")) > 0
-    assert S.stfas_workspace_bytes(S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational",
-                                                  scgs_local="exact")) == 0
+    # 3D: the local records of a 16^3 x 10 colour fit the one-launch form (no workspace); at 64^3 the
+    # finest colour (32^3 cells) takes the three launches, records of 56 words per (cell, slot)
+    for loc in ("finest", "collapsed", "exact"):
+        p3 = S.make_problem((16, 16, 16), 10, 1e-3, velocity="rotational", scgs_local=loc)
+        assert S.stfas_workspace_bytes(p3) == S.stfas_workspace_bytes(S.make_problem((16, 16, 16), 10, 1e-3))
+    big = S.stfas_workspace_bytes(S.make_problem((64, 64, 64), 8, 1e-3, velocity="rotational", precision="mixed",
+                                                 scgs_local="finest"))
+    assert big - S.stfas_workspace_bytes(S.make_problem((64, 64, 64), 8, 1e-3, precision="mixed")) == \
+        (32 ** 3 * 8 * 56 * 4 + 255) // 256 * 256
     bad = S.make_problem((32, 32), 10, 1e-3)
     bad.velocity_op = 2
     assert S.stfas_workspace_bytes(bad) == 0
     # the smoother's local matrix: the collapsed form keeps no block scratch; the
     # switch is the rotational operator's only, and 0, 1 or 2
-    for loc in ("collapsed", "finest"):
+    for loc in ("collapsed", "finest", "default"):
         col = S.make_problem((32, 32), 10, 1e-3, velocity="rotational", scgs_local=loc)
         assert S.stfas_workspace_bytes(col) == S.stfas_workspace_bytes(S.make_problem((32, 32), 10, 1e-3))
-    for vel, loc in (("sl", 1), ("sl", 2), ("rotational", 3), ("rotational", -1)):
+    for vel, loc in (("sl", 1), ("sl", 3), ("rotational", 4), ("rotational", -1)):
         assert S.stfas_workspace_bytes(S.make_problem((32, 32), 10, 1e-3, velocity=vel, scgs_local=loc)) == 0
 
 

@@ -148,7 +148,7 @@ def _colour_rows(g, colour):
     return faces[g.interior_mask()[faces] > 0], scgs._cell_flat(g, cells)
 
 
-@pytest.mark.parametrize("n", [(8, 8), (9, 6)])
+@pytest.mark.parametrize("n", [(8, 8), (9, 6), (6, 4, 4)])
 def test_local_block_is_the_exact_jacobian_at_zero_u(n, rng):
     """eq:HESS with the cell's block of dAdv/dv: at u = 0 (where the second
     derivative of Adv that eq:HESS leaves out is multiplied by zero) it is
@@ -164,7 +164,7 @@ def test_local_block_is_the_exact_jacobian_at_zero_u(n, rng):
     w = np.stack([_faces(g, rng, 0.5) for _ in range(N)])
     z = [np.stack([_faces(g, rng) for _ in range(N)]), rng.standard_normal((N, g.ncell)),
          np.stack([_faces(g, rng) for _ in range(N)]), rng.standard_normal((N, g.ncell))]
-    for colour in range(4):
+    for colour in range(2 ** g.dim):
         fr, cr = _colour_rows(g, colour)
         for local_adv, order in ((True, 2.0), (False, 1.0)):
             L = kkt.Level(g, N, dt, kr, velocity="vorticity", local_adv=local_adv)
