@@ -1,62 +1,16 @@
 // The rotational velocity operator of Sec. 3.1 eq:NSA on the MAC grid:
 // Adv[v] discretises (curl v) x v (the gradient part of (v . grad) v goes
-// into the kinetic pressure).  In 2D:
-//
-//   node vorticity (cell corners, the circulation around the node's dual
-//   cell; zero on the walls):  w_n = (v_y right - v_y left - v_x above + v_x below)/h
-//   node sums:  Sx_n, Sy_n = the two incident x-faces, y-faces of node n
-//   Adv_x(f) = -1/4 sum over the end nodes n of x-face f of w_n Sy_n
-//   Adv_y(g) = +1/4 sum over the end nodes n of y-face g of w_n Sx_n
-//
-// Each (x-face, y-face) pair that meets at a node enters both components
-// with the same weight and opposite signs, so sum_f v_f Adv_f(v) = 0: the
-// operator does no work, as (curl v) x v does not.  Adv is bilinear in
-// (w(v), v); the transpose of its Jacobian, J_Adv(v)^T y, is the gradient in
-// v of <y, Adv[v]> = 1/4 sum_n w_n (Sx_n Yy_n - Sy_n Yx_n), again a stencil
-// of node quantities.  Everything is evaluated per face from its two end
-// nodes; wall faces carry nothing.  In 3D the vorticity sits on the edges
-// (rot_adv, rot_adv_T below take either dimension); the node helpers serve
-// the 2D local block of the smoother.
+// into the kinetic pressure), with the vorticity on the grid's edges (in 2D
+// the edges along z are the grid nodes).  Adv is bilinear in (w(v), v); the
+// transpose of its Jacobian, J_Adv(v)^T y, is the gradient in v of
+// <y, Adv[v]>, again a stencil of edge quantities.  Everything is evaluated
+// per face from the edges at its ends; wall faces carry nothing.
 #pragma once
 #include "common.hpp"
 
 namespace stfas {
 
-// v_x at x-face (I, j) and v_y at y-face (i, J); 0 outside the lattice.
-template <typename T>
-__device__ inline T rot_vx(const Grid& g, const T* f, int I, int j) {
-    return (I >= 0 && I <= g.n[0] && j >= 0 && j < g.n[1]) ? f[face_index(g, 0, I, j, 0)] : (T)0;
-}
-template <typename T>
-__device__ inline T rot_vy(const Grid& g, const T* f, int i, int J) {
-    return (i >= 0 && i < g.n[0] && J >= 0 && J <= g.n[1]) ? f[face_index(g, 1, i, J, 0)] : (T)0;
-}
-
-// Node sums of a face field at node (I, J).  masked: wall faces count as 0.
-template <typename T>
-__device__ inline void rot_sums(const Grid& g, const T* f, int I, int J, bool masked, T& sx, T& sy) {
-    const int n0 = g.n[0], n1 = g.n[1];
-    const bool wx = masked && (I == 0 || I == n0);      // both incident x-faces lie on a wall column
-    sx = (T)0;
-    if (!wx) {
-        if (J <= n1 - 1) sx += rot_vx(g, f, I, J);
-        if (J >= 1) sx += rot_vx(g, f, I, J - 1);
-    }
-    const bool wy = masked && (J == 0 || J == n1);
-    sy = (T)0;
-    if (!wy) {
-        if (I <= n0 - 1) sy += rot_vy(g, f, I, J);
-        if (I >= 1) sy += rot_vy(g, f, I - 1, J);
-    }
-}
-
-template <typename T>
-__device__ inline T rot_vorticity(const Grid& g, const T* v, int I, int J, T ih) {
-    if (I <= 0 || I >= g.n[0] || J <= 0 || J >= g.n[1]) return (T)0;
-    return (rot_vy(g, v, I, J) - rot_vy(g, v, I - 1, J) - rot_vx(g, v, I, J) + rot_vx(g, v, I, J - 1)) * ih;
-}
-
-// The same operator on the edges of a 2D or 3D grid.  For each cyclic triple
+// The operator on the edges of a 2D or 3D grid.  For each cyclic triple
 // of axes (c, p, q) = (z, x, y), (x, y, z), (y, z, x) (2D: the first only, the
 // z-edges being the nodes) a c-edge sits at a p-node, a q-node and a c-cell
 // (lattice coordinates e[3]) and carries the circulation
@@ -64,7 +18,10 @@ __device__ inline T rot_vorticity(const Grid& g, const T* v, int I, int J, T ih)
 // two incident p-faces and q-faces; each incident p-face gains -1/4 w_c S_q and
 // each incident q-face +1/4 w_c S_p: (curl v) x v, with every pair of faces
 // meeting at an edge entering both components with opposite signs (no work).
-// For (c, p, q) = (z, x, y) this is the node form above.
+// In 2D, with (c, p, q) = (z, x, y) only: node vorticity
+// w_n = (v_y right - v_y left - v_x above + v_x below)/h, Adv_x(f) = -1/4 sum
+// over the end nodes n of x-face f of w_n Sy_n, Adv_y(g) = +1/4 sum over the
+// end nodes of y-face g of w_n Sx_n.
 template <int D>
 struct RotTriples;
 template <>
