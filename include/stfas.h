@@ -79,7 +79,8 @@ typedef enum { STFAS_DENSITY_SL = 0, STFAS_DENSITY_UPWIND = 1 } stfas_density;
  * elimination in time), by default on the finest level in 2D (scgs_local); the
  * re-simulation of the outputs (and stfas_step_forward) takes 4 fixed-point
  * steps per time step.  stfas_lbfgs and stfas_step_backward accept only the
- * semi-Lagrangian operator (STFAS_E_INVALID otherwise). */
+ * semi-Lagrangian operator (STFAS_E_INVALID otherwise); stfas_step_backward_u
+ * takes both. */
 typedef enum { STFAS_VELOCITY_SL = 0, STFAS_VELOCITY_ROTATIONAL = 1 } stfas_velocity;
 
 /* Problem description (Sec. 3.2 eq:opt and the parameter table of Sec. 5).
@@ -200,6 +201,21 @@ stfas_status stfas_step_forward(const stfas_problem* prob, void* hip_stream, con
 stfas_status stfas_step_backward(const stfas_problem* prob, void* hip_stream, const void* rho, const void* v,
                                  const void* g_rho_out, const void* g_v_out, void* g_rho, void* g_v, void* g_u,
                                  void* work);
+
+/* The adjoint of stfas_step_forward for either velocity operator, given
+ * also the step's control u (the rotational operator's fixed-point iterates
+ * depend on it; it is read only there).  For the rotational operator it is
+ * the exact adjoint of the fixed-point steps as computed (Sec. 3.1 eq:NSA
+ * solved by 4 of them, forward again inside the call): with b = v + dt u,
+ * y_0 = Q b and y_m = Q(b - dt Adv[y_{m-1}]), v_out = y_4,
+ *   g_y <- g_v_out; for m = 4 .. 0: g_w = Q g_y, g_b += g_w,
+ *   g_y <- -dt J_Adv(y_{m-1})^T g_w (m > 0);
+ * g_u = dt g_b and g_v = g_b + (dA/dv)^T g_rho_out; g_rho as in
+ * stfas_step_backward.  For the semi-Lagrangian operator it equals
+ * stfas_step_backward.  Asynchronous; work as for stfas_step_forward. */
+stfas_status stfas_step_backward_u(const stfas_problem* prob, void* hip_stream, const void* rho, const void* v,
+                                   const void* u, const void* g_rho_out, const void* g_v_out, void* g_rho, void* g_v,
+                                   void* g_u, void* work);
 
 size_t stfas_step_work_bytes(const stfas_problem* prob);
 

@@ -59,6 +59,8 @@ _SIGS = {
                                      c_void_p, c_void_p, c_void_p, c_void_p]),
     "stfas_step_backward": (c_int32, [ctypes.POINTER(StfasProblem), c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "stfas_step_backward_u": (c_int32, [ctypes.POINTER(StfasProblem), c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "stfas_step_forward_noalloc": (c_int32, [ctypes.POINTER(StfasProblem), c_void_p, c_void_p, c_void_p, c_void_p,
                                              c_void_p, c_void_p, c_void_p]),
     "stfas_step_work_bytes": (c_size_t, [ctypes.POINTER(StfasProblem)]),

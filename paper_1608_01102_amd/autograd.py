@@ -1,5 +1,6 @@
 """Differentiation form: one simulation step (Sec. 3.1 eq:NSA-eq:Conv with
-semi-Lagrangian advection) as a torch.autograd.Function whose backward is
+semi-Lagrangian advection, or the rotational velocity operator's implicit
+update by fixed-point steps) as a torch.autograd.Function whose backward is
 the library's adjoint kernels, and a checkpointed trajectory.
 
   forward:  rho' = A(rho, v),  v' = Q(S(v) + dt u)
@@ -46,20 +47,21 @@ class SimStep(torch.autograd.Function):
         rho_o = torch.empty_like(rho)
         v_o = torch.empty_like(v)
         S.stfas_step_forward(prob, rho, v, u, rho_o, v_o, work=_Work.get(prob, rho.device))
-        ctx.save_for_backward(rho, v)
+        ctx.save_for_backward(rho, v, u)
         ctx.prob = prob
         return rho_o, v_o
 
     @staticmethod
     def backward(ctx, g_rho_o, g_v_o):
-        rho, v = ctx.saved_tensors
+        rho, v, u = ctx.saved_tensors
         prob = ctx.prob
         g_rho_o = torch.zeros_like(rho) if g_rho_o is None else g_rho_o.contiguous()
         g_v_o = torch.zeros_like(v) if g_v_o is None else g_v_o.contiguous()
         g_rho = torch.empty_like(rho)
         g_v = torch.empty_like(v)
         g_u = torch.empty_like(v)
-        S.stfas_step_backward(prob, rho, v, g_rho_o, g_v_o, g_rho, g_v, g_u, work=_Work.get(prob, rho.device))
+        # the control enters the rotational step's fixed-point iterates, so its adjoint takes u
+        S.stfas_step_backward_u(prob, rho, v, u, g_rho_o, g_v_o, g_rho, g_v, g_u, work=_Work.get(prob, rho.device))
         return g_rho, g_v, g_u, None
 
 

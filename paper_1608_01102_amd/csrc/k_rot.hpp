@@ -134,4 +134,19 @@ __global__ void k_rot_rhs(Grid g, T dt, const T* __restrict__ v, const T* __rest
     out[f] = w;
 }
 
+// One step of the adjoint of the fixed-point steps: out = -dt J_Adv(y)^T x
+// on interior faces (y = null: out = x there), 0 on walls.
+template <typename T, int D>
+__global__ void k_rot_adj(Grid g, T dt, const T* __restrict__ y, const T* __restrict__ x, T* __restrict__ out) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= g.nface) return;
+    int a, i, j, k;
+    face_decode(g, f, a, i, j, k);
+    if (!face_interior(g, a, i, j, k)) {
+        out[f] = (T)0;
+        return;
+    }
+    out[f] = y ? -dt * rot_adv_T<T, D>(g, y, x, a, i, j, k, (T)(1.0 / g.h)) : x[f];
+}
+
 }  // namespace stfas

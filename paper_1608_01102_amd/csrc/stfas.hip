@@ -65,10 +65,11 @@ struct Step {
     Grid g;
     Poisson<T, D> pois;
     T *w, *gw;
+    T *ys[ROT_PICARD] = {}, *gy = nullptr, *gbase = nullptr;   // rotational adjoint: iterates, cotangents
     UpwindExp<T, D> up;
-    bool upwind;
+    bool upwind, vort;
     hipStream_t st;
-    Step(const Params& p, hipStream_t s) : upwind(p.density == STFAS_DENSITY_UPWIND), st(s) {
+    Step(const Params& p, hipStream_t s) : upwind(p.density == STFAS_DENSITY_UPWIND), vort(p.vort != 0), st(s) {
         const int n[3] = {p.n[0], p.n[1], p.n[2]};
         g = make_grid(p.dim, n, 1.0 / p.n[0]);
         pois.init(g, 1, s);
@@ -77,6 +78,11 @@ struct Step {
         pois.layout(A, pinv);
         w = A.take<T>(g.nface);
         gw = A.take<T>(g.nface);
+        if (vort) {
+            for (int m = 0; m < ROT_PICARD; ++m) ys[m] = A.take<T>(g.nface);
+            gy = A.take<T>(g.nface);
+            gbase = A.take<T>(g.nface);
+        }
         if (upwind) up.layout(A, g.ncell);
     }
     size_t bytes() {
@@ -107,8 +113,12 @@ struct Step {
     }
 
     void backward(const Params& p, const T* rho, const T* v, const T* grho_o, const T* gv_o, T* grho, T* gv,
-                  T* gu) {
+                  T* gu, const T* u) {
         const T cfl = (T)(p.dt / g.h);
+        if (vort) {
+            backward_rotational(p, rho, v, u, grho_o, gv_o, grho, gv, gu);
+            return;
+        }
         pois.project(gv_o, gw, nullptr, 1, p.poisson_rtol, step_cycles(p), nullptr);       // g_w = Q g_v'
         k_axpby<T><<<blocks_for(g.nface, BS), BS, 0, st>>>(g.nface, (T)p.dt, gw, (T)0, nullptr, gu);
         // g_v = (dA/dv)^T g_rho' + J_S^T g_w,  g_rho = (dA/drho)^T g_rho'
@@ -121,6 +131,39 @@ struct Step {
             launch_advect_T<T, D>(g, cfl, grho_o, v, grho, 1, st);
         }
         launch_self_advect_T<T, D>(g, cfl, v, gw, (T)1, gv, 1, st);
+    }
+
+    // The adjoint of the rotational step's fixed-point steps as computed:
+    // y_0 = Q(b), y_m = Q(b - dt Adv[y_{m-1}]) with b = v + dt u (walls 0),
+    // v' = y_M.  Backward from g_y = g_v': g_w = Q g_y adds to g_b and
+    // g_y <- -dt J_Adv(y_{m-1})^T g_w, for m = M .. 1, then g_w = Q g_y adds
+    // to g_b; g_u = dt g_b, g_v = g_b + the density part.
+    void backward_rotational(const Params& p, const T* rho, const T* v, const T* u, const T* grho_o,
+                             const T* gv_o, T* grho, T* gv, T* gu) {
+        const T cfl = (T)(p.dt / g.h), dt = (T)p.dt;
+        const int nb = blocks_for(g.nface, BS);
+        k_rot_rhs<T, D><<<nb, BS, 0, st>>>(g, dt, v, u, nullptr, w);
+        pois.project(w, ys[0], nullptr, 1, p.poisson_rtol, step_cycles(p), nullptr);
+        for (int m = 1; m < ROT_PICARD; ++m) {
+            k_rot_rhs<T, D><<<nb, BS, 0, st>>>(g, dt, v, u, ys[m - 1], w);
+            pois.project(w, ys[m], nullptr, 1, p.poisson_rtol, step_cycles(p), nullptr);
+        }
+        k_rot_adj<T, D><<<nb, BS, 0, st>>>(g, dt, nullptr, gv_o, gy);        // g_y = g_v' (walls 0)
+        k_fill<T><<<nb, BS, 0, st>>>(g.nface, gbase, (T)0);
+        for (int m = ROT_PICARD; m >= 0; --m) {
+            pois.project(gy, gw, nullptr, 1, p.poisson_rtol, step_cycles(p), nullptr);
+            k_axpby<T><<<nb, BS, 0, st>>>(g.nface, (T)1, gw, (T)1, gbase, gbase);
+            if (m > 0) k_rot_adj<T, D><<<nb, BS, 0, st>>>(g, dt, ys[m - 1], gw, gy);
+        }
+        k_axpby<T><<<nb, BS, 0, st>>>(g.nface, dt, gbase, (T)0, nullptr, gu);
+        k_fill<T><<<blocks_for(g.ncell, BS), BS, 0, st>>>(g.ncell, grho, (T)0);
+        if (upwind) {
+            up.adjoint(g, p.dt, grho_o, rho, v, grho, gv, nullptr, (T)1, st);
+        } else {
+            k_advect_dv_T<T, D><<<nb, BS, 0, st>>>(g, cfl, grho_o, rho, v, nullptr, (T)1, gv, g.ncell, g.nface);
+            launch_advect_T<T, D>(g, cfl, grho_o, v, grho, 1, st);
+        }
+        k_axpby<T><<<nb, BS, 0, st>>>(g.nface, (T)1, gbase, (T)1, gv, gv);
     }
 };
 
@@ -176,7 +219,8 @@ char* noalloc_scratch(const Grid& coarse, hipStream_t st) {
 
 template <typename T, int D>
 stfas_status run_step(const Params& p, hipStream_t st, void* work, bool fwd, const void* a0, const void* a1,
-                      const void* a2, const void* a3, void* o0, void* o1, void* o2, bool noalloc = false) {
+                      const void* a2, const void* a3, void* o0, void* o1, void* o2, bool noalloc = false,
+                      const void* a4 = nullptr) {
     Step<T, D> s(p, st);
     if (!s.pois.coarse_ok()) return STFAS_E_INVALID;
     Arena A;
@@ -196,19 +240,20 @@ stfas_status run_step(const Params& p, hipStream_t st, void* work, bool fwd, con
     if (fwd)
         s.forward(p, (const T*)a0, (const T*)a1, (const T*)a2, (T*)o0, (T*)o1, (T*)o2);
     else
-        s.backward(p, (const T*)a0, (const T*)a1, (const T*)a2, (const T*)a3, (T*)o0, (T*)o1, (T*)o2);
+        s.backward(p, (const T*)a0, (const T*)a1, (const T*)a2, (const T*)a3, (T*)o0, (T*)o1, (T*)o2, (const T*)a4);
     HCK(hipPeekAtLastError());
     return STFAS_OK;
 }
 
 stfas_status dispatch_step(const Params& p, hipStream_t st, void* work, bool fwd, const void* a0, const void* a1,
-                           const void* a2, const void* a3, void* o0, void* o1, void* o2, bool noalloc = false) {
+                           const void* a2, const void* a3, void* o0, void* o1, void* o2, bool noalloc = false,
+                           const void* a4 = nullptr) {
     if (p.precision == STFAS_FP64) {
-        if (p.dim == 2) return run_step<double, 2>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc);
-        return run_step<double, 3>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc);
+        if (p.dim == 2) return run_step<double, 2>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc, a4);
+        return run_step<double, 3>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc, a4);
     }
-    if (p.dim == 2) return run_step<float, 2>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc);
-    return run_step<float, 3>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc);
+    if (p.dim == 2) return run_step<float, 2>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc, a4);
+    return run_step<float, 3>(p, st, work, fwd, a0, a1, a2, a3, o0, o1, o2, noalloc, a4);
 }
 
 size_t step_bytes(const Params& p) {
@@ -382,6 +427,18 @@ stfas_status stfas_step_backward(const stfas_problem* prob, void* hip_stream, co
     if (!rho || !v || !g_rho_out || !g_v_out || !g_rho || !g_v || !g_u || !work) return STFAS_E_INVALID;
     return guard([&]() {
         return dispatch_step(p, (hipStream_t)hip_stream, work, false, rho, v, g_rho_out, g_v_out, g_rho, g_v, g_u);
+    });
+}
+
+stfas_status stfas_step_backward_u(const stfas_problem* prob, void* hip_stream, const void* rho, const void* v,
+                                   const void* u, const void* g_rho_out, const void* g_v_out, void* g_rho, void* g_v,
+                                   void* g_u, void* work) {
+    Params p;
+    if (!resolve(prob, p)) return STFAS_E_INVALID;
+    if (!rho || !v || !u || !g_rho_out || !g_v_out || !g_rho || !g_v || !g_u || !work) return STFAS_E_INVALID;
+    return guard([&]() {
+        return dispatch_step(p, (hipStream_t)hip_stream, work, false, rho, v, g_rho_out, g_v_out, g_rho, g_v, g_u,
+                             false, u);
     });
 }
 

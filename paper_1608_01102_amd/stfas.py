@@ -232,6 +232,16 @@ def stfas_step_backward(prob, rho, v, g_rho_out, g_v_out, g_rho, g_v, g_u, work=
         _ptr(g_v, dt, f, "g_v"), _ptr(g_u, dt, f, "g_u"), ctypes.c_void_p(work.data_ptr())), "stfas_step_backward")
 
 
+def stfas_step_backward_u(prob, rho, v, u, g_rho_out, g_v_out, g_rho, g_v, g_u, work=None, stream=None):
+    dt = dtype_of(prob)
+    c, f = counts(prob)
+    work = _step_work(prob, work, rho.device)
+    check(_lib.load().stfas_step_backward_u(
+        ctypes.byref(prob), _stream(stream), _ptr(rho, dt, c, "rho"), _ptr(v, dt, f, "v"), _ptr(u, dt, f, "u"),
+        _ptr(g_rho_out, dt, c, "g_rho_out"), _ptr(g_v_out, dt, f, "g_v_out"), _ptr(g_rho, dt, c, "g_rho"),
+        _ptr(g_v, dt, f, "g_v"), _ptr(g_u, dt, f, "g_u"), ctypes.c_void_p(work.data_ptr())), "stfas_step_backward_u")
+
+
 # ---------------------------------------------------------------- operator level
 def stfas_op_advect(ctx, batch, rho, v, out):
     c, f = ctx.cells, ctx.faces

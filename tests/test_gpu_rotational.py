@@ -215,6 +215,77 @@ def test_rotational_step_forward(prec):
     assert rel(to_np(ro), rr) <= tol and rel(to_np(vo), vr) <= tol and rel(to_np(po), pr) <= 10 * tol
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n", [(24, 20), (12, 10, 8)])
+def test_rotational_step_backward(n, prec):
+    """The adjoint of the rotational step (its fixed-point steps as computed)
+    against the oracle's, in rho, v and u."""
+    from paper_1608_01102_amd import stfas as S
+    from oracle import step
+    g = Grid(n)
+    dt = 0.9 * g.h
+    prob = S.make_problem(n, 1, 1.0, dt=dt, precision=prec, velocity="rotational")
+    rng = np.random.default_rng(86)
+    rho = _q(synthetic.smooth_noise_density(n, rng, 1.0), prec)
+    v = _q(synthetic.curl_noise_velocity(n, rng, 1.0, 1.0, dt / g.h), prec)
+    u = _q(synthetic.random_faces(n, rng, 2.0), prec)
+    grn = _q(rng.standard_normal(g.ncell), prec)
+    gvn = _q(synthetic.random_faces(n, rng, 1.0), prec)
+    gr, gv, gu = empty(g.ncell, prec), empty(g.nface, prec), empty(g.nface, prec)
+    flag(f"rotational step adjoint n={n} {prec}")
+    S.stfas_step_backward_u(prob, to_dev(rho, prec), to_dev(v, prec), to_dev(u, prec), to_dev(grn, prec),
+                            to_dev(gvn, prec), gr, gv, gu)
+    a, b, c = step.step_backward(g, rho, v, grn, gvn, dt, velocity="vorticity", u=u)
+    tol = TOL[prec] if prec == "fp64" else 2e-5
+    assert rel(to_np(gr), a) <= tol and rel(to_np(gv), b) <= tol and rel(to_np(gu), c) <= tol
+
+
+def test_step_backward_u_equals_the_sl_adjoint():
+    """With the semi-Lagrangian operator the adjoint that takes u is the one
+    that does not (to the rounding of the transposes' atomic adds, whose
+    order varies from call to call)."""
+    from paper_1608_01102_amd import stfas as S
+    n = (20, 16)
+    g = Grid(n)
+    prob = S.make_problem(n, 1, 1.0, precision="fp64")
+    rng = np.random.default_rng(87)
+    args = [to_dev(a, "fp64") for a in (synthetic.smooth_noise_density(n, rng, 1.0),
+                                        synthetic.curl_noise_velocity(n, rng, 1.0, 1.0, 1.0))]
+    u = to_dev(synthetic.random_faces(n, rng, 1.0), "fp64")
+    gin = [to_dev(rng.standard_normal(g.ncell), "fp64"), to_dev(synthetic.random_faces(n, rng, 1.0), "fp64")]
+    o1 = [empty(g.ncell, "fp64"), empty(g.nface, "fp64"), empty(g.nface, "fp64")]
+    o2 = [empty(g.ncell, "fp64"), empty(g.nface, "fp64"), empty(g.nface, "fp64")]
+    S.stfas_step_backward(prob, *args, *gin, *o1)
+    S.stfas_step_backward_u(prob, args[0], args[1], u, *gin, *o2)
+    for x, y in zip(o1, o2):
+        assert rel(to_np(x), to_np(y)) <= 1e-13
+
+
+def test_rotational_autograd_step():
+    """The differentiation form with the rotational operator: torch.autograd
+    through SimStep against the oracle's adjoint."""
+    import torch
+    from paper_1608_01102_amd import autograd as AG, stfas as S
+    from oracle import step
+    n = (16, 12)
+    g = Grid(n)
+    dt = 0.8 * g.h
+    prob = S.make_problem(n, 1, 1.0, dt=dt, precision="fp64", velocity="rotational")
+    rng = np.random.default_rng(88)
+    rho = synthetic.smooth_noise_density(n, rng, 1.0)
+    v = synthetic.curl_noise_velocity(n, rng, 1.0, 1.0, dt / g.h)
+    u = synthetic.random_faces(n, rng, 1.0)
+    wr, wv = rng.standard_normal(g.ncell), synthetic.random_faces(n, rng, 1.0)
+    t = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True) for a in (rho, v, u)]
+    flag("rotational autograd step")
+    ro, vo = AG.step(t[0], t[1], t[2], prob)
+    loss = (ro * torch.tensor(wr, device="cuda")).sum() + (vo * torch.tensor(wv, device="cuda")).sum()
+    grads = torch.autograd.grad(loss, t)
+    ref = step.step_backward(g, rho, v, wr, wv, dt, velocity="vorticity", u=u)
+    for a, b in zip(grads, ref):
+        assert rel(a.detach().cpu().numpy(), b) <= TOL["fp64"]
+
+
 def test_rotational_rejected_where_not_built():
     from paper_1608_01102_amd import stfas as S
     from paper_1608_01102_amd._lib import STFAS_E_INVALID, StfasError

@@ -76,7 +76,7 @@ def test_density_operator_selection():
 def test_velocity_operator_selection():
     """The rotational velocity operator: an unknown value is rejected before
     any allocation; the forward step takes it with the same scratch as the
-    semi-Lagrangian one."""
+    semi-Lagrangian one plus the adjoint's iterates."""
     from paper_1608_01102_amd import stfas as S
     ok = S.make_problem((32, 32), 10, 1e-3, velocity="rotational")
     assert S.stfas_workspace_bytes(ok) > 0
@@ -88,7 +88,10 @@ def test_velocity_operator_selection():
             extra = (S.stfas_workspace_bytes(S.make_problem((32, 32), N, 1e-3, velocity="rotational", precision=prec)) -
                      S.stfas_workspace_bytes(S.make_problem((32, 32), N, 1e-3, precision=prec)))
             assert extra == (0 if N == 10 else (16 * 16 * N * 24 * word + 255) // 256 * 256), (prec, N)
-    assert S.stfas_step_work_bytes(ok) == S.stfas_step_work_bytes(S.make_problem((32, 32), 10, 1e-3))
+    # the step's scratch gains the adjoint's fixed-point iterates (4) and two cotangents, one face field each
+    nf = 33 * 32 + 32 * 33
+    assert S.stfas_step_work_bytes(ok) == S.stfas_step_work_bytes(S.make_problem((32, 32), 10, 1e-3)) + \
+        6 * ((nf * 8 + 255) // 256 * 256)
     # 3D: the local records of a 16^3 x 10 colour fit the one-launch form (no workspace); at 64^3 the
     # finest colour (32^3 cells) takes the three launches, records of 56 words per (cell, slot)
     for loc in ("finest", "collapsed", "exact"):

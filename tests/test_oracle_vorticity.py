@@ -245,3 +245,28 @@ def test_3d_operator_on_planar_fields_is_the_2d_operator(c, rng):
     got = vorticity.adv_T(g3, v3, y3)
     # the transpose also has no c part: the c faces enter no pairing with a nonzero partner here
     assert np.max(np.abs(got - _embed(g3, c, t2x, t2y))) <= 1e-12 * np.max(np.abs(t2x))
+
+
+@pytest.mark.parametrize("n", [(12, 10), (8, 6, 6)])
+def test_rotational_step_adjoint_matches_fd(n, rng):
+    """The adjoint of the rotational step (its fixed-point steps as computed)
+    against central differences of the forward step, in rho, v and u."""
+    g = Grid(n)
+    dt = 0.5 * g.h
+    rho = rng.standard_normal(g.ncell)
+    v, _ = poisson.project(g, _faces(g, rng, 1.0))
+    u = _faces(g, rng, 2.0)
+    grn = rng.standard_normal(g.ncell)
+    gvn = _faces(g, rng)
+
+    def loss(r, vv, uu):
+        rn, vn, _ = step.step_forward(g, r, vv, uu, dt, velocity="vorticity")
+        return rn @ grn + vn @ gvn
+    g_rho, g_v, g_u = step.step_backward(g, rho, v, grn, gvn, dt, velocity="vorticity", u=u)
+    for _ in range(3):
+        dr = rng.standard_normal(g.ncell)
+        dv, du = _faces(g, rng), _faces(g, rng)
+        e = 1e-6
+        fd = (loss(rho + e * dr, v + e * dv, u + e * du) - loss(rho - e * dr, v - e * dv, u - e * du)) / (2 * e)
+        ad = dr @ g_rho + dv @ g_v + du @ g_u
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1.0)
