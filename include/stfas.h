@@ -78,9 +78,10 @@ typedef enum { STFAS_DENSITY_SL = 0, STFAS_DENSITY_UPWIND = 1 } stfas_density;
  * eq:HESS with the cell's block of dAdv/dv (Sec. 4.3, solved by block
  * elimination in time), by default on the finest level in 2D (scgs_local); the
  * re-simulation of the outputs (and stfas_step_forward) takes 4 fixed-point
- * steps per time step.  stfas_lbfgs and stfas_step_backward accept only the
- * semi-Lagrangian operator (STFAS_E_INVALID otherwise); stfas_step_backward_u
- * takes both. */
+ * steps per time step.  stfas_step_backward accepts only the semi-Lagrangian
+ * operator (STFAS_E_INVALID otherwise); stfas_step_backward_u and stfas_lbfgs
+ * take both (for the rotational operator the gradient is the adjoint of its
+ * fixed-point steps as computed). */
 typedef enum { STFAS_VELOCITY_SL = 0, STFAS_VELOCITY_ROTATIONAL = 1 } stfas_velocity;
 
 /* Problem description (Sec. 3.2 eq:opt and the parameter table of Sec. 5).

@@ -9,7 +9,9 @@ Reduced objective (Sec. 3.2 eq:opt with the simulation eliminated):
   J(u) = 1/2 sum_k <e_k, C e_k> + r/2 sum_i |u_i|^2,  e_k = rho_k - rho*_k,
 with (rho_i, v_i) from the simulation started at (rho_0, v_0 = 0).  Its
 gradient is the adjoint of the step chain (each evaluation costs a forward
-and a backward pass, as the paper notes).
+and a backward pass, as the paper notes).  With the rotational velocity
+operator (velocity = "vorticity") the simulation is that of its fixed-point
+steps and the gradient is their exact adjoint.
 
 Optimiser (Nocedal & Wright, two-loop recursion): history m = 8 (the
 paper's), initial Hessian gamma I with gamma = s^T y / y^T y of the newest
@@ -29,7 +31,7 @@ from .admm import objectives, resimulate
 from .step import step_backward
 
 
-def gradient(g: Grid, rho, v, u, keys, r, dt, levels, kind="sl"):
+def gradient(g: Grid, rho, v, u, keys, r, dt, levels, kind="sl", velocity="sl"):
     """dJ/du by the adjoint of the step chain; rho, v from resimulate."""
     N = u.shape[0]
     gu = np.zeros_like(u)
@@ -39,7 +41,8 @@ def gradient(g: Grid, rho, v, u, keys, r, dt, levels, kind="sl"):
         if i in keys:
             e = rho[i] - keys[i]
             g_rho = g_rho + metric.apply_metric(g, e, levels)
-        g_rho, g_v, gu[i - 1] = step_backward(g, rho[i - 1], v[i - 1], g_rho, g_v, dt, kind=kind)
+        g_rho, g_v, gu[i - 1] = step_backward(g, rho[i - 1], v[i - 1], g_rho, g_v, dt, kind=kind,
+                                              velocity=velocity, u=u[i - 1])
     return gu + r * u
 
 
@@ -102,7 +105,7 @@ def minimize(fg, x0, iters, m=8, c1=1e-4, max_halvings=20, stop=None):
     return x, hist, done
 
 
-def solve(g: Grid, rho0, keys, N, r, dt, levels, iters, u0=None, m=8, eps_stop=0.0, kind="sl"):
+def solve(g: Grid, rho0, keys, N, r, dt, levels, iters, u0=None, m=8, eps_stop=0.0, kind="sl", velocity="sl"):
     """L-BFGS on J(u) over N steps from u0 (zero by default), at most iters
     iterations; eps_stop > 0 adds the visual-difference stop.  Returns u,
     the J history and the iterations done."""
@@ -111,13 +114,13 @@ def solve(g: Grid, rho0, keys, N, r, dt, levels, iters, u0=None, m=8, eps_stop=0
 
     def fg(x):
         u = x.reshape(shape)
-        rho, v = resimulate(g, rho0, u, dt, kind)
+        rho, v = resimulate(g, rho0, u, dt, kind, velocity)
         f = objectives(g, rho, keys, u, r, levels)[0]
-        return f, gradient(g, rho, v, u, keys, r, dt, levels, kind).ravel()
+        return f, gradient(g, rho, v, u, keys, r, dt, levels, kind, velocity).ravel()
 
     def visual_stop(xa, xb):
-        ra, _ = resimulate(g, rho0, xa.reshape(shape), dt, kind)
-        rb, _ = resimulate(g, rho0, xb.reshape(shape), dt, kind)
+        ra, _ = resimulate(g, rho0, xa.reshape(shape), dt, kind, velocity)
+        rb, _ = resimulate(g, rho0, xb.reshape(shape), dt, kind, velocity)
         return float(np.max(np.abs(rb - ra))) <= eps_stop
 
     x, hist, done = minimize(fg, u0.ravel(), iters, m=m, stop=visual_stop if eps_stop > 0 else None)

@@ -818,6 +818,17 @@ public:
         k_advect_dv_T<T, D><<<dim3(blocks_for(g.nface, BS), batch), BS, 0, st>>>(g, cfl(0), m, r, v, vtt, scale,
                                                                                 gv, g.ncell, g.nface);
     }
+    // one fixed-point step's right-hand side of the rotational update on level 0:
+    // out = v + dt u - dt Adv[vk] on interior faces (vk = null: without Adv)
+    void rot_rhs(const T* v, const T* u, const T* vk, T* out) {
+        const Grid& g = L[0];
+        k_rot_rhs<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, (T)P.dt, v, u, vk, out);
+    }
+    // out = -dt J_Adv(y)^T x on interior faces of level 0 (y = null: out = x there), 0 on walls
+    void rot_adj(const T* y, const T* x, T* out) {
+        const Grid& g = L[0];
+        k_rot_adj<T, D><<<blocks_for(g.nface, BS), BS, 0, st>>>(g, (T)P.dt, y, x, out);
+    }
     void self_advect(int l, const T* v, const T* u, T* out, int batch) {
         const Grid& g = L[l];
         k_self_advect<T, D><<<dim3(blocks_for(g.nface, BS), batch), BS, 0, st>>>(g, cfl(l), (T)P.dt, v, u, out,
@@ -1362,6 +1373,7 @@ public:
     static constexpr int LB_R = LB_M + 1;   // ring slots: the newest pair is written into a free one
     T *lb_rho, *lb_rho_prev, *lb_v, *lb_x, *lb_g, *lb_xt, *lb_gt, *lb_d, *lb_s[LB_R], *lb_y[LB_R];
     T *lb_grho, *lb_grho2, *lb_gv, *lb_gw;
+    T *lb_ys[ROT_PICARD] = {}, *lb_gy = nullptr, *lb_gb = nullptr;   // rotational step adjoint
     bool lb_alloc() {
         if (lb) return true;
         const long C = L[0].ncell, F = L[0].nface;
@@ -1383,6 +1395,11 @@ public:
             lb_grho2 = a.take<T>(C);
             lb_gv = a.take<T>(F);
             lb_gw = a.take<T>(F);
+            if (P.vort) {
+                for (int m = 0; m < ROT_PICARD; ++m) lb_ys[m] = a.take<T>(F);
+                lb_gy = a.take<T>(F);
+                lb_gb = a.take<T>(F);
+            }
         };
         plan(A);
         if (hipMalloc((void**)&lb, A.off) != hipSuccess) {
@@ -1405,6 +1422,17 @@ public:
         const long C = L[0].ncell, F = L[0].nface;
         fill(lb_v, F, (T)0);
         for (int i = 0; i < N; ++i) {
+            if (P.vort) {
+                // the implicit rotational update: ROT_PICARD fixed-point steps from Q(v + dt u)
+                T* vn = lb_v + (i + 1) * F;
+                rot_rhs(lb_v + i * F, u + i * F, nullptr, rs_w);
+                project(rs_w, vn, nullptr, 1);
+                for (int m = 0; m < ROT_PICARD; ++m) {
+                    rot_rhs(lb_v + i * F, u + i * F, vn, rs_w);
+                    project(rs_w, vn, nullptr, 1);
+                }
+                continue;
+            }
             self_advect(0, lb_v + i * F, u + i * F, rs_w, 1);
             project(rs_w, lb_v + (i + 1) * F, nullptr, 1);
         }
@@ -1433,6 +1461,31 @@ public:
                 }
             const T* rho = lb_rho + (long)(i - 1) * C;
             const T* v = lb_v + (long)(i - 1) * F;
+            if (P.vort) {
+                // the adjoint of the fixed-point steps (as in the step's adjoint): their
+                // iterates again, then g_w = Q g_y into g_b and g_y <- -dt J_Adv^T g_w
+                const T* ui = u + (long)(i - 1) * F;
+                rot_rhs(v, ui, nullptr, rs_w);
+                project(rs_w, lb_ys[0], nullptr, 1);
+                for (int m = 1; m < ROT_PICARD; ++m) {
+                    rot_rhs(v, ui, lb_ys[m - 1], rs_w);
+                    project(rs_w, lb_ys[m], nullptr, 1);
+                }
+                rot_adj(nullptr, lb_gv, lb_gy);
+                fill(lb_gb, F, (T)0);
+                for (int m = ROT_PICARD; m >= 0; --m) {
+                    project(lb_gy, lb_gw, nullptr, 1);
+                    axpby(F, (T)1, lb_gw, (T)1, lb_gb, lb_gb);
+                    if (m > 0) rot_adj(lb_ys[m - 1], lb_gw, lb_gy);
+                }
+                axpby(F, (T)P.dt, lb_gb, (T)0, nullptr, gout + (long)(i - 1) * F);   // g_u = dt g_b
+                fill(lb_grho2, C, (T)0);
+                dens_adj(lb_grho, rho, v, lb_grho2, lb_gv, nullptr, (T)1,
+                         (int)lb_k.size() == N ? lb_k[i - 1] : -1);             // (dA/drho)^T, (dA/dv)^T g_rho'
+                axpby(F, (T)1, lb_gb, (T)1, lb_gv, lb_gv);                          // + g_b
+                std::swap(lb_grho, lb_grho2);
+                continue;
+            }
             project(lb_gv, lb_gw, nullptr, 1);                                   // g_w = Q g_v'
             axpby(F, (T)P.dt, lb_gw, (T)0, nullptr, gout + (long)(i - 1) * F);   // g_u = dt g_w
             fill(lb_grho2, C, (T)0);
@@ -1445,7 +1498,6 @@ public:
     }
     int lbfgs(const void* rho0v, int nk, const int* ks, const void* keysv, void* uv, int iters, double eps_stop,
               double* hist) override {
-        if (P.vort) return -3;   // the baseline runs the semi-Lagrangian step chain only
         const T* rho0 = (const T*)rho0v;
         const T* keys = (const T*)keysv;
         T* u = (T*)uv;

@@ -380,7 +380,6 @@ stfas_status stfas_lbfgs(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
         HCK(hipPeekAtLastError());
         HCK(hipStreamSynchronize(ctx->s->st));
         if (done == -1) return STFAS_E_NOMEM;
-        if (done == -3) return STFAS_E_INVALID;
         if (iters_done) *iters_done = done < 0 ? 0 : done;
         return done == -2 ? STFAS_E_NONFINITE : STFAS_OK;
     });

@@ -18,7 +18,8 @@ def _tiny(seed=0):
     return w
 
 
-def test_gradient_matches_finite_differences():
+@pytest.mark.parametrize("velocity", ["sl", "vorticity"])
+def test_gradient_matches_finite_differences(velocity):
     w = _tiny()
     g = Grid(w["n"])
     N, dt, r = w["num_steps"], w["dt"], w["r"]
@@ -27,11 +28,11 @@ def test_gradient_matches_finite_differences():
     u = 0.05 * np.stack([synthetic.random_faces(w["n"], rng) for _ in range(N)])
 
     def J(x):
-        rho, _ = resimulate(g, w["rho0"], x, dt)
+        rho, _ = resimulate(g, w["rho0"], x, dt, velocity=velocity)
         return objectives(g, rho, w["keys"], x, r, levels)[0]
 
-    rho, v = resimulate(g, w["rho0"], u, dt)
-    gr = lbfgs.gradient(g, rho, v, u, w["keys"], r, dt, levels)
+    rho, v = resimulate(g, w["rho0"], u, dt, velocity=velocity)
+    gr = lbfgs.gradient(g, rho, v, u, w["keys"], r, dt, levels, velocity=velocity)
     for k in range(3):
         d = np.stack([synthetic.random_faces(w["n"], rng) for _ in range(N)])
         eps = 1e-6
