@@ -286,8 +286,9 @@ def test_rotational_autograd_step():
         assert rel(a.detach().cpu().numpy(), b) <= TOL["fp64"]
 
 
-@pytest.mark.parametrize("n,N,iters", [((8, 8), 4, 5), ((8, 8, 8), 3, 3)])
-def test_rotational_lbfgs_fp64(n, N, iters):
+@pytest.mark.parametrize("n,N,iters,prec", [((8, 8), 4, 5, "fp64"), ((8, 8, 8), 3, 3, "fp64"),
+                                             ((8, 8), 4, 3, "mixed")])
+def test_rotational_lbfgs(n, N, iters, prec):
     """The L-BFGS baseline with the rotational operator (its gradient the
     adjoint of the fixed-point steps) against the oracle's: the same objective
     history, iteration count and controls."""
@@ -296,19 +297,20 @@ def test_rotational_lbfgs_fp64(n, N, iters):
     w = synthetic.small_problem(n, N, seed=7, r=1e-2)
     g = Grid(n)
     dt, r = w["dt"], w["r"]
-    ctx = S.stfas_create(S.make_problem(n, N, r, dt=dt, precision="fp64", velocity="rotational"))
-    keys = w["keys"]
+    ctx = S.stfas_create(S.make_problem(n, N, r, dt=dt, precision=prec, velocity="rotational"))
+    rho0 = _q(w["rho0"], prec)
+    keys = {t: _q(v, prec) for t, v in w["keys"].items()}
     ks = sorted(keys)
-    u = to_dev(np.zeros((N, g.nface)), "fp64")
-    flag(f"rotational lbfgs n={n} N={N}")
-    hist, done = S.stfas_lbfgs(ctx, to_dev(w["rho0"], "fp64"), ks, to_dev(np.stack([keys[k] for k in ks]), "fp64"),
+    u = to_dev(np.zeros((N, g.nface)), prec)
+    flag(f"rotational lbfgs n={n} N={N} {prec}")
+    hist, done = S.stfas_lbfgs(ctx, to_dev(rho0, prec), ks, to_dev(np.stack([keys[k] for k in ks]), prec),
                                u, iters, 0.0)
     ctx.destroy()
-    u_ref, hist_ref, done_ref = lbfgs.solve(g, w["rho0"], keys, N, r, dt, metric.default_levels(n), iters,
+    u_ref, hist_ref, done_ref = lbfgs.solve(g, rho0, keys, N, r, dt, metric.default_levels(n), iters,
                                             velocity="vorticity")
     assert done == done_ref
-    assert np.allclose(hist, hist_ref, rtol=1e-9, atol=0)
-    assert rel(to_np(u).reshape(N, -1), u_ref) <= 1e-9
+    assert np.allclose(hist, hist_ref, rtol=1e-9 if prec == "fp64" else 1e-4, atol=0)
+    assert rel(to_np(u).reshape(N, -1), u_ref) <= (1e-9 if prec == "fp64" else TOL["mixed"])
 
 
 def test_rotational_step_backward_without_u_rejected():
