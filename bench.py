@@ -324,6 +324,9 @@ def rotational_run(S, w, density, kw):
     return res
 
 
+EQUAL_COUNTS = (20, 3)   # ADMM iterations, V-cycles per iteration
+
+
 def precision_3d_run(S, velocity="sl"):
     """The 3D precision form (outside the step clock): the 64^3, 60-step
     workload (sphere to ellipsoid unions at t = 30 and 60, SL density) solved
@@ -334,7 +337,9 @@ def precision_3d_run(S, velocity="sl"):
     100 iterations from run to run), cap 150; iterations, seconds, seconds
     per V-cycle, final visual difference, and the mixed
     form's keyframe error against the FP64 run after re-simulating both
-    controls with the FP64 step.  velocity="rotational" runs the same with
+    controls with the FP64 step; then both forms again with equal fixed
+    iteration counts (EQUAL_COUNTS), whose keyframe error is that of the
+    arithmetic alone, for the SL and for the upwind density operator.  velocity="rotational" runs the same with
     the paper's rotational operator (vorticity on edges; its smoother without
     the local block in 3D)."""
     import torch
@@ -353,6 +358,20 @@ def precision_3d_run(S, velocity="sl"):
     kf = keyframe_error(S, w, "sl", us["mixed"], us["fp64"], velocity=velocity)
     res["kf_err_mixed_vs_fp64"] = kf
     res["meets_1e-4_kf_err"] = bool(kf <= 1e-4 and all(conv))
+    # the same solves with equal iteration counts in both forms: the difference
+    # left is that of the arithmetic, not of the iteration where the stop fires
+    # (with the SL velocity operator also with the upwind density operator,
+    # smooth in v where the SL backtrace's cell choice is not)
+    fc = dict(opts, max_admm=EQUAL_COUNTS[0], max_vcycles=EQUAL_COUNTS[1], fixed_counts=True)
+    eq = {"admm_iters": EQUAL_COUNTS[0], "vcycles_per_admm": EQUAL_COUNTS[1]}
+    for density in ("sl", "upwind") if velocity == "sl" else ("sl",):
+        d = eq if density == "sl" else eq.setdefault("upwind_density", {})
+        for prec in ("mixed", "fp64"):
+            st, us[prec] = solve_once(S, w, prec, density, velocity=velocity, **fc)
+            d[prec + "_seconds"] = st["seconds"]
+            torch.cuda.empty_cache()
+        d["kf_err_mixed_vs_fp64"] = keyframe_error(S, w, density, us["mixed"], us["fp64"], velocity=velocity)
+    res["equal_counts"] = eq
     res["workload"] = ("3D 64^3 MAC grid, 60 steps, r=1e-3, SL density, K dt^2/r = 4, 4 density-subproblem "
                        "iterations, ADMM to the visual-difference stop max(rho0)/100"
                        + (", rotational velocity operator" if velocity != "sl" else ""))
