@@ -181,7 +181,8 @@ stfas_status stfas_solve(stfas_ctx* ctx, const void* rho0, int32_t num_key, cons
  * iters + 1 entries, J at the start and after each accepted iteration;
  * *iters_done (may be NULL): the iterations done.  The first call on a
  * context allocates the optimiser's buffers ((N+3)(cells+faces) + (N+1) cells + 23 N faces
- * elements), freed by stfas_destroy; a context made by stfas_create_in makes
+ * elements, and 6 faces more with the rotational operator, whose backward
+ * pass recomputes each step's fixed-point iterates), freed by stfas_destroy; a context made by stfas_create_in makes
  * no allocation, so there the call returns STFAS_E_INVALID.  Blocks. */
 stfas_status stfas_lbfgs(stfas_ctx* ctx, const void* rho0, int32_t num_key, const int32_t* key_steps,
                          const void* key_rho, void* u_inout, int32_t iters, double eps_stop, int32_t* iters_done,
