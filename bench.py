@@ -170,6 +170,11 @@ def main():
     if not args.no_rotational:
         out["rotational_velocity"] = rotational_run(S, w, args.density, kw)
         progress("rotational-operator solves done")
+        if args.lbfgs_iters > 0:
+            out["rotational_velocity"]["lbfgs"] = lbfgs_run(
+                S, w, args.density, min(args.lbfgs_iters, ROT_LBFGS_CAP), out["rotational_velocity"]["mixed"],
+                velocity="rotational")
+            progress("rotational-operator L-BFGS done")
     if not args.no_3d:
         out["precision_3d"] = precision_3d_run(S)
         progress("3D solves done")
@@ -252,15 +257,18 @@ def sl_run(S, w, kw, no_fp64):
     return res
 
 
-def lbfgs_run(S, w, density, iters, admm_stats):
+def lbfgs_run(S, w, density, iters, admm_stats, velocity="sl"):
     """The gradient-based baseline of the paper's comparison (Sec. 5, outside
     the step clock): L-BFGS from u = 0 on the same problem, precision and
     objective, stopped by the same visual-difference rule as the ADMM loop
     (or the iteration cap); its time, its objective and the first iteration
-    (if any) at which it reaches the ADMM solve's objective."""
+    (if any) at which it reaches the ADMM solve's objective.  velocity:
+    the velocity operator of both (the rotational one's gradient is the
+    adjoint of its fixed-point steps)."""
     import numpy as np
     import torch
-    prob = S.make_problem(w["n"], w["num_steps"], w["r"], dt=w["dt"], precision="mixed", density=density)
+    prob = S.make_problem(w["n"], w["num_steps"], w["r"], dt=w["dt"], precision="mixed", density=density,
+                          velocity=velocity)
     ctx = S.stfas_create(prob)
     ks = sorted(w["keys"])
     rho0 = torch.tensor(w["rho0"], dtype=torch.float32, device="cuda")
@@ -325,6 +333,7 @@ def rotational_run(S, w, density, kw):
 
 
 EQUAL_COUNTS = (20, 3)   # ADMM iterations, V-cycles per iteration
+ROT_LBFGS_CAP = 150       # L-BFGS iterations with the rotational operator
 
 
 def precision_3d_run(S, velocity="sl"):
