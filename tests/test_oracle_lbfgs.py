@@ -59,14 +59,19 @@ def test_minimize_rosenbrock():
     assert done < 200
 
 
-def test_solve_decreases_objective():
+@pytest.mark.parametrize("velocity", ["sl", "vorticity"])
+def test_solve_decreases_objective(velocity):
     w = _tiny(3)
     g = Grid(w["n"])
     levels = metric.default_levels(w["n"])
-    u, hist, done = lbfgs.solve(g, w["rho0"], w["keys"], w["num_steps"], w["r"], w["dt"], levels, 6)
+    u, hist, done = lbfgs.solve(g, w["rho0"], w["keys"], w["num_steps"], w["r"], w["dt"], levels, 6,
+                                velocity=velocity)
     assert done == 6
     assert all(hist[i + 1] <= hist[i] for i in range(len(hist) - 1))
     assert hist[-1] < hist[0]
+    # the history is the objective of the returned controls under the same simulation
+    rho, _ = resimulate(g, w["rho0"], u, w["dt"], velocity=velocity)
+    assert abs(objectives(g, rho, w["keys"], u, w["r"], levels)[0] - hist[-1]) <= 1e-12 * hist[-1]
 
 
 def test_visual_difference_stop_by_brute_force():
