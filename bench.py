@@ -348,9 +348,9 @@ def precision_3d_run(S, velocity="sl"):
     form's keyframe error against the FP64 run after re-simulating both
     controls with the FP64 step; then both forms again with equal fixed
     iteration counts (EQUAL_COUNTS), whose keyframe error is that of the
-    arithmetic alone, for the SL and for the upwind density operator.  velocity="rotational" runs the same with
-    the paper's rotational operator (vorticity on edges; its smoother without
-    the local block in 3D)."""
+    arithmetic alone, for the SL and for the upwind density operator.
+    velocity="rotational" runs the same with the paper's rotational operator
+    (vorticity on edges; its smoother without the local block in 3D)."""
     import torch
     import synthetic
     w = synthetic.c3_precision_3d(0)
