@@ -5,7 +5,7 @@ import pytest
 
 import synthetic
 from gpu_common import TOL, empty, flag, rel, to_dev, to_np, zeros
-from oracle import advect, kkt, metric, poisson, scgs, stfas, transfer
+from oracle import advect, kkt, metric, poisson, scgs, transfer
 from oracle.grid import Grid
 
 pytestmark = pytest.mark.gpu

@@ -1,6 +1,5 @@
 """Serving form: results are the same alone and inside the concurrent mix,
 and admission never holds more than the HBM budget."""
-import numpy as np
 import pytest
 
 import synthetic

@@ -6,7 +6,7 @@ import pytest
 
 import synthetic
 from gpu_common import TOL, empty, flag, rel, to_dev, to_np, zeros
-from oracle import admm, ao, kkt, step, stfas
+from oracle import admm, ao, step, stfas
 from oracle.grid import Grid
 
 pytestmark = pytest.mark.gpu

@@ -1,6 +1,5 @@
 """CPU checks of the C interface: the library loads, exports every function
 the headers declare, and validates problems without a device."""
-import ctypes
 import glob
 import os
 import re

@@ -5,7 +5,6 @@ the oracle's arithmetic visible, so that it is regenerated on purpose.
 Iteration and V-cycle counts exactly; values to 1e-10 relative (summation
 order may differ between BLAS builds)."""
 import json
-import os
 
 import numpy as np
 import pytest

@@ -8,7 +8,7 @@ from scipy import ndimage
 
 import synthetic
 from oracle import advect, ao, kkt, metric, poisson, scgs, stfas, step, transfer
-from oracle.grid import Grid, div, grad, laplacian
+from oracle.grid import Grid, div, grad
 
 GRIDS = [(8, 6), (6, 4, 5)]
 
