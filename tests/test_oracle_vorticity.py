@@ -270,3 +270,41 @@ def test_rotational_step_adjoint_matches_fd(n, rng):
         fd = (loss(rho + e * dr, v + e * dv, u + e * du) - loss(rho - e * dr, v - e * dv, u - e * du)) / (2 * e)
         ad = dr @ g_rho + dv @ g_v + du @ g_u
         assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1.0)
+
+
+def _rigid_rotation(g, c, omega):
+    """Solid-body rotation about axis c at rate omega, sampled on the faces:
+    v_p = -omega (x_q - x_q0), v_q = omega (x_p - x_p0) for the cyclic
+    triple (c, p, q); its curl is 2 omega along c and 0 along the others."""
+    p, q = [(a, b) for (cc, a, b) in [(2, 0, 1), (0, 1, 2), (1, 2, 0)] if cc == c][0]
+    centre = [0.37 * n for n in g.n]
+    parts = []
+    for a in range(g.dim):
+        pos = g.face_positions(a) + 0.5                 # cell-centre offset on the axes other than a
+        pos[:, a] -= 0.5                                # a-faces sit on the cell boundary along a
+        f = np.zeros(len(pos))
+        if a == p:
+            f = -omega * g.h * (pos[:, q] - centre[q])
+        elif a == q:
+            f = omega * g.h * (pos[:, p] - centre[p])
+        parts.append(f.reshape(g.face_shapes[a]))
+    return g.join(parts)
+
+
+@pytest.mark.parametrize("n,c", [((10, 8), 2), ((7, 6, 5), 0), ((7, 6, 5), 1), ((7, 6, 5), 2)])
+def test_edge_vorticity_of_rigid_rotation_and_gradients(n, c, rng):
+    """The edge vorticity against closed forms: a solid-body rotation at rate
+    omega has curl 2 omega along its axis and none across it (every interior
+    edge, exactly for a linear field), and a discrete gradient has none."""
+    g = Grid(n)
+    omega = 1.7
+    v = _rigid_rotation(g, c, omega)
+    for cc in ((2,) if g.dim == 2 else (0, 1, 2)):
+        w = vorticity.edge_vorticity(g, v, cc)
+        inner = w[:, 1:-1, 1:-1]
+        want = 2 * omega if cc == c else 0.0
+        assert np.max(np.abs(inner - want)) <= 1e-12 * 2 * omega, cc
+        assert np.all(w[:, 0, :] == 0) and np.all(w[:, -1, :] == 0)
+        assert np.all(w[:, :, 0] == 0) and np.all(w[:, :, -1] == 0)
+        gphi = grad(g, rng.standard_normal(g.ncell))
+        assert np.max(np.abs(vorticity.edge_vorticity(g, gphi, cc))) <= 1e-12 * np.max(np.abs(gphi)) / g.h
