@@ -98,3 +98,26 @@ def test_visual_difference_stop_by_brute_force():
     # eps = 0 never stops early, a huge eps stops after the first iterate
     assert lbfgs.solve(g, w["rho0"], w["keys"], N, r, dt, levels, 3, eps_stop=0.0)[2] == 3
     assert lbfgs.solve(g, w["rho0"], w["keys"], N, r, dt, levels, 3, eps_stop=1e30)[2] == 1
+
+
+@pytest.mark.parametrize("velocity", ["sl", "vorticity"])
+def test_gradient_matches_finite_differences_3d(velocity):
+    """The same pin on a 3D grid (vorticity on edges for the rotational form)."""
+    w = synthetic.small_problem((5, 4, 4), 2, seed=12, r=1e-2)
+    g = Grid(w["n"])
+    N, dt, r = w["num_steps"], w["dt"], w["r"]
+    levels = metric.default_levels(w["n"])
+    rng = np.random.default_rng(13)
+    u = 0.05 * np.stack([synthetic.random_faces(w["n"], rng) for _ in range(N)])
+
+    def J(x):
+        rho, _ = resimulate(g, w["rho0"], x, dt, velocity=velocity)
+        return objectives(g, rho, w["keys"], x, r, levels)[0]
+
+    rho, v = resimulate(g, w["rho0"], u, dt, velocity=velocity)
+    gr = lbfgs.gradient(g, rho, v, u, w["keys"], r, dt, levels, velocity=velocity)
+    for k in range(2):
+        d = np.stack([synthetic.random_faces(w["n"], rng) for _ in range(N)])
+        eps = 1e-6
+        fd = (J(u + eps * d) - J(u - eps * d)) / (2 * eps)
+        assert abs(fd - np.sum(gr * d)) <= 1e-6 * max(abs(fd), 1e-12), k
